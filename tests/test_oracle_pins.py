@@ -1,0 +1,498 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test ties an oracle function to something other than itself: a value printed in the
+paper (tests/golden), a closed form, an invariant, a special case, or a brute force on tiny
+inputs written here in pure Python.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_11133_amd import meshes as M
+from tests import golden_io as G
+
+pytestmark = pytest.mark.cpu
+
+
+def refine_levels(X, T, L, db=None, nb=None):
+    for _ in range(L):
+        X, T, db, nb = O.refine(X, T, db, nb)
+    return X, T, db, nb
+
+
+def dets(X, T):
+    a, b, c, d = (X[:, T[i]] for i in range(4))
+    return np.einsum("ij,ij->j", b - a, np.cross(c - a, d - a, axis=0))
+
+
+# ------------------------------------------------------------------ refinement (a4)
+def test_refine_worked_example():
+    """Section 3.4 example: T=[1 3 2 4] on the unit simplex -> printed 12x4 T and 11x3 C."""
+    Tg, Cg = G.refine_example()
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float).T.copy()
+    T = np.array([[0, 2, 1, 3]], np.int32).T.copy()
+    Xo, To, _, _ = O.refine(X, T)
+    assert np.array_equal(To.T + 1, Tg)
+    assert np.array_equal(Xo.T, Cg)
+
+
+def test_refine_counts_and_volume():
+    """nE' = 12 nE, nC' = nC + nEd + nE; sum of dets is conserved exactly (dyadic coords);
+    children keep the parent's orientation sign with det ratios 1/8 (corners), 1/16 (octahedron)."""
+    for X, T in (M.kuhn_cube(), M.fichera()):
+        for _ in range(2):
+            e = O.edges(X.shape[1], T)
+            Xo, To, _, _ = O.refine(X, T)
+            nE = T.shape[1]
+            assert To.shape[1] == 12 * nE and Xo.shape[1] == X.shape[1] + e["nEd"] + nE
+            dp, dc = dets(X, T), dets(Xo, To)
+            assert dp.sum() == dc.sum()  # exact
+            ratio = np.concatenate([dc[:nE][None], dc[nE:].reshape(nE, 11).T]) / dp
+            assert np.all(ratio[:4] == 0.125) and np.all(ratio[4:] == 0.0625)
+            X, T = Xo, To
+
+
+def test_refine_faces_rule():
+    """refineFaces: each face -> 4 with the parent's orientation; children 2-4 at n + 3(f-1) + (c-1)."""
+    X, T, db, nb = M.paper_cube()
+    Xo, To, dbo, nbo = O.refine(X, T, db, nb)
+    e = O.edges(X.shape[1], T)
+    mid = {}
+    for k in range(e["nEd"]):
+        a, b = e["edges"][:, k]
+        m = np.where(np.all(Xo.T == (X[:, a] + X[:, b]) / 2, axis=1))[0]
+        mid[(a, b)] = mid[(b, a)] = int(m[0])
+    for F, Fo in ((db, dbo), (nb, nbo)):
+        n = F.shape[1]
+        for f in range(n):
+            n1, n2, n3 = F[:, f]
+            rows = [f, n + 3 * f, n + 3 * f + 1, n + 3 * f + 2]
+            exp = [[n1, mid[n1, n2], mid[n1, n3]], [n2, mid[n2, n3], mid[n1, n2]],
+                   [n3, mid[n1, n3], mid[n2, n3]], [mid[n1, n2], mid[n2, n3], mid[n1, n3]]]
+            for r, ex in zip(rows, exp):
+                assert list(Fo[:, r]) == ex
+
+
+# ------------------------------------------------------------------ edges (a1)
+def brute_edges(T):
+    """Stable unique of sorted local edge rows in (tet, IJ IK IL JK JL KL) order."""
+    order = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    ids, U, t2e = {}, [], np.zeros((6, T.shape[1]), int)
+    for t in range(T.shape[1]):
+        for j, (a, b) in enumerate(order):
+            k = tuple(sorted((int(T[a, t]), int(T[b, t]))))
+            if k not in ids:
+                ids[k] = len(U)
+                U.append(k)
+            t2e[j, t] = ids[k]
+    return np.array(U).T, t2e
+
+
+def test_nodes2edge_example():
+    """Section 3.1 example matrix Nodes2Edge, reproduced from the fixture tets."""
+    tets, N = G.nodes2edge_example()
+    e = O.edges(8, (tets - 1).T.astype(np.int32))
+    got = np.zeros((8, 8), int)
+    for k in range(e["nEd"]):
+        a, b = e["edges"][:, k]
+        got[a, b] = got[b, a] = k + 1
+    assert np.array_equal(got, N)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_edges_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, 1)
+    T = T[:, rng.permutation(T.shape[1])]
+    relabel = rng.permutation(X.shape[1])
+    T = relabel[T].astype(np.int32)
+    e = O.edges(X.shape[1], T)
+    U, t2e = brute_edges(T)
+    assert np.array_equal(e["edges"], U) and np.array_equal(e["tet2edge"], t2e)
+    first = np.array([np.where((t2e == k).any(axis=0))[0][0] for k in range(U.shape[1])])
+    assert np.array_equal(e["edge_first_tet"], first)
+    pre = np.array([np.sum(first < t) for t in range(T.shape[1])])
+    assert np.array_equal(e["tet_edge_prefix"], pre)
+
+
+# ------------------------------------------------------------------ faces (a2, a3)
+def test_faces_listing1_example():
+    """Section 3.3 example: 16 Faces rows; tet 5 -> rows [16 7 12 4], all repeated (sigma=-1)."""
+    Fg, tet5 = G.faces_listing1()
+    X, T, db, nb = M.paper_cube()
+    f = O.faces(8, T)
+    assert f["nF"] == 16
+    assert np.array_equal(f["faces"].T + 1, Fg)
+    assert np.array_equal(f["tet2face"][:, 4] + 1, tet5)
+    assert np.all(f["sigma"][:, 4] == -1) and np.all(f["sigma"][:, :4] == 1)
+    # Listing 1's boundary rows occur verbatim as rows of Faces
+    rows = {tuple(r) for r in f["faces"].T}
+    for F in (db, nb):
+        for r in F.T:
+            assert tuple(r) in rows
+
+
+def brute_faces(T):
+    """Owner = lowest tet holding the face; numbering by (owner, local face)."""
+    local = [(0, 1, 2), (0, 2, 3), (0, 3, 1), (3, 2, 1)]
+    occ = {}
+    for t in range(T.shape[1]):
+        for k, f in enumerate(local):
+            occ.setdefault(frozenset(int(T[i, t]) for i in f), []).append((t, k))
+    ids, faces = {}, []
+    t2f = np.zeros((4, T.shape[1]), int)
+    sig = np.zeros((4, T.shape[1]), int)
+    for t in range(T.shape[1]):
+        for k, f in enumerate(local):
+            key = frozenset(int(T[i, t]) for i in f)
+            o = occ[key]
+            if o[0] == (t, k):
+                ids[key] = len(faces)
+                faces.append([int(T[i, t]) for i in f])
+                sig[k, t] = 1
+            else:
+                sig[k, t] = -1
+            t2f[k, t] = ids[key]
+    return np.array(faces).T, t2f, sig
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_faces_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    X, T = M.fichera()
+    X, T, _, _ = refine_levels(X, T, 1)
+    T = T[:, rng.permutation(T.shape[1])]
+    f = O.faces(X.shape[1], T)
+    Fb, t2f, sig = brute_faces(T)
+    assert np.array_equal(f["faces"], Fb)
+    assert np.array_equal(f["tet2face"], t2f)
+    assert np.array_equal(f["sigma"], sig)
+    # neighbour = the other tet of the face, -1 on the boundary
+    for t in range(T.shape[1]):
+        for k in range(4):
+            F = t2f[k, t]
+            others = [tt for tt in range(T.shape[1]) for kk in range(4) if t2f[kk, tt] == F and tt != t]
+            assert f["nbr"][k, t] == (others[0] if others else -1)
+
+
+def test_edges2tetra_remark1():
+    """Remark 1: for the oriented face [a b c] of tet m with edges e1=(a,b), e2=(b,c), e3=(c,a),
+    E2T(e2,e1) = E2T(e3,e2) = E2T(e1,e3) = m, and E2T is not symmetric."""
+    X, T, _, _ = M.paper_cube()
+    r, c, t = O.edges2tetra(8, T)
+    e = O.edges(8, T)
+    eid = {tuple(sorted(e["edges"][:, k])): k for k in range(e["nEd"])}
+    E = {(int(a), int(b)): int(m) for a, b, m in zip(r, c, t)}
+    for m in range(T.shape[1]):
+        a, b, cc, d = T[:, m]
+        for f in [(a, b, cc), (a, cc, d), (a, d, b), (d, cc, b)]:
+            e1 = eid[tuple(sorted((f[0], f[1])))]
+            e2 = eid[tuple(sorted((f[1], f[2])))]
+            e3 = eid[tuple(sorted((f[2], f[0])))]
+            assert E[e2, e1] == E[e3, e2] == E[e1, e3] == m
+            assert E.get((e1, e2), -1) != m
+    assert len(E) == 3 * 4 * T.shape[1]
+
+
+@pytest.mark.parametrize("make,levels", [(M.kuhn_cube, 3), (M.fichera, 2)])
+def test_euler_and_face_invariants(make, levels):
+    """V - E + F - T = 1 (contractible domain); interior faces have 2 tets with opposite
+    sigma, boundary faces 1 with sigma = +1; nEd' = 2nEd + 3nF + 6nE, nF' = 4nF + 16nE,
+    nB' = 4nB."""
+    X, T = make()
+    prev = None
+    for lev in range(levels + 1):
+        c = O.connect(X.shape[1], T)
+        nE = T.shape[1]
+        assert X.shape[1] - c["nEd"] + c["nF"] - nE == 1
+        f2t = c["face2tet"]
+        interior = f2t[1] >= 0
+        assert c["nB"] == int((~interior).sum())
+        so = c["sigma"][f2t[0] % 4, f2t[0] // 4]
+        assert np.all(so == 1)
+        sn = c["sigma"][f2t[1][interior] % 4, f2t[1][interior] // 4]
+        assert np.all(sn == -1)
+        assert np.all(f2t[0][interior] // 4 < f2t[1][interior] // 4)
+        if prev is not None:
+            pE, pEd, pF, pB = prev
+            assert c["nEd"] == 2 * pEd + 3 * pF + 6 * pE
+            assert c["nF"] == 4 * pF + 16 * pE and c["nB"] == 4 * pB
+        prev = (nE, c["nEd"], c["nF"], c["nB"])
+        if lev < levels:
+            X, T, _, _ = O.refine(X, T)
+
+
+def test_table1_table2_counts():
+    """Tables 1-2: nE, nC, nEd, nF, N = 4nE, L = nF - |Nb| for levels 1-3 of Listing 1's mesh
+    computed directly, levels 4-5 through the count recurrences verified above."""
+    tab = G.counts_tables()
+    X, T, db, nb = M.paper_cube()
+    for lev in range(1, 4):
+        X, T, db, nb = O.refine(X, T, db, nb)
+        c = O.connect(X.shape[1], T)
+        row = tab[lev - 1]
+        got = [lev, T.shape[1], X.shape[1], c["nEd"], c["nF"], 4 * T.shape[1], c["nF"] - nb.shape[1]]
+        assert got == list(row)
+    nE, nC, nEd, nF, nN = T.shape[1], X.shape[1], c["nEd"], c["nF"], nb.shape[1]
+    for lev in (4, 5):
+        nE, nC, nEd, nF, nN = 12 * nE, nC + nEd + nE, 2 * nEd + 3 * nF + 6 * nE, 4 * nF + 16 * nE, 4 * nN
+        assert [lev, nE, nC, nEd, nF, 4 * nE, nF - nN] == list(tab[lev - 1])
+
+
+# ------------------------------------------------------------------ local matrices (a5)
+def test_local_unit_simplex_textbook():
+    """Unit simplex, kappa = c = 1: K = (1/6)[[3,-1,-1,-1],[-1,1,0,0],[-1,0,1,0],[-1,0,0,1]],
+    M = (1/120)(1 + delta_ij), C row k = sigma |F_k| r_k with |F| = 1/2 (3 faces), sqrt(3)/2."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float).T.copy()
+    T = np.array([[0, 1, 2, 3]], np.int32).T.copy()
+    sig = np.ones((4, 1), np.int8)
+    p = O.params(c=1.0, kappa=1.0, f=(O.FUN_CONST, (1.0,)))
+    L = O.local(X, T, sig, None, p)
+    Kt = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]]) / 6
+    assert np.allclose(L["K"][:, 0].reshape(4, 4), Kt, rtol=0, atol=1e-15)
+    assert L["vol"][0] == pytest.approx(1 / 6, rel=1e-15)
+    # faces [a b c], [a c d], [a d b] lie in coordinate planes; [d c b] is the slanted one
+    assert np.allclose(L["d"][:, 0], [0.5, 0.5, 0.5, np.sqrt(3) / 2], rtol=1e-15)
+    # f = 1: B_i = vol/4 (the rule is exact for constants)
+    assert np.allclose(L["B"][:, 0], 1 / 24, rtol=1e-15)
+
+
+def test_local_invariants():
+    """Stiffness rows sum to zero; K symmetric PSD; sum_k |F_k| n_k = 0 (closed surface)."""
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, 1)
+    X = M.jitter_unit_cube(X, T, 0.1, seed=5)
+    c = O.connect(X.shape[1], T)
+    kap = M.lognormal_kappa(T.shape[1], 1.0, seed=7)
+    p = O.params(c=1.0, f=(O.FUN_CONST, (1.0,)))
+    L = O.local(X, T, c["sigma"], kap, p)
+    K = L["K"].T.reshape(-1, 4, 4)
+    scale = np.abs(K).max(axis=(1, 2))
+    assert np.abs(K.sum(axis=2)).max(axis=1).max() <= 1e-13 * scale.max()
+    assert np.allclose(K, K.transpose(0, 2, 1), rtol=0, atol=1e-15 * scale.max())
+    assert np.linalg.eigvalsh(K).min() > -1e-12 * scale.max()
+    local = [(0, 1, 2), (0, 2, 3), (0, 3, 1), (3, 2, 1)]
+    for t in range(0, T.shape[1], 7):
+        s = np.zeros(3)
+        for k, f in enumerate(local):
+            x = X[:, T[list(f), t]]
+            n = np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0])
+            # |d_k| = |F_k|; the tuple orientation is consistent, so the area vectors close
+            assert abs(np.linalg.norm(n) / 2 - abs(L["d"][k, t])) <= 1e-15
+            s += n / 2
+        assert np.abs(s).max() <= 1e-15
+
+
+def test_element_schur_split_identity():
+    """A(T) 1 = (c|T|/4) 1 exactly, so S(T) = d d'/(c|T|) + C W C' with W the inverse of A on
+    the complement of constants; and S(T) is SPD."""
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, 1)
+    X = M.jitter_unit_cube(X, T, 0.1, seed=3)
+    c = O.connect(X.shape[1], T)
+    kap = M.lognormal_kappa(T.shape[1], 1.0, seed=9)
+    cc = 0.7
+    p = O.params(c=cc, f=(O.FUN_CONST, (1.0,)))
+    L = O.local(X, T, c["sigma"], kap, p)
+    local = [(0, 1, 2), (0, 2, 3), (0, 3, 1), (3, 2, 1)]
+    R = np.zeros((4, 4))
+    for k, f in enumerate(local):
+        R[k, list(f)] = 1 / 3
+    Pp = np.eye(4) - np.ones((4, 4)) / 4
+    for t in range(T.shape[1]):
+        vol = L["vol"][t]
+        A = L["K"][:, t].reshape(4, 4) + cc * vol / 20 * (np.eye(4) + 1)
+        W = np.linalg.pinv(Pp @ A @ Pp, rcond=1e-12)
+        d = L["d"][:, t]
+        Cm = d[:, None] * R
+        S = np.outer(d, d) / (cc * vol) + Cm @ W @ Cm.T
+        So = L["S"][:, t].reshape(4, 4)
+        assert np.abs(S - So).max() <= 1e-9 * np.abs(So).max()
+        assert np.linalg.eigvalsh(So).min() > 0
+
+
+def test_assembly_structure():
+    """nnz = 7 nI + 4 nB; symmetric (to rounding); each off-diagonal equals the single S(T) entry of the
+    one tet holding both faces (bit for bit)."""
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, 2)
+    c = O.connect(X.shape[1], T)
+    p = O.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    A, rhs = O.condense(X, T, c, None, p)
+    nB = c["nB"]
+    nI = c["nF"] - nB
+    assert A.nnz == 7 * nI + 4 * nB
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max()  # symmetric up to rounding
+    L = O.local(X, T, c["sigma"], None, p)
+    t2f = c["tet2face"]
+    for t in range(0, T.shape[1], 5):
+        for k in range(4):
+            for l in range(4):
+                if k != l:
+                    assert A[t2f[k, t], t2f[l, t]] == L["S"][4 * k + l, t]
+
+
+def test_dense_bruteforce_matches_schur():
+    """The full (N+L) block system of eq. (VectorForm), dense LU, equals condense + PCG +
+    recovery on Kuhn levels 0-1 (random kappa, jittered coordinates)."""
+    X, T = M.kuhn_cube()
+    for lev in range(2):
+        Xj = M.jitter_unit_cube(X, T, 0.1, seed=lev) if lev else X
+        kap = M.lognormal_kappa(T.shape[1], 1.0, seed=lev)
+        p = O.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)), ud=(O.FUN_LINEAR, (0.1, 0.2, -0.3, 0.5)))
+        conn, A, rhs, lam, U, it = O.solve(Xj, T, kap, p, tol=1e-14)
+        Ud, ld = O.dense_solve(Xj, T, conn, kap, p)
+        assert np.abs(U - Ud).max() <= 1e-11 * np.abs(Ud).max()
+        assert np.abs(lam - ld).max() <= 1e-11 * np.abs(ld).max()
+        X, T, _, _ = O.refine(X, T)
+
+
+def face_normals_owner(X, T, c):
+    """Unit normal of every face, outward from its owner."""
+    nF = c["nF"]
+    F = c["faces"]
+    n = np.cross(X[:, F[1]] - X[:, F[0]], X[:, F[2]] - X[:, F[0]], axis=0)
+    n /= np.linalg.norm(n, axis=0)
+    ot = c["face2tet"][0] // 4
+    opp = X[:, T[:, ot]].mean(axis=1)  # centroid of the owner
+    s = np.sign(np.einsum("ij,ij->j", n, X[:, F[0]] - opp))
+    return n * s
+
+
+@pytest.mark.parametrize("lev", [0, 1, 2])
+def test_linear_solution_exact(lev):
+    """u = a + b.x with the P1-interpolated load and u_D = u: U = nodal values and
+    lambda_F = kappa grad u . nu_F (owner's outward normal), to 1e-12."""
+    a = (0.3, 1.1, -0.7, 0.4)
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, lev)
+    kap = 2.5
+    p = O.params(c=1.3, kappa=kap, f=(O.FUN_LINEAR, tuple(1.3 * v for v in a)), ud=(O.FUN_LINEAR, a),
+                 quad=O.QUAD_P1_INTERP)
+    conn, A, rhs, lam, U, it = O.solve(X, T, None, p, tol=1e-15)
+    nod = a[0] + a[1] * X[0] + a[2] * X[1] + a[3] * X[2]
+    assert np.abs(U - nod[T]).max() <= 1e-12
+    nu = face_normals_owner(X, T, conn)
+    lam_ex = kap * (a[1] * nu[0] + a[2] * nu[1] + a[3] * nu[2])
+    assert np.abs(lam - lam_ex).max() <= 1e-12 * max(1.0, np.abs(lam_ex).max())
+
+
+def test_local_conservation():
+    """(c|T|/4) sum_i U_T,i = 1'B_T + sum_k sigma_k |F_k| lambda_k (test function v = 1 on T)."""
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, 2)
+    kap = M.lognormal_kappa(T.shape[1])
+    p = O.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    conn, A, rhs, lam, U, it = O.solve(X, T, kap, p)
+    L = O.local(X, T, conn["sigma"], kap, p)
+    lhs = L["vol"] / 4 * U.sum(axis=0)
+    r = L["B"].sum(axis=0) + (L["d"] * lam[conn["tet2face"]]).sum(axis=0)
+    assert np.abs(lhs - r).max() <= 1e-10 * np.abs(r).max()
+
+
+@pytest.mark.slow
+def test_oh_convergence():
+    """Manufactured u = sin(pi x) sin(pi y) sin(pi z): broken H1-seminorm error decays as O(h)
+    (rates >= 0.9, cf. Table 4's rates 0.97-1.0)."""
+    X, T = M.kuhn_cube()
+    errs = []
+    for lev in range(1, 4):
+        X, T, _, _ = O.refine(X, T)
+        p = O.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+        conn, A, rhs, lam, U, it = O.solve(X, T, None, p, tol=1e-10)
+        e = O.errors(X, T, conn, None, p, U, lam, O.FUN_SIN3, (1.0,), 2.0 ** -lev)
+        errs.append(np.sqrt(e["grad2"]))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates >= 0.9), rates
+
+
+def test_quadrature_monomials():
+    """Collapsed Gauss rule on the unit tet integrates x^a y^b z^c = a!b!c!/(a+b+c+3)! for
+    degree <= 2n-3."""
+    from math import factorial
+    n = 5
+    pts, w = O.tet_rule(n)
+    for a, b, cc in itertools.product(range(5), repeat=3):
+        if a + b + cc > 2 * n - 3:
+            continue
+        exact = factorial(a) * factorial(b) * factorial(cc) / factorial(a + b + cc + 3)
+        got = np.sum(w * pts[0] ** a * pts[1] ** b * pts[2] ** cc)
+        assert got == pytest.approx(exact, rel=1e-13)
+
+
+# ------------------------------------------------------------------ adjoint (a10)
+def _fd_setup(lev, f, ud):
+    X, T = M.kuhn_cube()
+    X, T, _, _ = refine_levels(X, T, lev)
+    X = M.jitter_unit_cube(X, T, 0.1, seed=11) if lev else X
+    kap = M.lognormal_kappa(T.shape[1], 1.0, seed=13)
+    p = O.params(c=1.0, f=f, ud=ud)
+    conn = O.connect(X.shape[1], T)
+    rng = np.random.default_rng(17)
+    Ut = rng.standard_normal((4, T.shape[1]))
+    return X, T, kap, p, conn, Ut
+
+
+def _J(X, T, kap, p, conn, Ut):
+    """J by the dense block solve (no iteration noise in the finite differences)."""
+    U, lam = O.dense_solve(X, T, conn, kap, p)
+    return 0.5 * np.sum((U - Ut) ** 2), U, lam
+
+
+@pytest.mark.parametrize("lev", [0, 1])
+def test_adjoint_central_fd(lev):
+    """dJ/dlog(kappa_T) and dJ/dX against central finite differences of J = 1/2|U - U_t|^2."""
+    X, T, kap, p, conn, Ut = _fd_setup(lev, (O.FUN_SIN3, (M.SIN3_AMPLITUDE,)), (O.FUN_LINEAR, (0.2, 0.5, -0.4, 0.3)))
+    J0, U, lam = _J(X, T, kap, p, conn, Ut)
+    g = O.adjoint(X, T, conn, kap, p, U, lam, U - Ut, tol=1e-15)
+    eps = 1e-5
+    for t in range(0, T.shape[1], max(1, T.shape[1] // 6)):
+        kp, km = kap.copy(), kap.copy()
+        kp[t] *= np.exp(eps)
+        km[t] *= np.exp(-eps)
+        fd = (_J(X, T, kp, p, conn, Ut)[0] - _J(X, T, km, p, conn, Ut)[0]) / (2 * eps)
+        assert fd == pytest.approx(g["dlogk"][t], rel=1e-6, abs=1e-9 * np.abs(g["dlogk"]).max())
+    h = 1e-6
+    gmax = np.abs(g["dX"]).max()
+    for v in range(0, X.shape[1], max(1, X.shape[1] // 8)):
+        for d in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[d, v] += h
+            Xm[d, v] -= h
+            fd = (_J(Xp, T, kap, p, conn, Ut)[0] - _J(Xm, T, kap, p, conn, Ut)[0]) / (2 * h)
+            assert abs(fd - g["dX"][d, v]) <= 1e-6 * gmax
+
+
+def test_adjoint_translation_invariance():
+    """With f constant and u_D = 0 the problem is translation invariant, so sum_v dJ/dX_v = 0."""
+    X, T, kap, p, conn, Ut = _fd_setup(1, (O.FUN_CONST, (1.0,)), (O.FUN_ZERO, ()))
+    J0, U, lam = _J(X, T, kap, p, conn, Ut)
+    g = O.adjoint(X, T, conn, kap, p, U, lam, U - Ut, tol=1e-15)
+    assert np.abs(g["dX"].sum(axis=1)).max() <= 1e-10 * np.abs(g["dX"]).max()
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_paths():
+    X, T = M.kuhn_cube()
+    bad = T.copy()
+    bad[0, 0] = 99
+    with pytest.raises(O.OracleError) as e:
+        O.edges(8, bad)
+    assert e.value.code == O.EINVAL
+    flip = T.copy()
+    flip[[2, 3], 1] = flip[[3, 2], 1]  # reverse the orientation of one tet
+    with pytest.raises(O.OracleError) as e:
+        O.faces(8, flip)
+    assert e.value.code == O.EORIENT
+    c = O.connect(8, T)
+    with pytest.raises(O.OracleError) as e:
+        O.condense(X, T, c, None, O.params(c=0.0))
+    assert e.value.code == O.ESINGULAR
+    flat = X.copy()
+    flat[2, :] = 0.0
+    with pytest.raises(O.OracleError) as e:
+        O.condense(flat, T, c, None, O.params(c=1.0))
+    assert e.value.code == O.EDEGEN
