@@ -1,0 +1,240 @@
+/*
+ * phfem.h -- C-ABI of the MI355X (gfx950) hot path of the vectorized primal hybrid FEM of
+ * "Vectorized 3D mesh refinement and implementation of primal hybrid FEM in MATLAB"
+ * (Nagula Mallesham, Gaddam, Valdman, Acharya; arXiv 2509.11133).
+ *
+ * The path: 12-subtet red refinement (Section 3.4), Nodes-to-Edge / Edges-to-Tetrahedron /
+ * Face-to-Tetrahedron connectivity (Sections 3.1-3.3), lowest-order primal hybrid local
+ * matrices (Section 4.2), element-wise Schur complement (Section 4.6, Algorithm 1) into a
+ * sparse SPD face system, Jacobi-PCG solve and recovery, and the adjoint gradient.
+ *
+ * Conventions for every call
+ *  - Return value: PHFEM_OK (0) or one of the phfem_status codes; phfem_last_error() gives
+ *    a text for the calling thread.  Arguments are validated before any work is enqueued;
+ *    on a validation failure nothing is written.  Errors found on the device (bad node
+ *    index, inconsistent orientation, zero volume) are reported by the calls that read back
+ *    a count (connect, refine with boundary faces, solve, grad); outputs are then undefined.
+ *  - Array arguments are DEVICE pointers to caller-owned memory; scalars and the *_stats /
+ *    counts / params structs are HOST memory.  Nothing is allocated inside a call: scratch
+ *    comes from the caller through (work, work_bytes), sized by the matching
+ *    phfem_*_workspace() query (256-byte aligned pointer expected).
+ *  - Indices are 0-based int32.  Arrays are SoA ("[r][n]" = r rows of n contiguous
+ *    entries, row stride n): coord[3][nC] float64, tetra[4][nE] int32.  This is the paper's
+ *    column-major MATLAB layout (k-th column of an n x r matrix = k-th row here).
+ *  - Local numbering of tet T = [a b c d]: edges IJ IK IL JK JL KL (j = 0..5, Listing 2);
+ *    faces [a b c], [a c d], [a d b], [d c b] (k = 0..3, Section 2.2).
+ *  - A "slot" is 4*t + k (local face k of tet t).
+ *  - Every call enqueues its kernels on `stream` (a hipStream_t) and returns without
+ *    waiting, except where a count must be read back (documented per call).
+ *  - Every kernel writes each output element exactly once or sums exactly two terms in
+ *    floating point, so results are bitwise reproducible run to run, except the
+ *    coordinate gradient of phfem_grad (atomic sums over the tets at a vertex).
+ */
+#ifndef PHFEM_H
+#define PHFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* phfem_stream_t; /* == hipStream_t */
+
+typedef enum {
+  PHFEM_OK = 0,
+  PHFEM_EINVAL = 1,     /* bad argument, node index out of range, repeated node, face not in mesh */
+  PHFEM_EORIENT = 2,    /* an oriented face occurs twice: tets not consistently oriented / non-manifold */
+  PHFEM_EDEGEN = 3,     /* zero-volume tet */
+  PHFEM_ESINGULAR = 4,  /* c <= 0: element matrices kappa K + c M singular */
+  PHFEM_ENOCONV = 5,    /* solver stopped at max_iter above tolerance (stats still filled) */
+  PHFEM_EWORKSPACE = 6, /* work_bytes smaller than the workspace query */
+  PHFEM_EHIP = 7        /* HIP runtime error */
+} phfem_status;
+
+/* Thread-local text of the last error ("" after success). */
+const char* phfem_last_error(void);
+int phfem_abi_version(void);
+
+/* ---------------------------------------------------------------- data functions ---- */
+/* f (load) and u_D (Dirichlet data) are evaluated in the kernels from a kind + 4 params. */
+enum {
+  PHFEM_FUN_ZERO = 0,
+  PHFEM_FUN_CONST = 1,         /* p0 */
+  PHFEM_FUN_SIN3 = 2,          /* p0 sin(pi x) sin(pi y) sin(pi z) */
+  PHFEM_FUN_LINEAR = 3,        /* p0 + p1 x + p2 y + p3 z */
+  PHFEM_FUN_X2Y2Z2 = 4,        /* p0 x^2 y^2 z^2 (exact solution of the paper's example) */
+  PHFEM_FUN_X2Y2Z2_LOAD = 5    /* -p0 Lap(x^2y^2z^2) + p1 x^2y^2z^2 (its load) */
+};
+enum { PHFEM_QUAD_FACE_CENTROID = 0, PHFEM_QUAD_P1_INTERP = 1 };
+enum { PHFEM_FP64 = 0, PHFEM_MIXED = 1 };
+
+/* Problem -div(kappa grad u) + c u = f, u = u_D on the boundary (model problem of
+ * Section 4 with a per-tet kappa; the paper has kappa = c = 1).  All boundary faces are Dirichlet faces.
+ *  quad: PHFEM_QUAD_FACE_CENTROID = the paper's load rule (f at the 4 face centroids,
+ *        weight |T|/4, StiffMassPH); PHFEM_QUAD_P1_INTERP = b(T) = M(T) f(x_i).
+ *  precision: PHFEM_FP64, or PHFEM_MIXED = FP32 local-matrix and element-Schur arithmetic
+ *        (Jacobian determinant and volume in FP64) summed into the FP64 face system. */
+typedef struct {
+  double c;
+  double kappa_const; /* kappa when the kappa array is NULL */
+  int32_t f_kind;
+  double f_par[4];
+  int32_t ud_kind;
+  double ud_par[4];
+  int32_t quad;
+  int32_t precision;
+} phfem_params;
+
+/* ---------------------------------------------------------------- connect (a1-a3) ---- */
+enum {
+  PHFEM_CONNECT_EDGES = 1,      /* Nodes-to-Edge numbering (NumEdges, Listing 2) */
+  PHFEM_CONNECT_FACES = 2,      /* Edges-to-Tet neighbours + Faces (Listings 3-4, fullFaces) */
+  PHFEM_CONNECT_NODES2EDGE = 4  /* also export Nodes2Edge (upper triangle) as CSR */
+};
+
+size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags);
+
+/* Connectivity of a conforming, consistently oriented tet mesh (all tets with the same
+ * sign of det[b-a, c-a, d-a]).
+ * Edges (Section 3.1, Listing 2): the 6 local edges of every tet, in (tet, local edge)
+ * order, keyed by their sorted node pair; edge e = rank of the first appearance (MATLAB
+ * unique(...,'stable')).
+ *   edges[2][nEd]        sorted node pair of edge e (paper's U); capacity 12 nE ints
+ *   tet2edge[6][nE]      edge of local edge j of tet t
+ *   edge_first_tet[nEd]  first tet holding edge e; capacity 6 nE
+ *   tet_edge_prefix[nE]  number of edges first seen in tets < t
+ *   n2e_rowptr[nC+1], n2e_col[nEd], n2e_edge[nEd] (flag NODES2EDGE): Nodes2Edge(i,j) for
+ *                        i < j as CSR over i with ascending j; capacities nC+1, 6 nE, 6 nE
+ * Faces (Sections 3.2-3.3, Listings 3-4, Remark 1): neighbour across local face k = the
+ * other tet holding the face (the paper's Edges2Tetra(e_ij, e_jk)); a face is numbered at
+ * its owner (lowest tet index holding it) by rank of (owner, local face).
+ *   faces[3][nF]         owner's oriented tuple (paper's Faces); capacity 12 nE ints
+ *   tet2face[4][nE]      face of local face k of tet t (fullFaces' g_ind)
+ *   sigma[4][nE]         +1 at the owner's occurrence, -1 at the other (sigma_k, Section 4.1)
+ *   face2tet[2][nF]      slot 4t+k of the owner, slot of the neighbour or -1; capacity 8 nE
+ *   nbr[4][nE]           tet across local face k, -1 on the boundary (may be NULL)
+ * counts (host int64[3]): nEd, nF, nB (boundary faces).  Face outputs may be NULL without
+ * the FACES flag.  Synchronizes `stream` (counts are read back).
+ * Errors: EINVAL (nC, nE <= 0 or > 2^28 / 2^26, node out of range, repeated node in a tet),
+ * EORIENT (a face held by two tets in the same orientation or by more than two tets). */
+int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, void* work, size_t work_bytes,
+                  int32_t* edges, int32_t* tet2edge, int32_t* edge_first_tet, int32_t* tet_edge_prefix,
+                  int32_t* n2e_rowptr, int32_t* n2e_col, int32_t* n2e_edge, int32_t* faces, int32_t* tet2face,
+                  int8_t* sigma, int32_t* face2tet, int32_t* nbr, int64_t* counts, phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- refine (a4) ------- */
+/* 12-subtet red refinement (Section 3.4, RedRefine + refineFaces).  New nodes: for every
+ * tet its centroid (((x_I+x_J)+x_K)+x_L)/4 and the midpoints (x_a+x_b)/2 of its edges, in
+ * first-appearance order over (tet; centroid, IJ, IK, IL, JK, JL, KL) -- the paper's
+ * coordinate-keyed stable unique.  In closed form: centroid(t) = nC + t + prefix(t),
+ * midpoint(e) = nC + first_tet(e) + e + 1.  Child 1 of tet t at row t, children 2..12 at
+ * rows nE + 11 t + (c - 2) with the vertex lists of RedRefine.  Boundary faces [n1 n2 n3]
+ * split into 4 keeping their orientation, child 1 at row f, children 2..4 at
+ * n + 3 f + (c - 2).
+ * Inputs: the coarse mesh and its phfem_connect edge outputs (+ Nodes2Edge CSR when
+ * nDb + nNb > 0).  Outputs: coord_out[3][nC + nEd + nE], tetra_out[4][12 nE],
+ * db_out[3][4 nDb], nb_out[3][4 nNb] (row strides = those counts).  Coordinates are
+ * bitwise those of the paper's formulas.  Synchronizes only when nDb + nNb > 0
+ * (EINVAL if a boundary face is not a mesh face). */
+int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
+                 const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
+                 const int32_t* n2e_rowptr, const int32_t* n2e_col, const int32_t* n2e_edge, int64_t nDb,
+                 const int32_t* db, int64_t nNb, const int32_t* nb, double* coord_out, int32_t* tetra_out,
+                 int32_t* db_out, int32_t* nb_out, phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- assemble (a5-a6) --- */
+/* Per-tet local blocks (Sections 4.2-4.5; StiffMassPH, Multiplier, the page solves of
+ * SchurComplement_vectorization).  kappa[nE] may be NULL (then p->kappa_const).
+ * Outputs (each may be NULL; float64 in both precisions):
+ *   vol[nE]      |det J| / 6
+ *   K[16][nE]    kappa K(T), row-major 4x4 (K(T) of Section 4.2 with |T| read as 6 vol)
+ *   d[4][nE]     sigma_k |F_k|; C(T) row k = d_k r_k (C(T) of Section 4.2)
+ *   B[4][nE]     load vector of the tet (rule p->quad)
+ *   S[16][nE]    element Schur block C A^-1 C' with A = kappa K + c M (SPD; the paper's
+ *                S(T) is its negative)
+ *   r[4][nE]     C A^-1 B
+ * Errors: EINVAL, ESINGULAR (c <= 0).  Does not synchronize. */
+int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, const int8_t* sigma,
+                   const double* kappa, const phfem_params* p, double* vol, double* K, double* d, double* B,
+                   double* S, double* r, phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- condense (a5-a7) --- */
+size_t phfem_condense_workspace(int64_t nF);
+
+/* Condensed face system S+ lambda = r+ with S+ = sum_T P_T' C A^-1 C' P_T and
+ * r+ = b_D - sum_T P_T' C A^-1 B, b_D,F = |F| u_D(centroid F) on boundary faces
+ * (Algorithm 1 lines "Assemble", Listing 8; sign-flipped to SPD form).
+ * Storage: diagonal separate, off-diagonals as CSR with columns ascending:
+ *   rowptr[nF+1] (row F holds 6 entries, 3 for a boundary face), col[6 nF] and val[6 nF]
+ *   (capacities), diag[nF], rhs[nF]; all float64 (the FP64 sums of FP32 blocks in mixed).
+ * Each off-diagonal has exactly one contributing tet; diagonal and rhs entries sum at most
+ * two tet contributions (bitwise order independent).  Inputs from phfem_connect.
+ * Errors: EINVAL, ESINGULAR, EWORKSPACE.  Does not synchronize (EDEGEN is reported by
+ * phfem_solve). */
+int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                   const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* nbr,
+                   const int32_t* face2tet, const double* kappa, const phfem_params* p, void* work,
+                   size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag, double* rhs,
+                   phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- solve (a8-a9) ------ */
+enum { PHFEM_SOLVE_FP64_PCG = 0, PHFEM_SOLVE_FP32_PCG_FP64_IR = 1 };
+
+typedef struct {
+  int32_t iters;    /* PCG iterations (all inner iterations in IR mode) */
+  int32_t ir_steps; /* outer refinement steps (IR mode) */
+  double rel_res;   /* final ||b_D - C U(lambda)|| / ||r+||, evaluated in FP64 matrix-free */
+  double rhs_norm;  /* ||r+|| */
+} phfem_solve_stats;
+
+size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
+
+/* Solve S+ lambda = r+ (Jacobi-PCG; the paper solves it with a sparse direct solver,
+ * Listing 8) and recover U(T) = A(T)^-1 (B(T) + C(T)' lambda(T)) (Algorithm 1, last loop).
+ *  mode FP64_PCG: PCG on the FP64 system to ||r|| <= tol ||r+||.
+ *  mode FP32_PCG_FP64_IR: iterative refinement; residual b_D - C U(lambda) recomputed per
+ *    tet in FP64 from the geometry (not from the stored system), corrections by FP32 PCG
+ *    on an FP32 copy of the system to relative tolerance inner_tol.
+ * Outputs: lambda[nF], U[4][nE] (float64).  Synchronizes (residual checks every few
+ * iterations).  Errors: EINVAL, EDEGEN, ENOCONV (max_iter reached; outputs and stats hold
+ * the last iterate), EWORKSPACE. */
+int phfem_solve(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
+                const double* kappa, const phfem_params* p, const int32_t* rowptr, const int32_t* col,
+                const double* val, const double* diag, const double* rhs, int32_t mode, double tol, double inner_tol,
+                int32_t max_iter, void* work, size_t work_bytes, double* lambda, double* U,
+                phfem_solve_stats* stats, phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- grad (a10) -------- */
+size_t phfem_grad_workspace(int64_t nE, int64_t nF, int32_t mode);
+
+/* Adjoint gradient of a scalar J(U) given dJdU[4][nE] at the solution (U, lambda) of
+ * phfem_solve: one adjoint face solve S+ Q = -C A^-1 dJdU (same system and mode), then
+ * P = A^-1 (dJdU + C'Q) and, per tet,
+ *   dJ/dlog kappa_T = -kappa_T P_T' K_T U_T,
+ *   dJ/dX = -d/dX [P'A U - lambda'C P - P'B - Q'C U + Q'b_D]  (P, U, lambda, Q fixed).
+ * Outputs: dJ_dlogkappa[nE] (may be NULL), dJ_dcoord[3][nC] (may be NULL; zeroed and
+ * accumulated with atomics).  Synchronizes.  Errors as phfem_solve. */
+int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF, const int32_t* faces,
+               const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet, const int32_t* nbr,
+               const double* kappa, const phfem_params* p, const int32_t* rowptr, const int32_t* col,
+               const double* val, const double* diag, const double* U, const double* lambda, const double* dJdU,
+               int32_t mode, double tol, double inner_tol, int32_t max_iter, void* work, size_t work_bytes,
+               double* dJ_dlogkappa, double* dJ_dcoord, phfem_solve_stats* stats, phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- profiling --------- */
+/* When enabled, every kernel launch of the library is bracketed by HIP events on its
+ * stream.  phfem_profile_query synchronizes those events and returns, for the kernel
+ * named `name`, the number of launches and their summed duration (ms) since the last
+ * reset.  phfem_profile_names writes the names seen, comma separated. */
+void phfem_profile_enable(int32_t on);
+void phfem_profile_reset(void);
+int phfem_profile_query(const char* name, int64_t* launches, double* total_ms);
+int phfem_profile_names(char* buf, size_t buf_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHFEM_H */

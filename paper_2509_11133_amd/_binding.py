@@ -1,0 +1,195 @@
+"""ctypes binding of libphfem.so: one Python function per C entry point, same names.
+
+Argument marshalling only: every step runs in the library's HIP kernels.  Tensors are
+torch tensors on the current HIP device (device pointers), launches go to the current
+torch stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphfem.so")
+
+OK, EINVAL, EORIENT, EDEGEN, ESINGULAR, ENOCONV, EWORKSPACE, EHIP = range(8)
+FUN_ZERO, FUN_CONST, FUN_SIN3, FUN_LINEAR, FUN_X2Y2Z2, FUN_X2Y2Z2_LOAD = range(6)
+QUAD_FACE_CENTROID, QUAD_P1_INTERP = 0, 1
+FP64, MIXED = 0, 1
+CONNECT_EDGES, CONNECT_FACES, CONNECT_NODES2EDGE = 1, 2, 4
+SOLVE_FP64_PCG, SOLVE_FP32_PCG_FP64_IR = 0, 1
+
+EXPORTS = [
+    "phfem_last_error", "phfem_abi_version", "phfem_connect_workspace", "phfem_connect", "phfem_refine",
+    "phfem_assemble", "phfem_condense_workspace", "phfem_condense", "phfem_solve_workspace", "phfem_solve",
+    "phfem_grad_workspace", "phfem_grad", "phfem_profile_enable", "phfem_profile_reset", "phfem_profile_query",
+    "phfem_profile_names",
+]
+
+
+class PhfemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"phfem error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("c", C.c_double),
+        ("kappa_const", C.c_double),
+        ("f_kind", C.c_int32),
+        ("f_par", C.c_double * 4),
+        ("ud_kind", C.c_int32),
+        ("ud_par", C.c_double * 4),
+        ("quad", C.c_int32),
+        ("precision", C.c_int32),
+    ]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("rel_res", C.c_double), ("rhs_norm", C.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, ir_steps=self.ir_steps, rel_res=self.rel_res, rhs_norm=self.rhs_norm)
+
+
+def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE_CENTROID, precision=FP64):
+    p = Params()
+    p.c, p.kappa_const = c, kappa
+    p.f_kind = f[0]
+    for i, v in enumerate(f[1]):
+        p.f_par[i] = v
+    p.ud_kind = ud[0]
+    for i, v in enumerate(ud[1]):
+        p.ud_par[i] = v
+    p.quad, p.precision = quad, precision
+    return p
+
+
+_lib = None
+VP, I64, I32, SZ, DBL = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t, C.c_double
+
+
+def lib():
+    """Load libphfem.so (raises if it was not built: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python paper_2509_11133_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        L.phfem_last_error.restype = C.c_char_p
+        for n in ("phfem_connect_workspace", "phfem_condense_workspace", "phfem_solve_workspace",
+                  "phfem_grad_workspace"):
+            getattr(L, n).restype = SZ
+        L.phfem_connect_workspace.argtypes = [I64, I64, I32]
+        L.phfem_condense_workspace.argtypes = [I64]
+        L.phfem_solve_workspace.argtypes = [I64, I64, I32]
+        L.phfem_grad_workspace.argtypes = [I64, I64, I32]
+        L.phfem_connect.argtypes = [I64, I64, VP, I32, VP, SZ] + [VP] * 12 + [VP, VP]
+        L.phfem_refine.argtypes = [I64, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP]
+        L.phfem_assemble.argtypes = [I64, VP, I64, VP, VP, VP, VP] + [VP] * 6 + [VP]
+        L.phfem_condense.argtypes = [I64, VP, I64, VP, I64] + [VP] * 7 + [VP, SZ] + [VP] * 5 + [VP]
+        L.phfem_solve.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 6 + [VP] * 5 + [I32, DBL, DBL, I32, VP, SZ]
+                                  + [VP] * 3 + [VP])
+        L.phfem_grad.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 7 + [VP] * 4 + [VP] * 3
+                                 + [I32, DBL, DBL, I32, VP, SZ] + [VP] * 3 + [VP])
+        L.phfem_profile_enable.argtypes = [I32]
+        L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP]
+        L.phfem_profile_names.argtypes = [C.c_char_p, SZ]
+        _lib = L
+    return _lib
+
+
+def _p(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _chk(rc):
+    if rc != 0:
+        raise PhfemError(rc, lib().phfem_last_error().decode())
+
+
+def workspace(nbytes, device):
+    """Caller-owned scratch (uint8, 256-byte aligned start)."""
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off: off + int(nbytes)] if nbytes else t[:0]
+
+
+# ---------------------------------------------------------------- raw entry points
+def phfem_connect(nC, nE, tetra, flags, work, edges, tet2edge, edge_first_tet, tet_edge_prefix, n2e_rowptr, n2e_col,
+                  n2e_edge, faces, tet2face, sigma, face2tet, nbr, counts):
+    _chk(lib().phfem_connect(nC, nE, _p(tetra), flags, _p(work), work.numel(), _p(edges), _p(tet2edge),
+                             _p(edge_first_tet), _p(tet_edge_prefix), _p(n2e_rowptr), _p(n2e_col), _p(n2e_edge),
+                             _p(faces), _p(tet2face), _p(sigma), _p(face2tet), _p(nbr), _p(counts), _stream()))
+
+
+def phfem_refine(nC, coord, nE, tetra, nEd, tet2edge, edge_first_tet, tet_edge_prefix, n2e_rowptr, n2e_col, n2e_edge,
+                 nDb, db, nNb, nb, coord_out, tetra_out, db_out, nb_out):
+    _chk(lib().phfem_refine(nC, _p(coord), nE, _p(tetra), nEd, _p(tet2edge), _p(edge_first_tet), _p(tet_edge_prefix),
+                            _p(n2e_rowptr), _p(n2e_col), _p(n2e_edge), nDb, _p(db), nNb, _p(nb), _p(coord_out),
+                            _p(tetra_out), _p(db_out), _p(nb_out), _stream()))
+
+
+def phfem_assemble(nC, coord, nE, tetra, sigma, kappa, prm, vol, K, d, B, S, r):
+    _chk(lib().phfem_assemble(nC, _p(coord), nE, _p(tetra), _p(sigma), _p(kappa), C.addressof(prm), _p(vol), _p(K),
+                              _p(d), _p(B), _p(S), _p(r), _stream()))
+
+
+def phfem_condense(nC, coord, nE, tetra, nF, faces, tet2face, sigma, nbr, face2tet, kappa, prm, work, rowptr, col, val,
+                   diag, rhs):
+    _chk(lib().phfem_condense(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(nbr),
+                              _p(face2tet), _p(kappa), C.addressof(prm), _p(work), work.numel(), _p(rowptr), _p(col),
+                              _p(val), _p(diag), _p(rhs), _stream()))
+
+
+def phfem_solve(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, kappa, prm, rowptr, col, val, diag, rhs,
+                mode, tol, inner_tol, max_iter, work, lam, U, stats, check=True):
+    rc = lib().phfem_solve(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(face2tet),
+                           _p(kappa), C.addressof(prm), _p(rowptr), _p(col), _p(val), _p(diag), _p(rhs), mode, tol,
+                           inner_tol, max_iter, _p(work), work.numel(), _p(lam), _p(U), C.addressof(stats), _stream())
+    if check:
+        _chk(rc)
+    return rc
+
+
+def phfem_grad(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, nbr, kappa, prm, rowptr, col, val, diag, U,
+               lam, dJdU, mode, tol, inner_tol, max_iter, work, dlogk, dX, stats):
+    _chk(lib().phfem_grad(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(face2tet), _p(nbr),
+                          _p(kappa), C.addressof(prm), _p(rowptr), _p(col), _p(val), _p(diag), _p(U), _p(lam),
+                          _p(dJdU), mode, tol, inner_tol, max_iter, _p(work), work.numel(), _p(dlogk), _p(dX),
+                          C.addressof(stats), _stream()))
+
+
+def phfem_profile_enable(on):
+    lib().phfem_profile_enable(1 if on else 0)
+
+
+def phfem_profile_reset():
+    lib().phfem_profile_reset()
+
+
+def phfem_profile_query(name):
+    n = C.c_int64()
+    ms = C.c_double()
+    _chk(lib().phfem_profile_query(name.encode(), C.addressof(n), C.addressof(ms)))
+    return n.value, ms.value
+
+
+def phfem_profile_names():
+    buf = C.create_string_buffer(8192)
+    _chk(lib().phfem_profile_names(buf, 8192))
+    return [s for s in buf.value.decode().split(",") if s]

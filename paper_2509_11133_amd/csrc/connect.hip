@@ -1,0 +1,367 @@
+// Connectivity on the device (Sections 3.1-3.3): Nodes-to-Edge numbering (NumEdges),
+// the neighbour across every face (the role of Edges2Tetra) and the face numbering of
+// FacesUp / fullFaces.
+//
+// Both numberings are "rank of first appearance" over a position order (edges: 6t + j,
+// faces: 4t + k).  On the GPU: build one key per occurrence, stable radix sort (key,
+// position), mark segment heads (= first appearance, since the sort is stable), count heads
+// per tet and scan -> per-tet prefix, then every occurrence takes the id
+// prefix(t_head) + (heads of t_head before j_head).  Segment heads are found with wave64
+// ballots over the sorted keys.
+#include "common.hpp"
+
+namespace ph {
+
+constexpr int CT = 256;  // threads per workgroup for the element-wise kernels
+
+static inline int bits_for(int64_t n) {  // bits needed for values in [0, n)
+  int b = 1;
+  while ((int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------- edges
+// keys[6t+j] = (min << nb) | max of local edge j of tet t; validates node ids.
+__global__ __launch_bounds__(CT) void k_edge_keys(int64_t nE, int64_t nC, const int32_t* __restrict__ tet, int nb,
+                                                  uint64_t* __restrict__ keys, int* __restrict__ flags) {
+  int64_t t = (int64_t)blockIdx.x * CT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    bad |= v[i] < 0 || v[i] >= nC;
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) bad |= v[i] == v[j];
+  }
+  if (bad) atomicOr(flags, DEV_BADNODE);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    uint32_t a = (uint32_t)v[ev0(j)], b = (uint32_t)v[ev1(j)];
+    uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    keys[6 * t + j] = ((uint64_t)lo << nb) | hi;
+  }
+}
+
+// first[pos] = 1 if the sorted element s starts a segment of equal keys
+__global__ __launch_bounds__(CT) void k_mark_heads(int64_t n, const uint64_t* __restrict__ sk,
+                                                   const int32_t* __restrict__ sv, uint32_t vmask,
+                                                   uint8_t* __restrict__ first) {
+  int64_t s = (int64_t)blockIdx.x * CT + threadIdx.x;
+  if (s >= n) return;
+  bool head = s == 0 || sk[s] != sk[s - 1];
+  first[(uint32_t)sv[s] & vmask] = head ? 1 : 0;
+}
+
+// cnt[t] = number of first appearances among the `per` positions of tet t
+template <int PER>
+__global__ __launch_bounds__(CT) void k_count_heads(int64_t nE, const uint8_t* __restrict__ first,
+                                                    uint32_t* __restrict__ cnt) {
+  int64_t t = (int64_t)blockIdx.x * CT + threadIdx.x;
+  if (t > nE) return;
+  uint32_t c = 0;
+  if (t < nE) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c += first[PER * t + j];
+  }
+  cnt[t] = c;  // cnt[nE] = 0 (room for the total)
+}
+
+// id of the first appearance at position p = PER*t + j
+template <int PER>
+__device__ __forceinline__ int32_t head_id(int64_t p, const uint8_t* __restrict__ first,
+                                           const uint32_t* __restrict__ prefix) {
+  int64_t t = p / PER;
+  int j = (int)(p - PER * t);
+  uint32_t id = prefix[t];
+  for (int i = 0; i < j; ++i) id += first[PER * t + i];
+  return (int32_t)id;
+}
+
+// Position of the segment head of sorted element s: nearest head at or below this lane in
+// the wave (ballot), else walk back in memory (segments are a few elements long).
+__device__ __forceinline__ int64_t find_head(int64_t s, bool valid, uint64_t key, bool head,
+                                             const uint64_t* __restrict__ sk) {
+  const int lane = lane_id();
+  uint64_t hm = ballot(head);
+  if (!valid) return s;
+  uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  uint64_t m = hm & le;
+  if (m) {
+    int hl = 63 - __clzll((long long)m);
+    return s - (lane - hl);
+  }
+  int64_t h = s - lane;  // first element of this wave's window; its head lies before it
+  while (h > 0 && sk[h - 1] == key) --h;
+  return h;
+}
+
+__global__ __launch_bounds__(CT) void k_edge_assign(int64_t n, int64_t nE, int64_t nEd, int nb,
+                                                    const uint64_t* __restrict__ sk, const int32_t* __restrict__ sv,
+                                                    const uint8_t* __restrict__ first,
+                                                    const uint32_t* __restrict__ prefix,
+                                                    int32_t* __restrict__ tet2edge, int32_t* __restrict__ edges,
+                                                    int32_t* __restrict__ eft, uint32_t* __restrict__ headflag) {
+  int64_t s = (int64_t)blockIdx.x * CT + threadIdx.x;
+  bool valid = s < n;
+  uint64_t key = valid ? sk[s] : 0;
+  bool head = valid && (s == 0 || sk[s - 1] != key);
+  int64_t h = find_head(s, valid, key, head, sk);
+  if (!valid) return;
+  int64_t ph = (int64_t)sv[h];
+  int32_t id = head_id<6>(ph, first, prefix);
+  int64_t p = (int64_t)sv[s];
+  int64_t t = p / 6;
+  int j = (int)(p - 6 * t);
+  tet2edge[j * nE + t] = id;
+  if (head) {
+    edges[id] = (int32_t)(key >> nb);
+    edges[nEd + id] = (int32_t)(key & ((1ull << nb) - 1ull));
+    eft[id] = (int32_t)t;
+  }
+  if (headflag) headflag[s] = head ? 1u : 0u;
+}
+
+// Nodes2Edge (upper triangle) CSR from the sorted unique keys; uidx = exclusive scan of
+// the head flags in sorted order (= rank of the key among the distinct keys).
+__global__ __launch_bounds__(CT) void k_n2e_fill(int64_t n, int nb, const uint64_t* __restrict__ sk,
+                                                 const int32_t* __restrict__ sv, const uint32_t* __restrict__ uidx,
+                                                 int64_t nE, const int32_t* __restrict__ tet2edge,
+                                                 int32_t* __restrict__ col, int32_t* __restrict__ eid,
+                                                 uint32_t* __restrict__ rowcnt) {
+  int64_t s = (int64_t)blockIdx.x * CT + threadIdx.x;
+  if (s >= n) return;
+  uint64_t key = sk[s];
+  if (s > 0 && sk[s - 1] == key) return;
+  uint32_t u = uidx[s];
+  int64_t p = sv[s];
+  int64_t t = p / 6;
+  int j = (int)(p - 6 * t);
+  col[u] = (int32_t)(key & ((1ull << nb) - 1ull));
+  eid[u] = tet2edge[j * nE + t];
+  atomicAdd(&rowcnt[key >> nb], 1u);
+}
+
+// ---------------------------------------------------------------- faces
+// key of local face k = (min node << eb) | edge opposite to that node within the face;
+// value = slot 4t+k with the parity of the tuple's node order in bit 30.
+__global__ __launch_bounds__(CT) void k_face_keys(int64_t nE, const int32_t* __restrict__ tet,
+                                                  const int32_t* __restrict__ t2e, int eb,
+                                                  uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  int64_t t = (int64_t)blockIdx.x * CT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], e[6];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) e[j] = t2e[j * nE + t];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a = fv(k, 0), b = fv(k, 1), c = fv(k, 2);
+    int na = v[a], nb_ = v[b], nc = v[c];
+    int lo, oe;
+    if (na < nb_ && na < nc) {
+      lo = na;
+      oe = e[eidx(b, c)];
+    } else if (nb_ < nc) {
+      lo = nb_;
+      oe = e[eidx(a, c)];
+    } else {
+      lo = nc;
+      oe = e[eidx(a, b)];
+    }
+    int parity = ((na > nb_) + (na > nc) + (nb_ > nc)) & 1;
+    keys[4 * t + k] = ((uint64_t)(uint32_t)lo << eb) | (uint32_t)oe;
+    vals[4 * t + k] = (int32_t)((4 * t + k) | ((int64_t)parity << 30));
+  }
+}
+
+constexpr uint32_t SLOT_MASK = (1u << 30) - 1u;
+
+__global__ __launch_bounds__(CT) void k_face_assign(int64_t n, int64_t nE, int64_t nF,
+                                                    const uint64_t* __restrict__ sk, const int32_t* __restrict__ sv,
+                                                    const uint8_t* __restrict__ first,
+                                                    const uint32_t* __restrict__ prefix,
+                                                    const int32_t* __restrict__ tet, int32_t* __restrict__ faces,
+                                                    int32_t* __restrict__ tet2face, int8_t* __restrict__ sigma,
+                                                    int32_t* __restrict__ face2tet, int32_t* __restrict__ nbr,
+                                                    int* __restrict__ flags) {
+  int64_t s = (int64_t)blockIdx.x * CT + threadIdx.x;
+  if (s >= n) return;
+  uint64_t key = sk[s];
+  bool head = s == 0 || sk[s - 1] != key;
+  if (head) {
+    uint32_t v0 = (uint32_t)sv[s];
+    int64_t q0 = v0 & SLOT_MASK;
+    int64_t t0 = q0 >> 2;
+    int k0 = (int)(q0 & 3);
+    int32_t id = head_id<4>(q0, first, prefix);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) faces[m * nF + id] = tet[fv(k0, m) * nE + t0];
+    face2tet[id] = (int32_t)q0;
+    tet2face[k0 * nE + t0] = id;
+    sigma[k0 * nE + t0] = 1;
+    bool two = s + 1 < n && sk[s + 1] == key;
+    if (two) {
+      uint32_t v1 = (uint32_t)sv[s + 1];
+      int64_t q1 = v1 & SLOT_MASK;
+      face2tet[nF + id] = (int32_t)q1;
+      if (nbr) nbr[k0 * nE + t0] = (int32_t)(q1 >> 2);
+      bool three = s + 2 < n && sk[s + 2] == key;
+      if (three || ((v0 >> 30) == (v1 >> 30))) atomicOr(flags, DEV_ORIENT);
+    } else {
+      face2tet[nF + id] = -1;
+      if (nbr) nbr[k0 * nE + t0] = -1;
+    }
+  } else {
+    if (s >= 2 && sk[s - 2] == key) return;  // third occurrence: flagged by the head
+    int64_t q0 = (uint32_t)sv[s - 1] & SLOT_MASK;
+    int64_t q1 = (uint32_t)sv[s] & SLOT_MASK;
+    int64_t t1 = q1 >> 2;
+    int k1 = (int)(q1 & 3);
+    int32_t id = head_id<4>(q0, first, prefix);
+    tet2face[k1 * nE + t1] = id;
+    sigma[k1 * nE + t1] = -1;
+    if (nbr) nbr[k1 * nE + t1] = (int32_t)(q0 >> 2);
+  }
+}
+
+// ---------------------------------------------------------------- workspace layout
+struct ConnWS {
+  uint64_t *kA, *kB;
+  int32_t *vA, *vB;
+  uint8_t* first;
+  uint32_t* cnt;   // nE + 1
+  uint32_t* flag;  // head flags / ranks in sorted order (Nodes2Edge only)
+  uint32_t* rowcnt;
+  int* dflags;
+  uint32_t* total;
+  size_t sub;  // offset where the sort/scan scratch starts
+};
+
+static void conn_layout(Arena& a, int64_t nC, int64_t nE, int32_t flags, ConnWS& w) {
+  int64_t n = 6 * nE;
+  w.kA = a.take<uint64_t>(n);
+  w.kB = a.take<uint64_t>(n);
+  w.vA = a.take<int32_t>(n);
+  w.vB = a.take<int32_t>(n);
+  w.first = a.take<uint8_t>(n);
+  w.cnt = a.take<uint32_t>(nE + 1);
+  w.flag = (flags & PHFEM_CONNECT_NODES2EDGE) ? a.take<uint32_t>(n) : nullptr;  // head flags, then ranks
+  w.rowcnt = (flags & PHFEM_CONNECT_NODES2EDGE) ? a.take<uint32_t>(nC + 1) : nullptr;
+  w.dflags = a.take<int>(16);
+  w.total = a.take<uint32_t>(16);
+  w.sub = a.size();
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags) {
+  if (nC <= 0 || nE <= 0) return 0;
+  Arena a;
+  ConnWS w;
+  conn_layout(a, nC, nE, flags, w);
+  size_t extra = sort_workspace(6 * nE);
+  extra = std::max(extra, scan_workspace(6 * nE + 1));
+  extra = std::max(extra, scan_workspace(nC + 1));
+  return w.sub + extra;
+}
+
+extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, void* work,
+                             size_t work_bytes, int32_t* edges, int32_t* tet2edge, int32_t* edge_first_tet,
+                             int32_t* tet_edge_prefix, int32_t* n2e_rowptr, int32_t* n2e_col, int32_t* n2e_edge,
+                             int32_t* faces, int32_t* tet2face, int8_t* sigma, int32_t* face2tet, int32_t* nbr,
+                             int64_t* counts, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  if (nC <= 0 || nE <= 0) return err(PHFEM_EINVAL, "nC and nE must be positive");
+  if (nE > (int64_t(1) << 26) || nC > (int64_t(1) << 28)) return err(PHFEM_EINVAL, "mesh too large for int32 ids");
+  if (!tetra || !edges || !tet2edge || !edge_first_tet || !tet_edge_prefix || !counts)
+    return err(PHFEM_EINVAL, "null edge output");
+  const bool want_faces = flags & PHFEM_CONNECT_FACES, want_n2e = flags & PHFEM_CONNECT_NODES2EDGE;
+  if (want_faces && (!faces || !tet2face || !sigma || !face2tet)) return err(PHFEM_EINVAL, "null face output");
+  if (want_n2e && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "null Nodes2Edge output");
+  if (!work || work_bytes < phfem_connect_workspace(nC, nE, flags))
+    return err(PHFEM_EWORKSPACE, "connect workspace too small");
+
+  Arena a(work, work_bytes);
+  ConnWS w;
+  conn_layout(a, nC, nE, flags, w);
+  const size_t sub = w.sub;
+  const int64_t n6 = 6 * nE, n4 = 4 * nE;
+  const int nb = bits_for(nC);
+  PH_HIP(hipMemsetAsync(w.dflags, 0, sizeof(int), s));
+
+  // ---- edges
+  PH_LAUNCH("edge_keys", k_edge_keys, grid_for(nE, CT), CT, 0, s, nE, nC, tetra, nb, w.kA, w.dflags);
+  int hflags = 0;
+  PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  if (hflags) return dev_flags_to_status(hflags);
+
+  uint64_t* sk;
+  int32_t* sv;
+  a.off = sub;
+  int rc = radix_sort(w.kA, w.vA, w.kB, w.vB, nullptr, n6, 2 * nb, &sk, &sv, a, s);
+  if (rc) return rc;
+  PH_LAUNCH("mark_heads", k_mark_heads, grid_for(n6, CT), CT, 0, s, n6, (const uint64_t*)sk, (const int32_t*)sv,
+            0xffffffffu, w.first);
+  PH_LAUNCH("count_heads6", k_count_heads<6>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
+  a.off = sub;
+  rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
+  if (rc) return rc;
+  uint32_t nEd32 = 0;
+  PH_HIP(hipMemcpyAsync(&nEd32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  const int64_t nEd = nEd32;
+  PH_HIP(hipMemcpyAsync(tet_edge_prefix, w.cnt, sizeof(int32_t) * nE, hipMemcpyDeviceToDevice, s));
+  PH_LAUNCH("edge_assign", k_edge_assign, grid_for(n6, CT), CT, 0, s, n6, nE, nEd, nb, (const uint64_t*)sk,
+            (const int32_t*)sv, (const uint8_t*)w.first, (const uint32_t*)w.cnt, tet2edge, edges, edge_first_tet,
+            w.flag);
+  if (want_n2e) {
+    a.off = sub;
+    rc = scan_exclusive(w.flag, w.flag, n6, nullptr, a, s);  // in place: head flag -> unique rank
+    if (rc) return rc;
+    PH_HIP(hipMemsetAsync(w.rowcnt, 0, sizeof(uint32_t) * (nC + 1), s));
+    PH_LAUNCH("n2e_fill", k_n2e_fill, grid_for(n6, CT), CT, 0, s, n6, nb, (const uint64_t*)sk, (const int32_t*)sv,
+              (const uint32_t*)w.flag, nE, (const int32_t*)tet2edge, n2e_col, n2e_edge, w.rowcnt);
+    a.off = sub;
+    rc = scan_exclusive(w.rowcnt, (uint32_t*)n2e_rowptr, nC + 1, nullptr, a, s);
+    if (rc) return rc;
+  }
+  counts[0] = nEd;
+  counts[1] = 0;
+  counts[2] = 0;
+  if (!want_faces) return PHFEM_OK;
+
+  // ---- faces: key = (min node, opposite edge) of every local face
+  const int eb = bits_for(nEd);
+  PH_LAUNCH("face_keys", k_face_keys, grid_for(nE, CT), CT, 0, s, nE, tetra, (const int32_t*)tet2edge, eb, w.kA,
+            w.vA);
+  a.off = sub;
+  rc = radix_sort(w.kA, w.vA, w.kB, w.vB, w.vA, n4, nb + eb, &sk, &sv, a, s);
+  if (rc) return rc;
+  PH_LAUNCH("mark_heads", k_mark_heads, grid_for(n4, CT), CT, 0, s, n4, (const uint64_t*)sk, (const int32_t*)sv,
+            SLOT_MASK, w.first);
+  PH_LAUNCH("count_heads4", k_count_heads<4>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
+  a.off = sub;
+  rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
+  if (rc) return rc;
+  uint32_t nF32 = 0;
+  PH_HIP(hipMemcpyAsync(&nF32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  const int64_t nF = nF32;
+  PH_LAUNCH("face_assign", k_face_assign, grid_for(n4, CT), CT, 0, s, n4, nE, nF, (const uint64_t*)sk,
+            (const int32_t*)sv, (const uint8_t*)w.first, (const uint32_t*)w.cnt, tetra, faces, tet2face, sigma,
+            face2tet, nbr, w.dflags);
+  PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  if (hflags) return dev_flags_to_status(hflags);
+  counts[1] = nF;
+  counts[2] = 2 * nF - 4 * nE;  // 4 nE = 2 nI + nB and nF = nI + nB
+  return PHFEM_OK;
+}

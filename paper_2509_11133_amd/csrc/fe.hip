@@ -1,0 +1,576 @@
+// Local matrices, element Schur complement and condensed face system (Sections 4.2-4.6,
+// Algorithm 1), the matrix-free FP64 recovery / residual, and the adjoint VJP.
+//
+// Element algebra (one tet, R = double or float):
+//   A = kappa K + c M with K = vol g_i.g_j and M = c vol/20 (1 + delta_ij).  K 1 = 0 and
+//   M 1 = vol/4 1, so 1 is an eigenvector of A with eigenvalue c vol/4 and
+//       A^-1 = 1 1' / (c vol) + W,   W = (A restricted to 1-perp)^-1  (W 1 = 0).
+//   W is formed in the orthonormal basis q1 = (1,1,-1,-1)/2, q2 = (1,-1,1,-1)/2,
+//   q3 = (1,-1,-1,1)/2 of 1-perp: N = kappa vol Gh Gh' + (c vol/20) I_3 with Gh = Q'G
+//   (3x3 SPD, conditioned like the tet's shape), W = Q N^-1 Q'.
+//   C row k = d_k r_k with d_k = sigma_k |F_k| and r_k = (1 1' - Pi)/3 row k, Pi the
+//   face -> opposite-vertex permutation; with W 1 = 0 this gives
+//       S_kl = d_k d_l (1/(c vol) + W[opp k][opp l] / 9),
+//       r_k  = d_k (sum B / (c vol) - (W B)[opp k] / 3),
+//       U    = 1 (sum B + sum mu) / (c vol) + W (B - Pi' mu / 3),   mu_k = d_k lambda_k.
+//   This split keeps the FP32 path accurate: A itself has cond ~ h^-2, N does not.
+#include "common.hpp"
+
+namespace ph {
+
+constexpr int FT = 256;
+
+template <class R>
+struct Elem {
+  double det, vol;  // FP64 in both precisions
+  R g[4][3];        // barycentric gradients
+  R d[4];           // sigma_k |F_k|
+  R W[4][4];
+  R icv;            // 1 / (c vol)
+  R kappa, c;
+
+  // x: vertex coordinates (FP64).  Returns false for a zero-volume tet.
+  __device__ __forceinline__ bool init(const double x[4][3], double kap, double cc, const int sig[4]) {
+    double v[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) v[i][e] = x[i + 1][e] - x[0][e];
+    det = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) - v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
+          v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
+    if (det == 0.0) return false;
+    vol = fabs(det) / 6.0;
+    kappa = (R)kap;
+    c = (R)cc;
+    R w[4][3];  // vertex positions relative to vertex 0
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      w[0][e] = (R)0;
+      w[1][e] = (R)v[0][e];
+      w[2][e] = (R)v[1][e];
+      w[3][e] = (R)v[2][e];
+    }
+    const R idet = (R)(1.0 / det);
+    // g_b = (v2 x v3)/det, g_c = (v3 x v1)/det, g_d = (v1 x v2)/det, g_a = -(g_b + g_c + g_d)
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+      const R* p = w[i == 1 ? 2 : (i == 2 ? 3 : 1)];
+      const R* q = w[i == 1 ? 3 : (i == 2 ? 1 : 2)];
+      g[i][0] = (p[1] * q[2] - p[2] * q[1]) * idet;
+      g[i][1] = (p[2] * q[0] - p[0] * q[2]) * idet;
+      g[i][2] = (p[0] * q[1] - p[1] * q[0]) * idet;
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) g[0][e] = -(g[1][e] + g[2][e] + g[3][e]);
+    // |F_k| = 0.5 |(x3 - x1) x (x2 - x1)| for the face tuple [x1 x2 x3]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = fv(k, 0), b = fv(k, 1), cc3 = fv(k, 2);
+      R u0 = w[cc3][0] - w[a][0], u1 = w[cc3][1] - w[a][1], u2 = w[cc3][2] - w[a][2];
+      R s0 = w[b][0] - w[a][0], s1 = w[b][1] - w[a][1], s2 = w[b][2] - w[a][2];
+      R n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
+      d[k] = (R)sig[k] * (R)0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    }
+    // W = Q N^-1 Q'
+    R gh[3][3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      gh[0][e] = (R)0.5 * (g[0][e] + g[1][e] - g[2][e] - g[3][e]);
+      gh[1][e] = (R)0.5 * (g[0][e] - g[1][e] + g[2][e] - g[3][e]);
+      gh[2][e] = (R)0.5 * (g[0][e] - g[1][e] - g[2][e] + g[3][e]);
+    }
+    const R kv = kappa * (R)vol, mv = c * (R)vol / (R)20;
+    R N[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int n = m; n < 3; ++n) {
+        R s = kv * (gh[m][0] * gh[n][0] + gh[m][1] * gh[n][1] + gh[m][2] * gh[n][2]);
+        if (m == n) s += mv;
+        N[m][n] = s;
+        N[n][m] = s;
+      }
+    R A00 = N[1][1] * N[2][2] - N[1][2] * N[2][1];
+    R A01 = N[0][2] * N[2][1] - N[0][1] * N[2][2];
+    R A02 = N[0][1] * N[1][2] - N[0][2] * N[1][1];
+    R A11 = N[0][0] * N[2][2] - N[0][2] * N[2][0];
+    R A12 = N[0][2] * N[1][0] - N[0][0] * N[1][2];
+    R A22 = N[0][0] * N[1][1] - N[0][1] * N[1][0];
+    R idn = (R)1 / (N[0][0] * A00 + N[0][1] * (N[1][2] * N[2][0] - N[1][0] * N[2][2]) + N[0][2] * (N[1][0] * N[2][1] - N[1][1] * N[2][0]));
+    R Ni[3][3] = {{A00 * idn, A01 * idn, A02 * idn}, {A01 * idn, A11 * idn, A12 * idn}, {A02 * idn, A12 * idn, A22 * idn}};
+    // Y = Q Ni (4x3), q_m[i] = 0.5 * sign pattern
+    const int sg[3][4] = {{1, 1, -1, -1}, {1, -1, 1, -1}, {1, -1, -1, 1}};
+    R Y[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        R s = (R)0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) s += sg[m][i] > 0 ? Ni[m][n] : -Ni[m][n];
+        Y[i][n] = (R)0.5 * s;
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i; j < 4; ++j) {
+        R s = (R)0;
+#pragma unroll
+        for (int n = 0; n < 3; ++n) s += sg[n][j] > 0 ? Y[i][n] : -Y[i][n];
+        W[i][j] = (R)0.5 * s;
+        W[j][i] = W[i][j];
+      }
+    icv = (R)(1.0 / (cc * vol));
+    return true;
+  }
+
+  __device__ __forceinline__ R S(int k, int l) const { return d[k] * d[l] * (icv + W[opp(k)][opp(l)] / (R)9); }
+
+  // r_k = (C A^-1 y)_k for a load-like vector y
+  __device__ __forceinline__ void CAinv(const R y[4], R r[4]) const {
+    R sy = (y[0] + y[1]) + (y[2] + y[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int o = opp(k);
+      R wy = W[o][0] * y[0] + W[o][1] * y[1] + W[o][2] * y[2] + W[o][3] * y[3];
+      r[k] = d[k] * (sy * icv - wy / (R)3);
+    }
+  }
+};
+
+// load vector of one tet (StiffMassPH's face-centroid rule or b = M f(x_i))
+template <class R>
+__device__ __forceinline__ void load_vec(const double x[4][3], double vol, const DevParams& P, R B[4]) {
+  if (P.quad == PHFEM_QUAD_P1_INTERP) {
+    R f[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = fun_at<R>(P.fk, P.fp, (R)x[i][0], (R)x[i][1], (R)x[i][2]);
+    R sf = (f[0] + f[1]) + (f[2] + f[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) B[i] = (R)vol / (R)20 * (sf + f[i]);
+    return;
+  }
+  R fc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a = fv(k, 0), b = fv(k, 1), c = fv(k, 2);
+    double cx = (x[a][0] + x[b][0] + x[c][0]) / 3.0;
+    double cy = (x[a][1] + x[b][1] + x[c][1]) / 3.0;
+    double cz = (x[a][2] + x[b][2] + x[c][2]) / 3.0;
+    fc[k] = fun_at<R>(P.fk, P.fp, (R)cx, (R)cy, (R)cz);
+  }
+  // vertex i lies on the three faces other than the one opposite it (opp(i))
+  const R w = (R)vol / (R)12;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) B[i] = w * (((fc[0] + fc[1]) + (fc[2] + fc[3])) - fc[opp(i)]);
+}
+
+__device__ __forceinline__ void gather_x(int64_t nC, const double* __restrict__ X, const int v[4], double x[4][3]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) x[i][e] = X[e * nC + v[i]];
+}
+
+// ---------------------------------------------------------------- assemble (inspection)
+template <class R>
+__global__ __launch_bounds__(FT) void k_assemble(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                                 const int32_t* __restrict__ tet, const int8_t* __restrict__ sigma,
+                                                 const double* __restrict__ kappa, DevParams P, double* vol,
+                                                 double* K, double* dd, double* Bo, double* So, double* ro) {
+  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], sig[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    sig[i] = sigma ? sigma[i * nE + t] : 1;
+  }
+  double x[4][3];
+  gather_x(nC, X, v, x);
+  const double kap = kappa ? kappa[t] : P.kc;
+  Elem<R> E;
+  if (!E.init(x, kap, P.c, sig)) return;
+  R B[4], r[4];
+  load_vec<R>(x, E.vol, P, B);
+  E.CAinv(B, r);
+  if (vol) vol[t] = E.vol;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (dd) dd[k * nE + t] = (double)E.d[k];
+    if (Bo) Bo[k * nE + t] = (double)B[k];
+    if (ro) ro[k * nE + t] = (double)r[k];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (K)
+        K[(4 * k + l) * nE + t] =
+            (double)(E.kappa * (R)E.vol * (E.g[k][0] * E.g[l][0] + E.g[k][1] * E.g[l][1] + E.g[k][2] * E.g[l][2]));
+      if (So) So[(4 * k + l) * nE + t] = (double)E.S(k, l);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- condense
+// per face: off-diagonal count (6 interior, 3 boundary) for the row-pointer scan, diagonal
+// cleared, rhs = b_D on boundary faces (|F| u_D(centroid)), 0 inside.
+__global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const double* __restrict__ X,
+                                                  const int32_t* __restrict__ faces,
+                                                  const int32_t* __restrict__ face2tet, DevParams P,
+                                                  uint32_t* __restrict__ cnt, double* __restrict__ diag,
+                                                  double* __restrict__ rhs) {
+  int64_t f = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (f > nF) return;
+  if (f == nF) {
+    if (cnt) cnt[nF] = 0;
+    return;
+  }
+  const bool interior = face2tet[nF + f] >= 0;
+  if (cnt) cnt[f] = interior ? 6u : 3u;
+  if (diag) diag[f] = 0.0;
+  double b = 0.0;
+  if (!interior && P.uk != PHFEM_FUN_ZERO) {
+    double x[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      int v = faces[m * nF + f];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) x[m][e] = X[e * nC + v];
+    }
+    double u0 = x[2][0] - x[0][0], u1 = x[2][1] - x[0][1], u2 = x[2][2] - x[0][2];
+    double s0 = x[1][0] - x[0][0], s1 = x[1][1] - x[0][1], s2 = x[1][2] - x[0][2];
+    double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
+    double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    double cx = (x[0][0] + x[1][0] + x[2][0]) / 3.0, cy = (x[0][1] + x[1][1] + x[2][1]) / 3.0,
+           cz = (x[0][2] + x[1][2] + x[2][2]) / 3.0;
+    b = area * fun_at<double>(P.uk, P.up, cx, cy, cz);
+  }
+  rhs[f] = b;
+}
+
+// One tet: element Schur block, off-diagonals written in place (single writer each),
+// diagonal and rhs summed with FP64 atomics onto exact zeros / b_D (at most two terms).
+template <class R>
+__global__ __launch_bounds__(FT) void k_condense(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                                 const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                                 const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
+                                                 const double* __restrict__ kappa, DevParams P,
+                                                 const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                 double* __restrict__ val, double* __restrict__ diag,
+                                                 double* __restrict__ rhs) {
+  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], sig[4], F[4], nb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    sig[i] = sigma[i * nE + t];
+    F[i] = t2f[i * nE + t];
+    nb[i] = nbr[i * nE + t];
+  }
+  double x[4][3];
+  gather_x(nC, X, v, x);
+  const double kap = kappa ? kappa[t] : P.kc;
+  Elem<R> E;
+  if (!E.init(x, kap, P.c, sig)) return;
+  R B[4], r[4];
+  load_vec<R>(x, E.vol, P, B);
+  E.CAinv(B, r);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int Fk = F[k];
+    int o[4] = {-1, -1, -1, -1};
+    if (nb[k] >= 0) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        int g = t2f[m * nE + nb[k]];
+        o[m] = (g == Fk) ? -1 : g;
+      }
+    }
+    const int base = rowptr[Fk];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (l == k) continue;
+      const int Fl = F[l];
+      int pos = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        pos += (m != k && F[m] < Fl) ? 1 : 0;
+        pos += (o[m] >= 0 && o[m] < Fl) ? 1 : 0;
+      }
+      col[base + pos] = Fl;
+      val[base + pos] = (double)E.S(k, l);
+    }
+    atomicAdd(&diag[Fk], (double)E.S(k, k));
+    atomicAdd(&rhs[Fk], -(double)r[k]);
+  }
+}
+
+// ---------------------------------------------------------------- recovery / residual (FP64)
+// U(T) = A^-1 (Bsrc + C' lambda) with Bsrc = load vector (gsrc == null) or gsrc[4][nE];
+// res[F] -= (C U)_k for every local face when res != null (res preset to b_D or 0).
+__global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                                const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                                const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
+                                                DevParams P, const double* __restrict__ lambda,
+                                                const double* __restrict__ gsrc, double* __restrict__ U,
+                                                double* __restrict__ res, int* __restrict__ flags) {
+  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], sig[4], F[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    sig[i] = sigma[i * nE + t];
+    F[i] = t2f[i * nE + t];
+  }
+  double x[4][3];
+  gather_x(nC, X, v, x);
+  const double kap = kappa ? kappa[t] : P.kc;
+  Elem<double> E;
+  if (!E.init(x, kap, P.c, sig)) {
+    if (flags) atomicOr(flags, DEV_DEGEN);
+    return;
+  }
+  double B[4];
+  if (gsrc) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) B[i] = gsrc[i * nE + t];
+  } else {
+    load_vec<double>(x, E.vol, P, B);
+  }
+  double mu[4] = {0, 0, 0, 0};
+  if (lambda) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mu[k] = E.d[k] * lambda[F[k]];
+  }
+  const double s = ((B[0] + B[1]) + (B[2] + B[3]) + ((mu[0] + mu[1]) + (mu[2] + mu[3]))) * E.icv;
+  double y[4], u[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[i] = B[i] - mu[opp(i)] / 3.0;  // face opposite vertex i is opp(i)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) u[i] = s + (E.W[i][0] * y[0] + E.W[i][1] * y[1] + E.W[i][2] * y[2] + E.W[i][3] * y[3]);
+  if (U) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) U[i * nE + t] = u[i];
+  }
+  if (res) {
+    const double su = (u[0] + u[1]) + (u[2] + u[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) atomicAdd(&res[F[k]], -E.d[k] * (su - u[opp(k)]) / 3.0);
+  }
+}
+
+// ---------------------------------------------------------------- adjoint VJP (FP64)
+// G_i = dPhi_T/dx_i for Phi_T = P'A U - lambda'C P - P'B - Q'C U + sum_bnd Q_F b_D,F;
+// dJ/dX_v -= G_i, dJ/dlog kappa_T = -kappa vol gP.gU.
+__global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                            const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                            const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
+                                            const double* __restrict__ kappa, DevParams P,
+                                            const double* __restrict__ Uu, const double* __restrict__ Pp,
+                                            const double* __restrict__ lambda, const double* __restrict__ Q,
+                                            double* __restrict__ dlogk, double* __restrict__ dX) {
+  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], sig[4];
+  double U[4], Pv[4], lam[4], Qf[4];
+  bool bnd[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    sig[i] = sigma[i * nE + t];
+    int Fi = t2f[i * nE + t];
+    lam[i] = lambda[Fi];
+    Qf[i] = Q[Fi];
+    bnd[i] = nbr[i * nE + t] < 0;
+    U[i] = Uu[i * nE + t];
+    Pv[i] = Pp[i * nE + t];
+  }
+  double x[4][3];
+  gather_x(nC, X, v, x);
+  const double kap = kappa ? kappa[t] : P.kc;
+  Elem<double> E;
+  if (!E.init(x, kap, P.c, sig)) return;
+  const double vol = E.vol, c = P.c;
+  double gU[3] = {0, 0, 0}, gP[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      gU[e] += U[i] * E.g[i][e];
+      gP[e] += Pv[i] * E.g[i][e];
+    }
+  const double gPU = gP[0] * gU[0] + gP[1] * gU[1] + gP[2] * gU[2];
+  if (dlogk) dlogk[t] = -kap * vol * gPU;
+  if (!dX) return;
+  double G[4][3];
+  const double sP = (Pv[0] + Pv[1]) + (Pv[2] + Pv[3]), sU = (U[0] + U[1]) + (U[2] + U[3]);
+  const double PU = Pv[0] * U[0] + Pv[1] * U[1] + Pv[2] * U[2] + Pv[3] * U[3];
+  // (1) P'A U: stiffness and mass parts
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double giU = E.g[i][0] * gU[0] + E.g[i][1] * gU[1] + E.g[i][2] * gU[2];
+    const double giP = E.g[i][0] * gP[0] + E.g[i][1] * gP[1] + E.g[i][2] * gP[2];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      G[i][e] = kap * vol * (gPU * E.g[i][e] - giU * gP[e] - giP * gU[e]) + c * vol / 20.0 * (PU + sP * sU) * E.g[i][e];
+  }
+  // (3) -P'B
+  if (P.quad == PHFEM_QUAD_P1_INTERP) {
+    double f[4], gf[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      f[i] = fun_at<double>(P.fk, P.fp, x[i][0], x[i][1], x[i][2]);
+      fun_grad(P.fk, P.fp, x[i][0], x[i][1], x[i][2], gf[i]);
+    }
+    const double Pf = Pv[0] * f[0] + Pv[1] * f[1] + Pv[2] * f[2] + Pv[3] * f[3];
+    const double sf = (f[0] + f[1]) + (f[2] + f[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        G[i][e] -= vol / 20.0 * ((Pf + sP * sf) * E.g[i][e] + (Pv[i] + sP) * gf[i][e]);
+  } else {
+    double fc[4], gfc[4][3], sPk[4];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = fv(k, 0), b = fv(k, 1), cc = fv(k, 2);
+      double cx = (x[a][0] + x[b][0] + x[cc][0]) / 3.0, cy = (x[a][1] + x[b][1] + x[cc][1]) / 3.0,
+             cz = (x[a][2] + x[b][2] + x[cc][2]) / 3.0;
+      fc[k] = fun_at<double>(P.fk, P.fp, cx, cy, cz);
+      fun_grad(P.fk, P.fp, cx, cy, cz, gfc[k]);
+      sPk[k] = sP - Pv[opp(k)];
+      acc += fc[k] * sPk[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        double s = vol / 12.0 * acc * E.g[i][e];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (opp(k) != i) s += vol / 36.0 * sPk[k] * gfc[k][e];
+        G[i][e] -= s;
+      }
+  }
+  // (2) -lambda'C P - Q'C U  and  (4) + Q_F b_D,F on boundary faces: area derivatives
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a = fv(k, 0), b = fv(k, 1), cc = fv(k, 2);
+    double n[3];
+    {
+      double p0 = x[b][0] - x[a][0], p1 = x[b][1] - x[a][1], p2 = x[b][2] - x[a][2];
+      double q0 = x[cc][0] - x[a][0], q1 = x[cc][1] - x[a][1], q2 = x[cc][2] - x[a][2];
+      n[0] = p1 * q2 - p2 * q1;
+      n[1] = p2 * q0 - p0 * q2;
+      n[2] = p0 * q1 - p1 * q0;
+    }
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double area = 0.5 * nn;
+    double coef = -(double)sig[k] * (lam[k] * (sP - Pv[opp(k)]) + Qf[k] * (sU - U[opp(k)])) / 3.0;
+    double gud[3] = {0, 0, 0};
+    if (bnd[k]) {
+      double cx = (x[a][0] + x[b][0] + x[cc][0]) / 3.0, cy = (x[a][1] + x[b][1] + x[cc][1]) / 3.0,
+             cz = (x[a][2] + x[b][2] + x[cc][2]) / 3.0;
+      coef += Qf[k] * fun_at<double>(P.uk, P.up, cx, cy, cz);
+      fun_grad(P.uk, P.up, cx, cy, cz, gud);
+    }
+    // d|F|/dx_a = 0.5 nhat x (x_c - x_b), cyclic
+    const int vv[3] = {a, b, cc};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int p = vv[m], q = vv[(m + 1) % 3], r = vv[(m + 2) % 3];
+      double e0 = x[r][0] - x[q][0], e1 = x[r][1] - x[q][1], e2 = x[r][2] - x[q][2];
+      double dA0 = 0.5 * (n[1] * e2 - n[2] * e1) / nn, dA1 = 0.5 * (n[2] * e0 - n[0] * e2) / nn,
+             dA2 = 0.5 * (n[0] * e1 - n[1] * e0) / nn;
+      G[p][0] += coef * dA0;
+      G[p][1] += coef * dA1;
+      G[p][2] += coef * dA2;
+      if (bnd[k]) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) G[p][e] += Qf[k] * area * gud[e] / 3.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) atomicAdd(&dX[e * nC + v[i]], -G[i][e]);
+}
+
+// instantiations used by the solver / grad drivers (solve.hip)
+int launch_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f,
+                   const int8_t* sigma, const double* kappa, const DevParams& P, const double* lambda,
+                   const double* gsrc, double* U, double* res, int* flags, hipStream_t s) {
+  PH_LAUNCH("recover", k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, kappa, P, lambda, gsrc, U,
+            res, flags);
+  return PHFEM_OK;
+}
+
+int launch_face_init(int64_t nF, int64_t nC, const double* X, const int32_t* faces, const int32_t* face2tet,
+                     const DevParams& P, uint32_t* cnt, double* diag, double* rhs, hipStream_t s) {
+  PH_LAUNCH("face_init", k_face_init, grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
+  return PHFEM_OK;
+}
+
+int launch_vjp(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f, const int8_t* sigma,
+               const int32_t* nbr, const double* kappa, const DevParams& P, const double* U, const double* Pp,
+               const double* lambda, const double* Q, double* dlogk, double* dX, hipStream_t s) {
+  PH_LAUNCH("vjp", k_vjp, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q,
+            dlogk, dX);
+  return PHFEM_OK;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, const int8_t* sigma,
+                              const double* kappa, const phfem_params* p, double* vol, double* K, double* d,
+                              double* B, double* S, double* r, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (nC <= 0 || nE <= 0 || !coord || !tetra) return err(PHFEM_EINVAL, "bad mesh arguments");
+  DevParams P = to_dev(*p);
+  if (p->precision == PHFEM_MIXED)
+    PH_LAUNCH("assemble_f32", k_assemble<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, sigma, kappa, P,
+              vol, K, d, B, S, r);
+  else
+    PH_LAUNCH("assemble_f64", k_assemble<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, sigma, kappa, P,
+              vol, K, d, B, S, r);
+  return PHFEM_OK;
+}
+
+extern "C" size_t phfem_condense_workspace(int64_t nF) { return scan_workspace(nF + 1); }
+
+extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                              const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* nbr,
+                              const int32_t* face2tet, const double* kappa, const phfem_params* p, void* work,
+                              size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag,
+                              double* rhs, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !nbr || !face2tet ||
+      !rowptr || !col || !val || !diag || !rhs)
+    return err(PHFEM_EINVAL, "bad condense arguments");
+  if (6 * nF >= (int64_t(1) << 31)) return err(PHFEM_EINVAL, "face system exceeds int32 indexing");
+  if (!work || work_bytes < phfem_condense_workspace(nF)) return err(PHFEM_EWORKSPACE, "condense workspace too small");
+  Arena a(work, work_bytes);
+  DevParams P = to_dev(*p);
+  rc = launch_face_init(nF, nC, coord, faces, face2tet, P, (uint32_t*)rowptr, diag, rhs, s);
+  if (rc) return rc;
+  rc = scan_exclusive((const uint32_t*)rowptr, (uint32_t*)rowptr, nF + 1, nullptr, a, s);
+  if (rc) return rc;
+  if (p->precision == PHFEM_MIXED)
+    PH_LAUNCH("condense_f32", k_condense<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma, nbr,
+              kappa, P, (const int32_t*)rowptr, col, val, diag, rhs);
+  else
+    PH_LAUNCH("condense_f64", k_condense<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma,
+              nbr, kappa, P, (const int32_t*)rowptr, col, val, diag, rhs);
+  return PHFEM_OK;
+}

@@ -1,0 +1,351 @@
+// Library-wide state (error text, profiler) and the device primitives used by the
+// connectivity kernels: a device-wide exclusive scan and a stable LSD radix sort of
+// (uint64 key, int32 value) pairs.  Written for gfx950: wave64 ballots for the in-tile
+// ranking, 256-thread workgroups (4 waves), one 4096-element tile per workgroup.
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ph {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+int dev_flags_to_status(int f) {
+  if (f & DEV_BADNODE) return err(PHFEM_EINVAL, "node index out of range or repeated node in a tet");
+  if (f & DEV_ORIENT) return err(PHFEM_EORIENT, "a face occurs twice with the same orientation or in more than two tets");
+  if (f & DEV_DEGEN) return err(PHFEM_EDEGEN, "zero-volume tet");
+  if (f & DEV_NOFACE) return err(PHFEM_EINVAL, "boundary face is not a face of the mesh");
+  return PHFEM_OK;
+}
+
+int check_params(const phfem_params* p) {
+  if (!p) return err(PHFEM_EINVAL, "params is NULL");
+  if (!(p->c > 0)) return err(PHFEM_ESINGULAR, "reaction coefficient c must be > 0 (kappa K + c M singular)");
+  if (p->quad != PHFEM_QUAD_FACE_CENTROID && p->quad != PHFEM_QUAD_P1_INTERP) return err(PHFEM_EINVAL, "bad quad");
+  if (p->precision != PHFEM_FP64 && p->precision != PHFEM_MIXED) return err(PHFEM_EINVAL, "bad precision");
+  if (p->f_kind < 0 || p->f_kind > PHFEM_FUN_X2Y2Z2_LOAD || p->ud_kind < 0 || p->ud_kind > PHFEM_FUN_X2Y2Z2_LOAD)
+    return err(PHFEM_EINVAL, "bad function kind");
+  return PHFEM_OK;
+}
+
+// ------------------------------------------------------------------ profiler
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+static bool g_prof = false;
+static std::vector<ProfRec> g_recs;
+static std::vector<hipEvent_t> g_pool;
+static size_t g_pool_used = 0;
+static std::mutex g_prof_mu;
+
+static hipEvent_t pool_event() {
+  if (g_pool_used == g_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_pool.push_back(e);
+  }
+  return g_pool[g_pool_used++];
+}
+
+bool profiling() { return g_prof; }
+
+void prof_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfRec r{name, pool_event(), pool_event()};
+  if (r.a) (void)hipEventRecord(r.a, s);
+  g_recs.push_back(r);
+}
+
+void prof_end(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_recs.empty() && g_recs.back().b) (void)hipEventRecord(g_recs.back().b, s);
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int SC_THREADS = 256;
+constexpr int SC_ITEMS = 16;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+// inclusive scan of one value per thread over the 256-thread block; returns the block total
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* lds_waves, uint32_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) lds_waves[w] = v;
+  __syncthreads();
+  uint32_t add = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < SC_THREADS / 64; ++i) {
+    uint32_t t = lds_waves[i];
+    if (i < w) add += t;
+    total += t;
+  }
+  __syncthreads();
+  return v + add;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                            uint32_t* __restrict__ partial) {
+  __shared__ uint32_t lw[SC_THREADS / 64];
+  int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  uint32_t tot;
+  block_inclusive_scan(s, lw, tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// single workgroup: exclusive scan of the tile sums in place
+__global__ __launch_bounds__(SC_THREADS) void k_scan_partials(uint32_t* __restrict__ partial, int64_t nb,
+                                                              uint32_t* __restrict__ total) {
+  __shared__ uint32_t lw[SC_THREADS / 64];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += SC_THREADS) {
+    int64_t idx = base + threadIdx.x;
+    uint32_t v = idx < nb ? partial[idx] : 0;
+    uint32_t tot;
+    uint32_t inc = block_inclusive_scan(v, lw, tot);
+    if (idx < nb) partial[idx] = carry + inc - v;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+// blocked per-thread items: thread t of tile b owns [b*TILE + t*ITEMS, +ITEMS)
+__global__ __launch_bounds__(SC_THREADS) void k_scan_apply(const uint32_t* in, int64_t n,
+                                                           const uint32_t* __restrict__ partial, uint32_t* out) {
+  __shared__ uint32_t lw[SC_THREADS / 64];
+  int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+  uint32_t v[SC_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t inc = block_inclusive_scan(s, lw, tot);
+  uint32_t run = partial[blockIdx.x] + inc - s;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+size_t scan_workspace(int64_t n) {
+  Arena a;
+  a.take<uint32_t>((size_t)((n + SC_TILE - 1) / SC_TILE) + 1);
+  return a.size();
+}
+
+int scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, Arena& ws, hipStream_t s) {
+  int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+  uint32_t* partial = ws.take<uint32_t>((size_t)nb + 1);
+  if (n == 0) return PHFEM_OK;
+  PH_LAUNCH("scan_reduce", k_scan_reduce, (unsigned)nb, SC_THREADS, 0, s, in, n, partial);
+  PH_LAUNCH("scan_partials", k_scan_partials, 1, SC_THREADS, 0, s, partial, nb, total);
+  PH_LAUNCH("scan_apply", k_scan_apply, (unsigned)nb, SC_THREADS, 0, s, in, n, (const uint32_t*)partial, out);
+  return PHFEM_OK;
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int RS_BITS = 8;
+constexpr int RS_RADIX = 1 << RS_BITS;
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+static_assert(RS_RADIX == RS_THREADS, "one digit per thread in the offset pass");
+
+// per-tile digit histogram, digit-major: hist[d * nblocks + b]
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                        uint32_t* __restrict__ hist, int64_t nblocks) {
+  __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < RS_WAVES * RS_RADIX; i += RS_THREADS) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  // wave-contiguous chunks; peers with the same digit aggregate before the LDS atomic
+  int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * 64 * RS_ITEMS;
+#pragma unroll 4
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    int64_t idx = wbase + i * 64 + lane;
+    bool valid = idx < n;
+    uint32_t d = valid ? (uint32_t)((keys[idx] >> shift) & (RS_RADIX - 1)) : 0u;
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RS_BITS; ++b) {
+      uint64_t bb = ballot(valid && ((d >> b) & 1u));
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    if (valid && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&cnt[w][d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  uint32_t s = 0;
+#pragma unroll
+  for (int ww = 0; ww < RS_WAVES; ++ww) s += cnt[ww][threadIdx.x];
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s;
+}
+
+// Stable scatter: element order inside a tile is (wave, item, lane); each wave ranks its
+// items with ballot-based peer masks and a per-wave digit counter in LDS.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                           const int32_t* __restrict__ vin, int64_t n, int shift,
+                                                           const uint32_t* __restrict__ offs, int64_t nblocks,
+                                                           uint64_t* __restrict__ kout, int32_t* __restrict__ vout) {
+  __shared__ uint32_t wh[RS_WAVES][RS_RADIX];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < RS_WAVES * RS_RADIX; i += RS_THREADS) (&wh[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * 64 * RS_ITEMS;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint64_t key[RS_ITEMS];
+  int32_t val[RS_ITEMS];
+  uint32_t rank[RS_ITEMS];
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    int64_t idx = wbase + i * 64 + lane;
+    bool valid = idx < n;
+    key[i] = valid ? kin[idx] : 0ull;
+    val[i] = valid ? (vin ? vin[idx] : (int32_t)idx) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    int64_t idx = wbase + i * 64 + lane;
+    bool valid = idx < n;
+    uint32_t d = (uint32_t)((key[i] >> shift) & (RS_RADIX - 1));
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RS_BITS; ++b) {
+      uint64_t bb = ballot(valid && ((d >> b) & 1u));
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    int leader = valid ? __ffsll((unsigned long long)peers) - 1 : lane;
+    uint32_t base = 0;
+    if (valid && lane == leader) base = atomicAdd(&wh[w][d], (uint32_t)__popcll(peers));
+    base = __shfl(base, leader, 64);
+    rank[i] = base + (uint32_t)__popcll(peers & lt);
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;
+    uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+#pragma unroll
+    for (int ww = 0; ww < RS_WAVES; ++ww) {
+      uint32_t c = wh[ww][d];
+      wh[ww][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    int64_t idx = wbase + i * 64 + lane;
+    if (idx < n) {
+      uint32_t d = (uint32_t)((key[i] >> shift) & (RS_RADIX - 1));
+      uint32_t pos = wh[w][d] + rank[i];
+      kout[pos] = key[i];
+      vout[pos] = val[i];
+    }
+  }
+}
+
+size_t sort_workspace(int64_t n) {
+  int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+  Arena a;
+  a.take<uint32_t>((size_t)(nb * RS_RADIX));
+  size_t s = a.size() + scan_workspace(nb * RS_RADIX);
+  return s;
+}
+
+int radix_sort(uint64_t* keysA, int32_t* valsA, uint64_t* keysB, int32_t* valsB, const int32_t* vals_in, int64_t n,
+               int bits, uint64_t** keys_out, int32_t** vals_out, Arena& ws, hipStream_t s) {
+  if (n >= (int64_t(1) << 32)) return err(PHFEM_EINVAL, "sort size exceeds 2^32");
+  int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+  uint32_t* hist = ws.take<uint32_t>((size_t)(nb * RS_RADIX));
+  size_t mark = ws.off;
+  // input keys in keysA, values in vals_in (identity when null; must not be valsB)
+  uint64_t* kbuf[2] = {keysA, keysB};
+  int32_t* vbuf[2] = {valsA, valsB};
+  int cur = 0;
+  const int32_t* vsrc = vals_in;
+  if (bits <= 0) bits = RS_BITS;  // still run one pass so values are materialised
+  for (int shift = 0; shift < bits; shift += RS_BITS) {
+    ws.off = mark;
+    PH_LAUNCH("rs_hist", k_rs_hist, (unsigned)nb, RS_THREADS, 0, s, (const uint64_t*)kbuf[cur], n, shift, hist, nb);
+    int rc = scan_exclusive(hist, hist, nb * RS_RADIX, nullptr, ws, s);
+    if (rc) return rc;
+    PH_LAUNCH("rs_scatter", k_rs_scatter, (unsigned)nb, RS_THREADS, 0, s, (const uint64_t*)kbuf[cur], vsrc, n,
+              shift, (const uint32_t*)hist, nb, kbuf[cur ^ 1], vbuf[cur ^ 1]);
+    cur ^= 1;
+    vsrc = vbuf[cur];
+  }
+  *keys_out = kbuf[cur];
+  *vals_out = vbuf[cur];
+  return PHFEM_OK;
+}
+
+}  // namespace ph
+
+// ------------------------------------------------------------------ C-ABI: errors, profiler
+extern "C" {
+
+const char* phfem_last_error(void) { return ph::g_error.c_str(); }
+int phfem_abi_version(void) { return 1; }
+
+void phfem_profile_enable(int32_t on) { ph::g_prof = on != 0; }
+
+void phfem_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(ph::g_prof_mu);
+  ph::g_recs.clear();
+  ph::g_pool_used = 0;
+}
+
+int phfem_profile_query(const char* name, int64_t* launches, double* total_ms) {
+  std::lock_guard<std::mutex> lk(ph::g_prof_mu);
+  int64_t n = 0;
+  double ms = 0;
+  for (auto& r : ph::g_recs) {
+    if (std::strcmp(r.name, name) != 0 || !r.a || !r.b) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return ph::err(PHFEM_EHIP, "event sync");
+    float t = 0;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return ph::err(PHFEM_EHIP, "event elapsed");
+    ms += t;
+    ++n;
+  }
+  *launches = n;
+  *total_ms = ms;
+  return PHFEM_OK;
+}
+
+int phfem_profile_names(char* buf, size_t buf_bytes) {
+  std::lock_guard<std::mutex> lk(ph::g_prof_mu);
+  std::vector<std::string> seen;
+  for (auto& r : ph::g_recs) {
+    bool have = false;
+    for (auto& s : seen) have = have || s == r.name;
+    if (!have) seen.push_back(r.name);
+  }
+  std::string out;
+  for (size_t i = 0; i < seen.size(); ++i) out += (i ? "," : "") + seen[i];
+  if (buf_bytes == 0) return PHFEM_EINVAL;
+  std::strncpy(buf, out.c_str(), buf_bytes - 1);
+  buf[buf_bytes - 1] = 0;
+  return PHFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// 12-subtet red refinement on the device (Section 3.4, RedRefine and refineFaces).
+//
+// The paper numbers the new nodes by a coordinate-keyed stable unique over
+// (tet; centroid, IJ, IK, IL, JK, JL, KL).  Every tet contributes its centroid and the
+// midpoints of the edges that first appear in it, so that order has a closed form given
+// the NumEdges outputs (first-appearance edge numbering, first tet of every edge, prefix
+// count of edges first seen before every tet):
+//     centroid(t) = nC + t + prefix(t),     midpoint(e) = nC + first_tet(e) + e + 1.
+// Each tet writes its own new nodes (a contiguous id range) and its 12 children, so the
+// kernel needs no sort and no comparison of floating-point coordinates.
+#include "common.hpp"
+
+namespace ph {
+
+constexpr int RT = 256;
+
+__device__ int g_face_flag;
+
+__global__ __launch_bounds__(RT) void k_copy_coords(int64_t nC, const double* __restrict__ X, int64_t nCo,
+                                                    double* __restrict__ Xo) {
+  int64_t v = (int64_t)blockIdx.x * RT + threadIdx.x;
+  if (v >= nC) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) Xo[d * nCo + v] = X[d * nC + v];
+}
+
+__global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                               const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
+                                               const int32_t* __restrict__ eft, const int32_t* __restrict__ pre,
+                                               int64_t nCo, double* __restrict__ Xo, int32_t* __restrict__ To) {
+  int64_t t = (int64_t)blockIdx.x * RT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], e[6], m[6];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+  const int C = (int)(nC + t + pre[t]);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    e[j] = t2e[j * nE + t];
+    int ft = eft[e[j]];
+    m[j] = (int)(nC + ft + e[j] + 1);
+    e[j] = (ft == t) ? 1 : 0;  // reuse: does the edge first appear in this tet?
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double x0 = X[d * nC + v[0]], x1 = X[d * nC + v[1]], x2 = X[d * nC + v[2]], x3 = X[d * nC + v[3]];
+    Xo[d * nCo + C] = (((x0 + x1) + x2) + x3) / 4.0;
+    const double xs[4] = {x0, x1, x2, x3};
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (e[j]) Xo[d * nCo + m[j]] = (xs[ev0(j)] + xs[ev1(j)]) / 2.0;
+  }
+  // children (RedRefine's vertex lists; m0..m5 = midpoints of IJ IK IL JK JL KL)
+  const int I = v[0], J = v[1], K = v[2], L = v[3];
+  const int ch[12][4] = {{I, m[0], m[1], m[2]},    {J, m[3], m[0], m[4]},    {K, m[1], m[3], m[5]},
+                         {L, m[5], m[4], m[2]},    {m[0], m[1], m[2], C},    {m[3], m[0], m[4], C},
+                         {m[1], m[3], m[5], C},    {m[5], m[4], m[2], C},    {m[0], m[3], m[1], C},
+                         {m[1], m[5], m[2], C},    {m[0], m[2], m[4], C},    {m[5], m[3], m[4], C}};
+  const int64_t nEo = 12 * nE;
+  const int64_t r1 = nE + 11 * t;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    To[i * nEo + t] = ch[0][i];
+#pragma unroll
+    for (int c = 1; c < 12; ++c) To[i * nEo + r1 + (c - 1)] = ch[c][i];
+  }
+}
+
+// edge id of the node pair (a, b) from the Nodes2Edge CSR (row min(a,b), column max(a,b))
+__device__ __forceinline__ int n2e_lookup(int a, int b, int64_t nC, const int32_t* __restrict__ rp,
+                                          const int32_t* __restrict__ col, const int32_t* __restrict__ eid) {
+  int lo = a < b ? a : b, hi = a < b ? b : a;
+  if (lo < 0 || hi >= nC) return -1;
+  for (int q = rp[lo]; q < rp[lo + 1]; ++q)
+    if (col[q] == hi) return eid[q];
+  return -1;
+}
+
+__global__ __launch_bounds__(RT) void k_refine_faces(int64_t n, const int32_t* __restrict__ F, int64_t nC,
+                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ eid, const int32_t* __restrict__ eft,
+                                                     int32_t* __restrict__ Fo, int* __restrict__ flags) {
+  int64_t f = (int64_t)blockIdx.x * RT + threadIdx.x;
+  if (f >= n) return;
+  int n1 = F[f], n2 = F[n + f], n3 = F[2 * n + f];
+  int e12 = n2e_lookup(n1, n2, nC, rp, col, eid), e23 = n2e_lookup(n2, n3, nC, rp, col, eid),
+      e13 = n2e_lookup(n1, n3, nC, rp, col, eid);
+  if (e12 < 0 || e23 < 0 || e13 < 0) {
+    atomicOr(flags, DEV_NOFACE);
+    return;
+  }
+  int m12 = (int)(nC + eft[e12] + e12 + 1), m23 = (int)(nC + eft[e23] + e23 + 1), m13 = (int)(nC + eft[e13] + e13 + 1);
+  const int rows[4][3] = {{n1, m12, m13}, {n2, m23, m12}, {n3, m13, m23}, {m12, m23, m13}};
+  const int64_t n4 = 4 * n;
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) {
+    Fo[mm * n4 + f] = rows[0][mm];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) Fo[mm * n4 + n + 3 * f + (c - 1)] = rows[c][mm];
+  }
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
+                            const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
+                            const int32_t* n2e_rowptr, const int32_t* n2e_col, const int32_t* n2e_edge, int64_t nDb,
+                            const int32_t* db, int64_t nNb, const int32_t* nb, double* coord_out, int32_t* tetra_out,
+                            int32_t* db_out, int32_t* nb_out, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  if (nC <= 0 || nE <= 0 || nEd <= 0 || nDb < 0 || nNb < 0) return err(PHFEM_EINVAL, "bad sizes");
+  const int64_t nCo = nC + nEd + nE;
+  if (12 * nE >= (int64_t(1) << 31) || nCo >= (int64_t(1) << 31)) return err(PHFEM_EINVAL, "refined mesh exceeds int32");
+  if (!coord || !tetra || !tet2edge || !edge_first_tet || !tet_edge_prefix || !coord_out || !tetra_out)
+    return err(PHFEM_EINVAL, "null argument");
+  const bool faces = nDb + nNb > 0;
+  if (faces && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "boundary faces need Nodes2Edge");
+  if ((nDb > 0 && (!db || !db_out)) || (nNb > 0 && (!nb || !nb_out))) return err(PHFEM_EINVAL, "null face list");
+  PH_LAUNCH("copy_coords", k_copy_coords, grid_for(nC, RT), RT, 0, s, nC, coord, nCo, coord_out);
+  PH_LAUNCH("refine", k_refine, grid_for(nE, RT), RT, 0, s, nC, coord, nE, tetra, tet2edge, edge_first_tet,
+            tet_edge_prefix, nCo, coord_out, tetra_out);
+  if (!faces) return PHFEM_OK;
+  // error flag of the face lookups: a 4-byte device global (calls on one device that
+  // overlap in time share it)
+  int* dflag = nullptr;
+  PH_HIP(hipGetSymbolAddress((void**)&dflag, HIP_SYMBOL(g_face_flag)));
+  const int zero = 0;
+  PH_HIP(hipMemcpyAsync(dflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  if (nDb > 0)
+    PH_LAUNCH("refine_faces", k_refine_faces, grid_for(nDb, RT), RT, 0, s, nDb, db, nC, n2e_rowptr, n2e_col,
+              n2e_edge, edge_first_tet, db_out, dflag);
+  if (nNb > 0)
+    PH_LAUNCH("refine_faces", k_refine_faces, grid_for(nNb, RT), RT, 0, s, nNb, nb, nC, n2e_rowptr, n2e_col,
+              n2e_edge, edge_first_tet, nb_out, dflag);
+  int h = 0;
+  PH_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  if (h) return dev_flags_to_status(h);
+  return PHFEM_OK;
+}

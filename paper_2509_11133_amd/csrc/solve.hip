@@ -1,0 +1,476 @@
+// Face-system solve (Jacobi-PCG; the paper uses a sparse direct solve, Listing 8), the
+// mixed-precision iterative refinement, recovery (Algorithm 1) and the adjoint driver.
+//
+// PCG scalars never leave the device: every block of a consumer kernel re-sums the fixed
+// array of per-block partial dot products in a fixed order, so alpha and beta are
+// bitwise identical across blocks and runs.  The host reads one residual norm every
+// CHECK iterations.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace ph {
+
+int launch_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f,
+                   const int8_t* sigma, const double* kappa, const DevParams& P, const double* lambda,
+                   const double* gsrc, double* U, double* res, int* flags, hipStream_t s);
+int launch_face_init(int64_t nF, int64_t nC, const double* X, const int32_t* faces, const int32_t* face2tet,
+                     const DevParams& P, uint32_t* cnt, double* diag, double* rhs, hipStream_t s);
+int launch_vjp(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f, const int8_t* sigma,
+               const int32_t* nbr, const double* kappa, const DevParams& P, const double* U, const double* Pp,
+               const double* lambda, const double* Q, double* dlogk, double* dX, hipStream_t s);
+
+constexpr int ST = 256;
+constexpr int MAXG = 1024;
+constexpr int CHECK = 16;
+
+static unsigned pcg_grid(int64_t n) {
+  int64_t g = (n + ST - 1) / ST;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, MAXG));
+}
+
+// block-wide sum of one double per thread, fixed order; result valid in all threads
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int G, double* lds) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < G; i += ST) v += part[i];
+  return block_sum(v, lds);
+}
+
+template <class T>
+__global__ __launch_bounds__(ST) void k_spmv_dot(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                 const T* __restrict__ diag, const T* __restrict__ x,
+                                                 T* __restrict__ y, double* __restrict__ part) {
+  __shared__ double lds[ST / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    T s = diag[i] * x[i];
+    const int q1 = rowptr[i + 1];
+    for (int q = rowptr[i]; q < q1; ++q) s += val[q] * x[col[q]];
+    y[i] = s;
+    acc += (double)x[i] * (double)s;
+  }
+  double b = block_sum(acc, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+template <class T>
+__global__ __launch_bounds__(ST) void k_pcg_init(int64_t n, const T* __restrict__ b, const T* __restrict__ diag,
+                                                 T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                                 T* __restrict__ p, double* __restrict__ part_rz,
+                                                 double* __restrict__ part_rr) {
+  __shared__ double lds[ST / 64];
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    T ri = b[i];
+    T zi = ri / diag[i];
+    x[i] = (T)0;
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    arz += (double)ri * (double)zi;
+    arr += (double)ri * (double)ri;
+  }
+  double s1 = block_sum(arz, lds);
+  double s2 = block_sum(arr, lds);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = s1;
+    part_rr[blockIdx.x] = s2;
+  }
+}
+
+// scal[slot] = sum part_rz, scal[2] = sum part_rr (single block)
+__global__ __launch_bounds__(ST) void k_scalars(int G, const double* __restrict__ part_rz,
+                                                const double* __restrict__ part_rr, double* __restrict__ scal,
+                                                int slot) {
+  __shared__ double lds[ST / 64];
+  double a = sum_partials(part_rz, G, lds);
+  double b = sum_partials(part_rr, G, lds);
+  if (threadIdx.x == 0) {
+    scal[slot] = a;
+    scal[2] = b;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(ST) void k_pcg_update(int64_t n, int G, const double* __restrict__ part_pq,
+                                                   const double* __restrict__ scal, int slot, T* __restrict__ x,
+                                                   T* __restrict__ r, const T* __restrict__ p,
+                                                   const T* __restrict__ q, const T* __restrict__ diag,
+                                                   T* __restrict__ z, double* __restrict__ part_rz,
+                                                   double* __restrict__ part_rr) {
+  __shared__ double lds[ST / 64];
+  const double pq = sum_partials(part_pq, G, lds);
+  const double rz = scal[slot];
+  const T alpha = (T)(rz / pq);
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    x[i] += alpha * p[i];
+    T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    T zi = ri / diag[i];
+    z[i] = zi;
+    arz += (double)ri * (double)zi;
+    arr += (double)ri * (double)ri;
+  }
+  double s1 = block_sum(arz, lds);
+  double s2 = block_sum(arr, lds);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = s1;
+    part_rr[blockIdx.x] = s2;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(ST) void k_pcg_dir(int64_t n, int G, const double* __restrict__ part_rz,
+                                                const double* __restrict__ part_rr, double* __restrict__ scal,
+                                                int slot_old, const T* __restrict__ z, T* __restrict__ p) {
+  __shared__ double lds[ST / 64];
+  const double rzn = sum_partials(part_rz, G, lds);
+  const double rr = sum_partials(part_rr, G, lds);
+  const T beta = (T)(rzn / scal[slot_old]);
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) p[i] = z[i] + beta * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[slot_old ^ 1] = rzn;
+    scal[2] = rr;
+  }
+}
+
+__global__ __launch_bounds__(ST) void k_norm2(int64_t n, const double* __restrict__ v, double* __restrict__ part) {
+  __shared__ double lds[ST / 64];
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) a += v[i] * v[i];
+  double s = block_sum(a, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(ST) void k_sum1(int G, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double lds[ST / 64];
+  double a = sum_partials(part, G, lds);
+  if (threadIdx.x == 0) *out = a;
+}
+
+__global__ __launch_bounds__(ST) void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) b[i] = (float)a[i];
+}
+
+__global__ __launch_bounds__(ST) void k_add_f32(int64_t n, const float* __restrict__ d, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) x[i] += (double)d[i];
+}
+
+__global__ __launch_bounds__(ST) void k_fill0(int64_t n, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) x[i] = 0.0;
+}
+
+// ---------------------------------------------------------------- workspace
+struct PcgWS {
+  void *r, *z, *p, *q;
+  double *part_pq, *part_rz, *part_rr, *scal;
+};
+
+template <class T>
+static void pcg_layout(Arena& a, int64_t n, PcgWS& w) {
+  w.r = a.take<T>(n);
+  w.z = a.take<T>(n);
+  w.p = a.take<T>(n);
+  w.q = a.take<T>(n);
+  w.part_pq = a.take<double>(MAXG);
+  w.part_rz = a.take<double>(MAXG);
+  w.part_rr = a.take<double>(MAXG);
+  w.scal = a.take<double>(8);
+}
+
+struct SolveWS {
+  PcgWS pcg;
+  double *bD, *r64;
+  float *val32, *diag32, *b32, *x32;
+  int* flags;
+};
+
+static void solve_layout(Arena& a, int64_t nF, int32_t mode, SolveWS& w) {
+  if (mode == PHFEM_SOLVE_FP32_PCG_FP64_IR)
+    pcg_layout<float>(a, nF, w.pcg);
+  else
+    pcg_layout<double>(a, nF, w.pcg);
+  w.bD = a.take<double>(nF);
+  w.r64 = a.take<double>(nF);
+  if (mode == PHFEM_SOLVE_FP32_PCG_FP64_IR) {
+    w.val32 = a.take<float>(6 * nF);
+    w.diag32 = a.take<float>(nF);
+    w.b32 = a.take<float>(nF);
+    w.x32 = a.take<float>(nF);
+  } else {
+    w.val32 = w.diag32 = w.b32 = w.x32 = nullptr;
+  }
+  w.flags = a.take<int>(16);
+}
+
+static int read_scalar(const double* d, double* h, hipStream_t s) {
+  PH_HIP(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  return PHFEM_OK;
+}
+
+static int norm2(int64_t n, const double* v, PcgWS& w, double* out, hipStream_t s) {
+  unsigned G = pcg_grid(n);
+  PH_LAUNCH("norm2", k_norm2, G, ST, 0, s, n, v, w.part_pq);
+  PH_LAUNCH("sum1", k_sum1, 1, ST, 0, s, (int)G, (const double*)w.part_pq, w.scal + 4);
+  double h = 0;
+  int rc = read_scalar(w.scal + 4, &h, s);
+  *out = std::sqrt(h);
+  return rc;
+}
+
+// PCG on (rowptr, col, val, diag) from x0 = 0; stops at ||r|| <= tol ||b|| or maxit.
+template <class T>
+static int pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* diag, const T* b, T* x,
+               double tol, int maxit, PcgWS& w, int* iters, double* relres, hipStream_t s) {
+  const unsigned G = pcg_grid(n);
+  T *r = (T*)w.r, *z = (T*)w.z, *p = (T*)w.p, *q = (T*)w.q;
+  PH_LAUNCH("pcg_init", k_pcg_init<T>, G, ST, 0, s, n, b, diag, x, r, z, p, w.part_rz, w.part_rr);
+  PH_LAUNCH("pcg_scalars", k_scalars, 1, ST, 0, s, (int)G, (const double*)w.part_rz, (const double*)w.part_rr, w.scal,
+            0);
+  double rr0 = 0;
+  int rc = read_scalar(w.scal + 2, &rr0, s);
+  if (rc) return rc;
+  const double bn = std::sqrt(rr0);
+  *iters = 0;
+  *relres = 0;
+  if (bn == 0) return PHFEM_OK;
+  int slot = 0, it = 0;
+  double rel = 1.0;
+  while (it < maxit) {
+    PH_LAUNCH("spmv_dot", k_spmv_dot<T>, G, ST, 0, s, n, rowptr, col, val, diag, (const T*)p, q, w.part_pq);
+    PH_LAUNCH("pcg_update", k_pcg_update<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
+              slot, x, r, (const T*)p, (const T*)q, diag, z, w.part_rz, w.part_rr);
+    PH_LAUNCH("pcg_dir", k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz, (const double*)w.part_rr,
+              w.scal, slot, (const T*)z, p);
+    slot ^= 1;
+    ++it;
+    if (it % CHECK == 0 || it == maxit) {
+      double rr = 0;
+      rc = read_scalar(w.scal + 2, &rr, s);
+      if (rc) return rc;
+      rel = std::sqrt(rr) / bn;
+      if (!(rel > tol)) break;  // also stops on NaN
+    }
+  }
+  *iters = it;
+  *relres = rel;
+  return PHFEM_OK;
+}
+
+// Mesh-side data of the matrix-free FP64 operator b_D - C A^-1 (Bsrc + C'lambda).
+struct MeshOp {
+  int64_t nC, nE, nF;
+  const double* X;
+  const int32_t* tet;
+  const int32_t* t2f;
+  const int8_t* sigma;
+  const double* kappa;
+  DevParams P;
+  const double* gsrc;  // null: load vector of f
+  const double* bD;    // null: zero
+};
+
+static int residual(const MeshOp& m, const double* lambda, double* U, double* r64, int* flags, hipStream_t s) {
+  if (m.bD)
+    PH_HIP(hipMemcpyAsync(r64, m.bD, sizeof(double) * m.nF, hipMemcpyDeviceToDevice, s));
+  else
+    PH_LAUNCH("fill0", k_fill0, pcg_grid(m.nF), ST, 0, s, m.nF, r64);
+  return launch_recover(m.nC, m.X, m.nE, m.tet, m.t2f, m.sigma, m.kappa, m.P, lambda, m.gsrc, U, r64, flags, s);
+}
+
+static int check_flags(int* dflags, hipStream_t s) {
+  int h = 0;
+  PH_HIP(hipMemcpyAsync(&h, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  return h ? dev_flags_to_status(h) : PHFEM_OK;
+}
+
+// Solve S+ x = r+ (FP64 PCG on the stored system) or by FP64 iterative refinement with
+// FP32 PCG corrections; U = A^-1 (Bsrc + C'x) in FP64 on exit; stats filled.
+static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col, const double* val,
+                      const double* diag, const double* rhs, int32_t mode, double tol, double inner_tol, int maxit,
+                      SolveWS& w, double* x, double* U, phfem_solve_stats* st, hipStream_t s) {
+  const int64_t nF = m.nF;
+  PH_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+  int rc;
+  phfem_solve_stats loc = {0, 0, 0.0, 0.0};
+  if (mode == PHFEM_SOLVE_FP64_PCG) {
+    double rel = 0;
+    int it = 0;
+    rc = pcg<double>(nF, rowptr, col, val, diag, rhs, x, tol, maxit, w.pcg, &it, &rel, s);
+    if (rc) return rc;
+    loc.iters = it;
+    // true residual in FP64, matrix-free; also writes U
+    rc = residual(m, x, U, w.r64, w.flags, s);
+    if (rc) return rc;
+    rc = check_flags(w.flags, s);
+    if (rc) return rc;
+    double rn = 0, bn = 0;
+    rc = norm2(nF, w.r64, w.pcg, &rn, s);
+    if (rc) return rc;
+    if (rhs) {
+      rc = norm2(nF, rhs, w.pcg, &bn, s);
+      if (rc) return rc;
+    }
+    loc.rhs_norm = bn;
+    loc.rel_res = bn > 0 ? rn / bn : rn;
+    *st = loc;
+    if (!(loc.rel_res <= std::max(tol, 1e-15) * 10) && it >= maxit)
+      return err(PHFEM_ENOCONV, "PCG reached max_iter above tolerance");
+    return PHFEM_OK;
+  }
+  // mixed: FP32 copy of the system (nnz = rowptr[nF] off-diagonals)
+  {
+    int32_t nnz = 0;
+    PH_HIP(hipMemcpyAsync(&nnz, rowptr + nF, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (nnz < 0 || nnz > 6 * nF) return err(PHFEM_EINVAL, "row pointer inconsistent with nF");
+    PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nnz), ST, 0, s, (int64_t)nnz, val, w.val32);
+    PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, diag, w.diag32);
+  }
+  PH_LAUNCH("fill0", k_fill0, pcg_grid(nF), ST, 0, s, nF, x);
+  double r0 = 0;
+  int total_it = 0, steps = 0;
+  for (;;) {
+    rc = residual(m, x, U, w.r64, w.flags, s);
+    if (rc) return rc;
+    double rn = 0;
+    rc = norm2(nF, w.r64, w.pcg, &rn, s);
+    if (rc) return rc;
+    if (steps == 0) {
+      rc = check_flags(w.flags, s);
+      if (rc) return rc;
+      r0 = rn;
+    }
+    loc.rel_res = r0 > 0 ? rn / r0 : 0.0;
+    loc.rhs_norm = r0;
+    if (!(loc.rel_res > tol) || r0 == 0) break;
+    if (total_it >= maxit || steps >= 60) {
+      loc.iters = total_it;
+      loc.ir_steps = steps;
+      *st = loc;
+      return err(PHFEM_ENOCONV, "iterative refinement stopped above tolerance");
+    }
+    PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, (const double*)w.r64, w.b32);
+    int it = 0;
+    double rel = 0;
+    rc = pcg<float>(nF, rowptr, col, w.val32, w.diag32, w.b32, w.x32, inner_tol, maxit - total_it, w.pcg, &it, &rel,
+                    s);
+    if (rc) return rc;
+    total_it += it;
+    PH_LAUNCH("add_f32", k_add_f32, pcg_grid(nF), ST, 0, s, nF, (const float*)w.x32, x);
+    ++steps;
+  }
+  loc.iters = total_it;
+  loc.ir_steps = steps;
+  *st = loc;
+  return PHFEM_OK;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode) {
+  (void)nE;
+  Arena a;
+  SolveWS w;
+  solve_layout(a, nF, mode, w);
+  return a.size();
+}
+
+static int solve_args_ok(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                         const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
+                         const int32_t* rowptr, const int32_t* col, const double* val, const double* diag,
+                         int32_t mode, double tol, int32_t max_iter) {
+  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !face2tet || !rowptr ||
+      !col || !val || !diag)
+    return err(PHFEM_EINVAL, "bad solve arguments");
+  if (mode != PHFEM_SOLVE_FP64_PCG && mode != PHFEM_SOLVE_FP32_PCG_FP64_IR) return err(PHFEM_EINVAL, "bad mode");
+  if (!(tol >= 0) || max_iter <= 0) return err(PHFEM_EINVAL, "bad tolerance or max_iter");
+  return PHFEM_OK;
+}
+
+extern "C" int phfem_solve(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                           const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
+                           const double* kappa, const phfem_params* p, const int32_t* rowptr, const int32_t* col,
+                           const double* val, const double* diag, const double* rhs, int32_t mode, double tol,
+                           double inner_tol, int32_t max_iter, void* work, size_t work_bytes, double* lambda,
+                           double* U, phfem_solve_stats* stats, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  int rc = check_params(p);
+  if (rc) return rc;
+  rc = solve_args_ok(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, rowptr, col, val, diag, mode, tol,
+                     max_iter);
+  if (rc) return rc;
+  if (!rhs || !lambda || !U || !stats) return err(PHFEM_EINVAL, "null rhs/lambda/U/stats");
+  if (!work || work_bytes < phfem_solve_workspace(nE, nF, mode)) return err(PHFEM_EWORKSPACE, "solve workspace too small");
+  Arena a(work, work_bytes);
+  SolveWS w;
+  solve_layout(a, nF, mode, w);
+  MeshOp m{nC, nE, nF, coord, tetra, tet2face, sigma, kappa, to_dev(*p), nullptr, w.bD};
+  rc = launch_face_init(nF, nC, coord, faces, face2tet, m.P, nullptr, nullptr, w.bD, s);
+  if (rc) return rc;
+  if (!(inner_tol > 0)) inner_tol = 1e-4;
+  return face_solve(m, rowptr, col, val, diag, rhs, mode, tol, inner_tol, max_iter, w, lambda, U, stats, s);
+}
+
+extern "C" size_t phfem_grad_workspace(int64_t nE, int64_t nF, int32_t mode) {
+  Arena a;
+  a.take<double>(nF);      // adjoint rhs
+  a.take<double>(nF);      // Q
+  a.take<double>(4 * nE);  // P
+  return a.size() + phfem_solve_workspace(nE, nF, mode);
+}
+
+extern "C" int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                          const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
+                          const int32_t* nbr, const double* kappa, const phfem_params* p, const int32_t* rowptr,
+                          const int32_t* col, const double* val, const double* diag, const double* U,
+                          const double* lambda, const double* dJdU, int32_t mode, double tol, double inner_tol,
+                          int32_t max_iter, void* work, size_t work_bytes, double* dJ_dlogkappa, double* dJ_dcoord,
+                          phfem_solve_stats* stats, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  int rc = check_params(p);
+  if (rc) return rc;
+  rc = solve_args_ok(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, rowptr, col, val, diag, mode, tol,
+                     max_iter);
+  if (rc) return rc;
+  if (!nbr || !U || !lambda || !dJdU || !stats) return err(PHFEM_EINVAL, "null nbr/U/lambda/dJdU/stats");
+  if (!work || work_bytes < phfem_grad_workspace(nE, nF, mode)) return err(PHFEM_EWORKSPACE, "grad workspace too small");
+  Arena a(work, work_bytes);
+  double* radj = a.take<double>(nF);
+  double* Q = a.take<double>(nF);
+  double* Pv = a.take<double>(4 * nE);
+  SolveWS w;
+  solve_layout(a, nF, mode, w);
+  DevParams P = to_dev(*p);
+  PH_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+  // adjoint right-hand side -C A^-1 dJdU (recovery with lambda = 0 and the load replaced by dJdU)
+  PH_LAUNCH("fill0", k_fill0, pcg_grid(nF), ST, 0, s, nF, radj);
+  rc = launch_recover(nC, coord, nE, tetra, tet2face, sigma, kappa, P, nullptr, dJdU, Pv, radj, w.flags, s);
+  if (rc) return rc;
+  MeshOp m{nC, nE, nF, coord, tetra, tet2face, sigma, kappa, P, dJdU, nullptr};
+  if (!(inner_tol > 0)) inner_tol = 1e-4;
+  rc = face_solve(m, rowptr, col, val, diag, radj, mode, tol, inner_tol, max_iter, w, Q, Pv, stats, s);
+  if (rc) return rc;  // Pv = A^-1 (dJdU + C'Q) on exit
+  if (dJ_dcoord) PH_HIP(hipMemsetAsync(dJ_dcoord, 0, sizeof(double) * 3 * nC, s));
+  return launch_vjp(nC, coord, nE, tetra, tet2face, sigma, nbr, kappa, P, U, Pv, lambda, Q, dJ_dlogkappa, dJ_dcoord, s);
+}

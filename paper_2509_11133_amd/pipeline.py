@@ -1,0 +1,159 @@
+"""Convenience layer over the C-ABI: allocates outputs and workspaces as torch tensors on
+the mesh's device and calls the library.  No arithmetic of the method happens here.
+
+Mesh arrays: coord float64 (3, nC), tetra int32 (4, nE), boundary face lists int32 (3, n),
+all contiguous on a HIP device.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _binding as B
+from ._binding import (CONNECT_EDGES, CONNECT_FACES, CONNECT_NODES2EDGE, ENOCONV, FP64, MIXED, OK,
+                       SOLVE_FP32_PCG_FP64_IR, SOLVE_FP64_PCG, PhfemError, SolveStats, params)
+
+I32, F64 = torch.int32, torch.float64
+
+
+def connect(tetra, nC, faces=True, n2e=False):
+    """Edges (+ Nodes2Edge CSR) and, with faces=True, the face numbering (a1-a3)."""
+    dev = tetra.device
+    nE = tetra.shape[1]
+    flags = CONNECT_EDGES | (CONNECT_FACES if faces else 0) | (CONNECT_NODES2EDGE if n2e else 0)
+    work = B.workspace(B.lib().phfem_connect_workspace(nC, nE, flags), dev)
+    e = torch.empty(12 * nE, dtype=I32, device=dev)
+    t2e = torch.empty((6, nE), dtype=I32, device=dev)
+    eft = torch.empty(6 * nE, dtype=I32, device=dev)
+    pre = torch.empty(nE, dtype=I32, device=dev)
+    rp = torch.empty(nC + 1, dtype=I32, device=dev) if n2e else None
+    nc = torch.empty(6 * nE, dtype=I32, device=dev) if n2e else None
+    ne = torch.empty(6 * nE, dtype=I32, device=dev) if n2e else None
+    fa = torch.empty(12 * nE, dtype=I32, device=dev) if faces else None
+    t2f = torch.empty((4, nE), dtype=I32, device=dev) if faces else None
+    sig = torch.empty((4, nE), dtype=torch.int8, device=dev) if faces else None
+    f2t = torch.empty(8 * nE, dtype=I32, device=dev) if faces else None
+    nbr = torch.empty((4, nE), dtype=I32, device=dev) if faces else None
+    counts = np.zeros(3, np.int64)
+    B.phfem_connect(nC, nE, tetra, flags, work, e, t2e, eft, pre, rp, nc, ne, fa, t2f, sig, f2t, nbr, counts)
+    nEd, nF, nB = (int(v) for v in counts)
+    out = dict(nC=nC, nE=nE, nEd=nEd, edges=e[: 2 * nEd].view(2, nEd), tet2edge=t2e, edge_first_tet=eft[:nEd],
+               tet_edge_prefix=pre)
+    if n2e:
+        out.update(n2e_rowptr=rp, n2e_col=nc[:nEd], n2e_edge=ne[:nEd])
+    if faces:
+        out.update(nF=nF, nB=nB, faces=fa[: 3 * nF].view(3, nF), tet2face=t2f, sigma=sig,
+                   face2tet=f2t[: 2 * nF].view(2, nF), nbr=nbr)
+    return out
+
+
+def refine(coord, tetra, conn, db=None, nb=None):
+    """One level of the 12-subtet refinement (a4).  Needs connect(..., n2e=True) when
+    boundary face lists are given.  Returns (coord, tetra, db, nb)."""
+    dev = coord.device
+    nC, nE, nEd = coord.shape[1], tetra.shape[1], conn["nEd"]
+    nCo = nC + nEd + nE
+    Xo = torch.empty((3, nCo), dtype=F64, device=dev)
+    To = torch.empty((4, 12 * nE), dtype=I32, device=dev)
+    nDb = 0 if db is None else db.shape[1]
+    nNb = 0 if nb is None else nb.shape[1]
+    dbo = torch.empty((3, 4 * nDb), dtype=I32, device=dev) if nDb else None
+    nbo = torch.empty((3, 4 * nNb), dtype=I32, device=dev) if nNb else None
+    B.phfem_refine(nC, coord, nE, tetra, nEd, conn["tet2edge"], conn["edge_first_tet"], conn["tet_edge_prefix"],
+                   conn.get("n2e_rowptr"), conn.get("n2e_col"), conn.get("n2e_edge"), nDb, db if nDb else None, nNb,
+                   nb if nNb else None, Xo, To, dbo, nbo)
+    return Xo, To, dbo, nbo
+
+
+def assemble(coord, tetra, sigma, kappa, prm):
+    """Per-tet blocks: vol, kappa K (16), sigma|F| (4), B (4), S (16), r (4)."""
+    dev = coord.device
+    nC, nE = coord.shape[1], tetra.shape[1]
+    out = dict(vol=torch.empty(nE, dtype=F64, device=dev), K=torch.empty((16, nE), dtype=F64, device=dev),
+               d=torch.empty((4, nE), dtype=F64, device=dev), B=torch.empty((4, nE), dtype=F64, device=dev),
+               S=torch.empty((16, nE), dtype=F64, device=dev), r=torch.empty((4, nE), dtype=F64, device=dev))
+    B.phfem_assemble(nC, coord, nE, tetra, sigma, kappa, prm, out["vol"], out["K"], out["d"], out["B"], out["S"],
+                     out["r"])
+    return out
+
+
+def condense(coord, tetra, conn, kappa, prm):
+    """Condensed face system (a5-a7): diag, off-diagonal CSR (rowptr, col, val), rhs."""
+    dev = coord.device
+    nC, nE, nF, nB = coord.shape[1], tetra.shape[1], conn["nF"], conn["nB"]
+    work = B.workspace(B.lib().phfem_condense_workspace(nF), dev)
+    nnz = 6 * nF - 3 * nB
+    rowptr = torch.empty(nF + 1, dtype=I32, device=dev)
+    col = torch.empty(max(nnz, 1), dtype=I32, device=dev)
+    val = torch.empty(max(nnz, 1), dtype=F64, device=dev)
+    diag = torch.empty(nF, dtype=F64, device=dev)
+    rhs = torch.empty(nF, dtype=F64, device=dev)
+    B.phfem_condense(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"], conn["nbr"],
+                     conn["face2tet"], kappa, prm, work, rowptr, col, val, diag, rhs)
+    return dict(rowptr=rowptr, col=col[:nnz], val=val[:nnz], diag=diag, rhs=rhs, nnz=nnz)
+
+
+def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=1e-4, max_iter=200000,
+          allow_noconv=False):
+    """Face solve + recovery (a8-a9).  Returns (lambda, U, stats)."""
+    dev = coord.device
+    nC, nE, nF = coord.shape[1], tetra.shape[1], conn["nF"]
+    work = B.workspace(B.lib().phfem_solve_workspace(nE, nF, mode), dev)
+    lam = torch.empty(nF, dtype=F64, device=dev)
+    U = torch.empty((4, nE), dtype=F64, device=dev)
+    st = SolveStats()
+    rc = B.phfem_solve(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"], conn["face2tet"],
+                       kappa, prm, sysm["rowptr"], sysm["col"], sysm["val"], sysm["diag"], sysm["rhs"], mode, tol,
+                       inner_tol, max_iter, work, lam, U, st, check=False)
+    stats = st.as_dict()
+    stats["converged"] = rc == OK
+    if rc != OK and not (rc == ENOCONV and allow_noconv):
+        raise PhfemError(rc, B.lib().phfem_last_error().decode())
+    return lam, U, stats
+
+
+def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=1e-4,
+         max_iter=200000, want_coord=True):
+    """Adjoint gradient (a10): (dJ/dlog kappa [nE], dJ/dX [3, nC], stats)."""
+    dev = coord.device
+    nC, nE, nF = coord.shape[1], tetra.shape[1], conn["nF"]
+    work = B.workspace(B.lib().phfem_grad_workspace(nE, nF, mode), dev)
+    dlogk = torch.empty(nE, dtype=F64, device=dev)
+    dX = torch.empty((3, nC), dtype=F64, device=dev) if want_coord else None
+    st = SolveStats()
+    B.phfem_grad(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"], conn["face2tet"],
+                 conn["nbr"], kappa, prm, sysm["rowptr"], sysm["col"], sysm["val"], sysm["diag"], U, lam,
+                 dJdU.contiguous(), mode, tol, inner_tol, max_iter, work, dlogk, dX, st)
+    return dlogk, dX, st.as_dict()
+
+
+def refine_levels(coord, tetra, levels, db=None):
+    """Pipeline of the paper's uniform refinement: [connect edges -> refine] per level."""
+    for _ in range(levels):
+        conn = connect(tetra, coord.shape[1], faces=False, n2e=db is not None)
+        coord, tetra, db, _ = refine(coord, tetra, conn, db)
+    return coord, tetra, db
+
+
+class PrimalHybridSolve(torch.autograd.Function):
+    """U = solution of the primal hybrid system for per-tet log-diffusivity and vertex
+    coordinates; backward = one adjoint face solve + per-tet VJP kernels (phfem_grad).
+    Mesh connectivity (from connect) and params are fixed inputs."""
+
+    @staticmethod
+    def forward(ctx, log_kappa, coord, tetra, conn, prm, mode, tol):
+        kappa = torch.exp(log_kappa.detach()).contiguous()
+        X = coord.detach().contiguous()
+        sysm = condense(X, tetra, conn, kappa, prm)
+        lam, U, st = solve(X, tetra, conn, sysm, kappa, prm, mode=mode, tol=tol)
+        ctx.save_for_backward(X, kappa, U, lam)
+        ctx.tetra, ctx.conn, ctx.prm, ctx.mode, ctx.tol, ctx.sysm = tetra, conn, prm, mode, tol, sysm
+        ctx.need_X = coord.requires_grad
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        X, kappa, U, lam = ctx.saved_tensors
+        dlogk, dX, _ = grad(X, ctx.tetra, ctx.conn, ctx.sysm, kappa, ctx.prm, U, lam, gU.contiguous(), mode=ctx.mode,
+                            tol=ctx.tol, want_coord=ctx.need_X)
+        return dlogk, dX, None, None, None, None, None

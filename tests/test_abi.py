@@ -1,0 +1,63 @@
+"""The C-ABI library loads on the host, exports every declared entry point, and rejects
+bad arguments before touching the device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_11133_amd import _binding as B
+
+pytestmark = pytest.mark.cpu
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "phfem.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(phfem_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = B.lib()
+    names = declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTS)
+    assert L.phfem_abi_version() == 1
+
+
+def test_workspace_queries():
+    L = B.lib()
+    assert L.phfem_connect_workspace(8, 6, 7) > 0
+    assert L.phfem_connect_workspace(0, 6, 7) == 0
+    assert L.phfem_connect_workspace(10 ** 6, 10 ** 6, 1) > 10 ** 6 * 6 * 20
+    assert L.phfem_condense_workspace(100) > 0
+    assert L.phfem_solve_workspace(100, 200, 1) > L.phfem_solve_workspace(100, 200, 0)
+    assert L.phfem_grad_workspace(100, 200, 0) > L.phfem_solve_workspace(100, 200, 0)
+
+
+def test_validation_errors_on_host():
+    L = B.lib()
+    counts = np.zeros(3, np.int64)
+    rc = L.phfem_connect(0, 6, None, 1, None, 0, *([None] * 12), counts.ctypes.data, None)
+    assert rc == B.EINVAL and b"positive" in L.phfem_last_error()
+    rc = L.phfem_connect(8, 6, 16, 1, 16, 0, *([16] * 4), *([None] * 8), counts.ctypes.data, None)
+    assert rc == B.EWORKSPACE
+    p = B.params(c=0.0)
+    rc = L.phfem_assemble(8, 16, 6, 16, None, None, C.addressof(p), *([None] * 6), None)
+    assert rc == B.ESINGULAR
+    p = B.params(c=1.0)
+    p.quad = 7
+    rc = L.phfem_assemble(8, 16, 6, 16, None, None, C.addressof(p), *([None] * 6), None)
+    assert rc == B.EINVAL
+    st = B.SolveStats()
+    p = B.params()
+    rc = L.phfem_solve(8, 16, 6, 16, 18, *([16] * 4), None, C.addressof(p), *([16] * 5), 5, 1e-10, 1e-4, 10, 16, 0,
+                       16, 16, C.addressof(st), None)
+    assert rc == B.EINVAL  # bad mode
+    rc = L.phfem_refine(8, 16, 6, 16, 0, *([16] * 3), None, None, None, 0, None, 0, None, 16, 16, None, None, None)
+    assert rc == B.EINVAL

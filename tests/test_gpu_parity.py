@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Connectivity and refinement bit-exact; FP64 local blocks and face system within 1e-12
+(row-relative); mixed precision within 1e-5 on matrix entries; u_h within 1e-10 after the
+solve (both paths); adjoint gradients within 1e-6 of the oracle's.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_2509_11133_amd import meshes as M
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2509_11133_amd import pipeline as P  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def levels(make, L, with_faces=False):
+    out = make()
+    X, T = out[0], out[1]
+    db = out[2] if with_faces else None
+    nb = out[3] if with_faces else None
+    for _ in range(L):
+        X, T, db, nb = O.refine(X, T, db, nb)
+    return X, T, db, nb
+
+
+MESHES = [(M.kuhn_cube, 0), (M.kuhn_cube, 1), (M.kuhn_cube, 3), (M.fichera, 0), (M.fichera, 2)]
+
+
+def single_tet():
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float).T.copy()
+    return X, np.array([[0, 2, 1, 3]], np.int32).T.copy()
+
+
+# ------------------------------------------------------------------ connectivity (a1-a3)
+@pytest.mark.parametrize("make,L", MESHES + [(single_tet, 0), (single_tet, 2)])
+def test_connect_bitexact(make, L):
+    X, T, _, _ = levels(make, L)
+    oc = O.connect(X.shape[1], T)
+    gc = P.connect(dev(T), X.shape[1], faces=True, n2e=True)
+    assert gc["nEd"] == oc["nEd"] and gc["nF"] == oc["nF"] and gc["nB"] == oc["nB"]
+    for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma", "face2tet",
+              "nbr"):
+        assert np.array_equal(host(gc[k]), oc[k]), k
+    # Nodes2Edge: row i lists (j, e) for i < j with j ascending
+    nEd = oc["nEd"]
+    A = sp.csr_matrix((np.arange(nEd) + 1, (oc["edges"][0], oc["edges"][1])), shape=(X.shape[1], X.shape[1]))
+    A.sort_indices()
+    assert np.array_equal(host(gc["n2e_rowptr"]), A.indptr)
+    assert np.array_equal(host(gc["n2e_col"]), A.indices)
+    assert np.array_equal(host(gc["n2e_edge"]) + 1, A.data)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_connect_permuted_relabelled(seed):
+    """Random tet order and node labels (orientation kept): still the oracle's numbering."""
+    rng = np.random.default_rng(seed)
+    X, T, _, _ = levels(M.fichera, 1)
+    T = T[:, rng.permutation(T.shape[1])]
+    T = rng.permutation(X.shape[1])[T].astype(np.int32)
+    oc = O.connect(X.shape[1], T)
+    gc = P.connect(dev(T), X.shape[1])
+    for k in ("edges", "tet2edge", "faces", "tet2face", "sigma", "face2tet", "nbr"):
+        assert np.array_equal(host(gc[k]), oc[k]), k
+
+
+def test_connect_paper_mesh_example():
+    """Listing 1 mesh on the GPU: 16 Faces rows, tet 5 -> [16 7 12 4] (Section 3.3)."""
+    from tests import golden_io as G
+
+    Fg, tet5 = G.faces_listing1()
+    X, T, db, nb = M.paper_cube()
+    gc = P.connect(dev(T), 8)
+    assert np.array_equal(host(gc["faces"]).T + 1, Fg)
+    assert np.array_equal(host(gc["tet2face"])[:, 4] + 1, tet5)
+
+
+def test_connect_errors():
+    X, T = M.kuhn_cube()
+    flip = T.copy()
+    flip[[2, 3], 1] = flip[[3, 2], 1]
+    with pytest.raises(P.PhfemError) as e:
+        P.connect(dev(flip), 8)
+    assert e.value.code == P.B.EORIENT
+    bad = T.copy()
+    bad[0, 3] = 8
+    with pytest.raises(P.PhfemError) as e:
+        P.connect(dev(bad), 8)
+    assert e.value.code == P.B.EINVAL
+
+
+# ------------------------------------------------------------------ refinement (a4)
+@pytest.mark.parametrize("make,L", [(M.kuhn_cube, 3), (M.fichera, 2), (single_tet, 3)])
+def test_refine_bitexact(make, L):
+    X, T = make()[:2]
+    Xd, Td = dev(X), dev(T)
+    for _ in range(L):
+        X, T, _, _ = O.refine(X, T)
+        conn = P.connect(Td, Xd.shape[1], faces=False)
+        Xd, Td, _, _ = P.refine(Xd, Td, conn)
+        assert np.array_equal(host(Td), T)
+        assert np.array_equal(host(Xd), X)  # bitwise
+
+
+def test_refine_worked_example_and_faces():
+    """Section 3.4 example through the GPU, and refineFaces on Listing 1's Db/Nb."""
+    from tests import golden_io as G
+
+    Tg, Cg = G.refine_example()
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float).T.copy()
+    T = np.array([[0, 2, 1, 3]], np.int32).T.copy()
+    conn = P.connect(dev(T), 4, faces=False)
+    Xo, To, _, _ = P.refine(dev(X), dev(T), conn)
+    assert np.array_equal(host(To).T + 1, Tg) and np.array_equal(host(Xo).T, Cg)
+    X, T, db, nb = M.paper_cube()
+    Xd, Td, dbd, nbd = dev(X), dev(T), dev(db), dev(nb)
+    for _ in range(3):
+        X, T, db, nb = O.refine(X, T, db, nb)
+        conn = P.connect(Td, Xd.shape[1], faces=False, n2e=True)
+        Xd, Td, dbd, nbd = P.refine(Xd, Td, conn, dbd, nbd)
+        for a, b in ((Xd, X), (Td, T), (dbd, db), (nbd, nb)):
+            assert np.array_equal(host(a), b)
+
+
+# ------------------------------------------------------------------ local blocks (a5, a6)
+def problem(kind, nE, seed=3):
+    if kind == "sin3":
+        return dict(c=1.0, kappa=None, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)), ud=(O.FUN_ZERO, ()), quad=0)
+    if kind == "rough":
+        return dict(c=0.7, kappa=M.lognormal_kappa(nE, 1.0, seed), f=(O.FUN_SIN3, (2.0,)),
+                    ud=(O.FUN_LINEAR, (0.1, 0.2, -0.3, 0.5)), quad=0)
+    if kind == "p1":
+        return dict(c=1.3, kappa=M.lognormal_kappa(nE, 0.5, seed), f=(O.FUN_X2Y2Z2_LOAD, (1.0, 1.3)),
+                    ud=(O.FUN_X2Y2Z2, (1.0,)), quad=1)
+    raise ValueError(kind)
+
+
+def prm_pair(pb, precision=0):
+    kc = 1.0
+    op = O.params(c=pb["c"], kappa=kc, f=pb["f"], ud=pb["ud"], quad=pb["quad"])
+    gp = P.params(c=pb["c"], kappa=kc, f=pb["f"], ud=pb["ud"], quad=pb["quad"], precision=precision)
+    return op, gp
+
+
+def rowrel(a, b):
+    """max_ij |a_ij - b_ij| / max_j |b_ij| over rows (entries as [rows, n] blocks)."""
+    scale = np.abs(b).max(axis=0)
+    scale[scale == 0] = 1
+    return (np.abs(a - b).max(axis=0) / scale).max()
+
+
+def jittered(L, seed=1):
+    X, T, _, _ = levels(M.kuhn_cube, L)
+    return M.jitter_unit_cube(X, T, 0.1, seed=seed) if L else X, T
+
+
+@pytest.mark.parametrize("kind", ["sin3", "rough", "p1"])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_assemble_parity(kind, precision, tol):
+    X, T = jittered(2)
+    oc = O.connect(X.shape[1], T)
+    pb = problem(kind, T.shape[1])
+    op, gp = prm_pair(pb, precision)
+    ref = O.local(X, T, oc["sigma"], pb["kappa"], op)
+    kap = None if pb["kappa"] is None else dev(pb["kappa"])
+    got = P.assemble(dev(X), dev(T), dev(oc["sigma"]), kap, gp)
+    assert np.abs(host(got["vol"]) - ref["vol"]).max() <= 1e-15 * ref["vol"].max()
+    for k in ("K", "d", "B", "S", "r"):
+        g, r = host(got[k]), ref[k]
+        nb = 4 if k in ("K", "S") else 1
+        err = max(rowrel(g[i * nb:(i + 1) * nb], r[i * nb:(i + 1) * nb]) for i in range(g.shape[0] // nb))
+        assert err <= tol, (k, err)
+
+
+def full_csr(sysm, nF):
+    rp, col, val, diag = (host(sysm[k]) for k in ("rowptr", "col", "val", "diag"))
+    A = sp.csr_matrix((val, col, rp), shape=(nF, nF)) + sp.diags(diag)
+    return A.tocsr()
+
+
+@pytest.mark.parametrize("make,L,kind", [(M.kuhn_cube, 1, "sin3"), (M.kuhn_cube, 3, "sin3"), (M.fichera, 1, "rough"),
+                                         (M.kuhn_cube, 2, "p1")])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_condense_parity(make, L, kind, precision, tol):
+    X, T, _, _ = levels(make, L)
+    oc = O.connect(X.shape[1], T)
+    pb = problem(kind, T.shape[1])
+    op, gp = prm_pair(pb, precision)
+    A, rhs = O.condense(X, T, oc, pb["kappa"], op)
+    gc = P.connect(dev(T), X.shape[1])
+    kap = None if pb["kappa"] is None else dev(pb["kappa"])
+    sysm = P.condense(dev(X), dev(T), gc, kap, gp)
+    G = full_csr(sysm, oc["nF"])
+    # pattern: columns ascending, diagonal separate, nnz = 6 nI + 3 nB off-diagonals
+    assert sysm["nnz"] == A.nnz - oc["nF"]
+    Ad = (A - sp.diags(A.diagonal())).tocsr()
+    Ad.eliminate_zeros()
+    Ad.sort_indices()
+    assert np.array_equal(host(sysm["rowptr"]), Ad.indptr) and np.array_equal(host(sysm["col"]), Ad.indices)
+    D = abs(G - A).tocsr()
+    rowmax = np.asarray(abs(A).max(axis=1).todense()).ravel()
+    assert (np.asarray(D.max(axis=1).todense()).ravel() / rowmax).max() <= tol
+    r = host(sysm["rhs"])
+    assert np.abs(r - rhs).max() <= tol * np.abs(rhs).max()
+
+
+def test_condense_deterministic():
+    X, T, _, _ = levels(M.kuhn_cube, 3)
+    gc = P.connect(dev(T), X.shape[1])
+    gp = P.params(f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    a = P.condense(dev(X), dev(T), gc, None, gp)
+    b = P.condense(dev(X), dev(T), gc, None, gp)
+    for k in ("val", "diag", "rhs", "col"):
+        assert torch.equal(a[k], b[k]), k
+
+
+# ------------------------------------------------------------------ solve + recovery (a8, a9)
+@pytest.mark.parametrize("make,L,kind", [(M.kuhn_cube, 2, "sin3"), (M.kuhn_cube, 3, "sin3"), (M.fichera, 1, "rough")])
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
+def test_solve_parity(make, L, kind, mode, precision):
+    X, T, _, _ = levels(make, L)
+    pb = problem(kind, T.shape[1])
+    op, gp = prm_pair(pb, precision)
+    oc, A, rhs, olam, oU, _ = O.solve(X, T, pb["kappa"], op, tol=1e-14)
+    gc = P.connect(dev(T), X.shape[1])
+    kap = None if pb["kappa"] is None else dev(pb["kappa"])
+    Xd, Td = dev(X), dev(T)
+    sysm = P.condense(Xd, Td, gc, kap, gp)
+    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=1e-5)
+    assert st["rel_res"] <= 1e-11, st
+    assert np.abs(host(U) - oU).max() <= 1e-10 * np.abs(oU).max(), st
+    assert np.abs(host(lam) - olam).max() <= 1e-9 * np.abs(olam).max(), st
+
+
+def test_linear_solution_gpu():
+    """u = a + b.x, P1-interpolated load: U = nodal values to 1e-12 on the GPU path."""
+    a = (0.3, 1.1, -0.7, 0.4)
+    X, T, _, _ = levels(M.kuhn_cube, 2)
+    gp = P.params(c=1.3, kappa=2.5, f=(O.FUN_LINEAR, tuple(1.3 * v for v in a)), ud=(O.FUN_LINEAR, a), quad=1)
+    Xd, Td = dev(X), dev(T)
+    gc = P.connect(Td, X.shape[1])
+    sysm = P.condense(Xd, Td, gc, None, gp)
+    lam, U, st = P.solve(Xd, Td, gc, sysm, None, gp, tol=1e-15, max_iter=20000, allow_noconv=True)
+    nod = a[0] + a[1] * X[0] + a[2] * X[1] + a[3] * X[2]
+    assert np.abs(host(U) - nod[T]).max() <= 1e-12
+
+
+# ------------------------------------------------------------------ adjoint (a10)
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
+def test_grad_parity(mode, precision):
+    X, T = jittered(1, seed=11)
+    pb = problem("rough", T.shape[1], seed=13)
+    op, gp = prm_pair(pb, precision)
+    oc, A, rhs, olam, oU, _ = O.solve(X, T, pb["kappa"], op, tol=1e-14)
+    Ut = np.random.default_rng(17).standard_normal(oU.shape)
+    og = O.adjoint(X, T, oc, pb["kappa"], op, oU, olam, oU - Ut, tol=1e-14)
+    Xd, Td, kap = dev(X), dev(T), dev(pb["kappa"])
+    gc = P.connect(Td, X.shape[1])
+    sysm = P.condense(Xd, Td, gc, kap, gp)
+    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=1e-5)
+    dlogk, dX, st2 = P.grad(Xd, Td, gc, sysm, kap, gp, U, lam, U - dev(Ut), mode=mode, tol=1e-13, inner_tol=1e-5)
+    assert np.abs(host(dlogk) - og["dlogk"]).max() <= 1e-6 * np.abs(og["dlogk"]).max()
+    assert np.abs(host(dX) - og["dX"]).max() <= 1e-6 * np.abs(og["dX"]).max()
+
+
+def test_autograd_function():
+    """torch.autograd through PrimalHybridSolve equals phfem_grad's VJP."""
+    X, T = jittered(1, seed=5)
+    kap = M.lognormal_kappa(T.shape[1], 1.0, 3)
+    Xd, Td = dev(X), dev(T)
+    gc = P.connect(Td, X.shape[1])
+    gp = P.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    logk = dev(np.log(kap)).requires_grad_(True)
+    Xr = Xd.clone().requires_grad_(True)
+    U = P.PrimalHybridSolve.apply(logk, Xr, Td, gc, gp, 0, 1e-13)
+    Ut = torch.zeros_like(U)
+    J = 0.5 * ((U - Ut) ** 2).sum()
+    J.backward()
+    oc = O.connect(X.shape[1], T)
+    op = O.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    _, _, _, olam, oU, _ = O.solve(X, T, kap, op, tol=1e-14)
+    og = O.adjoint(X, T, oc, kap, op, oU, olam, oU, tol=1e-14)
+    assert np.abs(host(logk.grad) - og["dlogk"]).max() <= 1e-6 * np.abs(og["dlogk"]).max()
+    assert np.abs(host(Xr.grad) - og["dX"]).max() <= 1e-6 * np.abs(og["dX"]).max()
