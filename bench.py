@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the primal hybrid FEM hot path on one MI355X.
+
+Headline (one JSON line on stdout): tets/s of refine + connect + condensed assembly
+(12-subtet refinement per level with edge connectivity, full connectivity at the final
+level, local matrices + element Schur + FP64 face system) on the Kuhn cube refined 6 times
+(17,915,904 tets), mixed precision, inputs resident on the GPU.  One step = the whole
+pipeline from the 6-tet level-0 mesh.  The same pipeline in FP64 is timed beside it, and
+the face solve, recovery and adjoint (timed separately, not in the headline) on the 5-level
+cube.  The roofline object is computed from HIP events around every launch of the
+dominant kernel in the timed region; cpu_baseline times the CPU oracle on a smaller mesh.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kuhn_counts(L):
+    """(nE, nC, nEd, nF, nB) of the Kuhn cube after L levels (size recurrences of the split)."""
+    nE, nC, nEd, nF, nB = 6, 8, 19, 18, 12
+    for _ in range(L):
+        nE, nC, nEd, nF, nB = 12 * nE, nC + nEd + nE, 2 * nEd + 3 * nF + 6 * nE, 4 * nF + 16 * nE, 4 * nB
+    return nE, nC, nEd, nF, nB
+
+
+def compulsory_bytes(L):
+    """Algorithmic bytes of the whole pipeline (every array read once and written once):
+    per level l < L edge connectivity of level l and refinement to l+1; at level L full
+    connectivity and the condensed assembly (FP64 face system)."""
+    tot = 0.0
+    for l in range(L):
+        nE, nC, nEd, nF, nB = kuhn_counts(l)
+        tot += 16 * nE + 8 * nEd + 24 * nE + 4 * nEd + 4 * nE              # connect edges: tets -> U, tet2edge, first, prefix
+        tot += 16 * nE + 28 * nE + 4 * nEd + 24 * nC + 192 * nE + 24 * (nE + nEd)  # refine
+    nE, nC, nEd, nF, nB = kuhn_counts(L)
+    tot += 16 * nE + 8 * nEd + 24 * nE + 4 * nEd + 4 * nE
+    tot += 12 * nF + 16 * nE + 4 * nE + 8 * nF + 16 * nE                      # faces, tet2face, sigma, face2tet, nbr
+    nnz = 6 * nF - 3 * nB
+    tot += 52 * nE + 24 * nC + 4 * nF + 12 * nnz + 16 * nF                    # condense
+    return tot
+
+
+def run_pipeline(P, X0, T0, db0, L, prm, kappa=None):
+    X, T, db = X0, T0, db0
+    for _ in range(L):
+        conn = P.connect(T, X.shape[1], faces=False, n2e=True)
+        X, T, db, _ = P.refine(X, T, conn, db)
+    conn = P.connect(T, X.shape[1], faces=True)
+    sysm = P.condense(X, T, conn, kappa, prm)
+    return X, T, conn, sysm
+
+
+def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile):
+    for _ in range(warmup):
+        run_pipeline(P, X0, T0, db0, L, prm)
+    torch.cuda.synchronize()
+    B.phfem_profile_reset()
+    B.phfem_profile_enable(profile)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        out = run_pipeline(P, X0, T0, db0, L, prm)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    B.phfem_profile_enable(False)
+    ms = e0.elapsed_time(e1) / steps
+    kern = {}
+    if profile:
+        for name in B.phfem_profile_names():
+            n, tms, by = B.phfem_profile_query(name)
+            kern[name] = dict(launches=n, ms=tms, bytes=by)
+    return ms, wall / steps * 1e3, kern, out
+
+
+def roofline(kern, steps):
+    name, k = max(kern.items(), key=lambda kv: kv[1]["ms"])
+    if k["bytes"] <= 0:  # fall back to the heaviest kernel with a byte count
+        name, k = max(((n, v) for n, v in kern.items() if v["bytes"] > 0), key=lambda kv: kv[1]["ms"])
+    gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    return name, dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=name,
+                      launches_per_step=k["launches"] // max(steps, 1),
+                      avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 5),
+                      algorithmic_bytes_per_step=k["bytes"] / max(steps, 1))
+
+
+def cpu_baseline(levels):
+    """The oracle (single-threaded FP64 C++) on the same pipeline at a smaller level."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2509_11133_amd import meshes as M
+
+    O.build()
+    X, T = M.kuhn_cube()
+    db = M.boundary_faces_box(X, T)
+    prm = O.params(c=1.0, kappa=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    t0 = time.perf_counter()
+    for _ in range(levels):
+        O.edges(X.shape[1], T)
+        X, T, db, _ = O.refine(X, T, db)
+    conn = O.connect(X.shape[1], T)
+    O.condense(X, T, conn, None, prm)
+    dt = time.perf_counter() - t0
+    nE = T.shape[1]
+    del np
+    return dict(value=round(nE / dt, 1), unit="tets/s", cores=1, kind="oracle",
+                sample=f"Kuhn cube, {levels} levels ({nE} tets): edges+refine per level, full connectivity, "
+                       f"condensed assembly; FP64, 1 thread; {dt:.2f} s")
+
+
+def solve_block(torch, P, B, M, Ls):
+    """a8-a10 time-to-solution on the Kuhn cube at Ls levels (FP64 PCG, mixed IR, adjoint)."""
+    dev = torch.device("cuda:0")
+    X0, T0 = M.kuhn_cube()
+    X, T, _ = P.refine_levels(torch.tensor(X0, device=dev), torch.tensor(T0, device=dev), Ls)
+    conn = P.connect(T, X.shape[1])
+    out = {"workload": f"Kuhn cube, {Ls} levels ({T.shape[1]} tets, {conn['nF']} faces), tol 1e-10"}
+    for label, prec, mode in (("fp64_pcg", B.FP64, B.SOLVE_FP64_PCG), ("mixed_ir", B.MIXED, B.SOLVE_FP32_PCG_FP64_IR)):
+        prm = P.params(c=1.0, kappa=1.0, f=(B.FUN_SIN3, (M.SIN3_AMPLITUDE,)), precision=prec)
+        sysm = P.condense(X, T, conn, None, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, U, st = P.solve(X, T, conn, sysm, None, prm, mode=mode, tol=1e-10, inner_tol=1e-4, max_iter=400000,
+                             allow_noconv=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        dlogk, dX, st2 = P.grad(X, T, conn, sysm, None, prm, U, lam, U, mode=mode, tol=1e-10, inner_tol=1e-4,
+                                max_iter=400000)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        out[label] = dict(solve_ms=round(ts * 1e3, 1), iters=st["iters"], ir_steps=st["ir_steps"],
+                          rel_res=st["rel_res"], converged=st["converged"], grad_ms=round(tg * 1e3, 1),
+                          grad_iters=st2["iters"])
+        log(label, out[label])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--solve-levels", type=int, default=5)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=5)
+    ap.add_argument("--no-profile", action="store_true", help="time without the per-launch HIP events")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only: the hot path runs on a single MI355X; "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_11133_amd import _binding as B
+    from paper_2509_11133_amd import meshes as M
+    from paper_2509_11133_amd import pipeline as P
+
+    B.lib()
+    dev = torch.device("cuda:0")
+    X0, T0 = M.kuhn_cube()
+    db0 = M.boundary_faces_box(X0, T0)
+    X0d, T0d, db0d = (torch.tensor(a, device=dev) for a in (X0, T0, db0))
+    L = args.levels
+    nE, nC, nEd, nF, nB = kuhn_counts(L)
+    f = (B.FUN_SIN3, (M.SIN3_AMPLITUDE,))
+    res = {}
+    for label, prec in (("mixed", B.MIXED), ("fp64", B.FP64)):
+        prm = P.params(c=1.0, kappa=1.0, f=f, precision=prec)
+        ms, wall_ms, kern, out = time_pipeline(torch, P, B, X0d, T0d, db0d, L, prm, args.steps, args.warmup,
+                                               not args.no_profile)
+        assert out[1].shape[1] == nE and out[2]["nF"] == nF
+        res[label] = dict(ms=ms, wall_ms=wall_ms, kern=kern)
+        log(f"{label}: {ms:.3f} ms/step, {nE / ms * 1e3:.4g} tets/s")
+        del out
+        torch.cuda.empty_cache()
+
+    mixed, fp64 = res["mixed"], res["fp64"]
+    value = nE / (mixed["ms"] * 1e-3)
+    comp = compulsory_bytes(L)
+    line = {
+        "metric": "tets/s refine+connect+condensed assembly, mixed vs FP64 on 1 GPU; % HBM peak",
+        "value": round(value, 1),
+        "unit": "tets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"Kuhn cube (6 tets) refined {L} times by the 12-subtet split -> {nE} tets, "
+                               f"{nF} faces; refine+connect per level, full connect + assemble + condense at the "
+                               f"last level; mixed precision (FP32 local/Schur, FP64 dets and face system)",
+                   "levels": L, "nE": nE, "nC": nC, "nEd": nEd, "nF": nF, "nnz_offdiag": 6 * nF - 3 * nB},
+        "fp64": {"value": round(nE / (fp64["ms"] * 1e-3), 1), "ms_per_step": round(fp64["ms"], 4),
+                 "mixed_speedup": round(fp64["ms"] / mixed["ms"], 3)},
+        "useful_hbm_frac": round(comp / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "compulsory_bytes_per_step": comp,
+    }
+    if mixed["kern"]:
+        name, rl = roofline(mixed["kern"], args.steps)
+        line["roofline"] = rl
+        line["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
+                                       for k, v in sorted(mixed["kern"].items(), key=lambda kv: -kv[1]["ms"])}
+        line["fp64"]["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
+                                               for k, v in sorted(fp64["kern"].items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_solve:
+        line["solve"] = solve_block(torch, P, B, M, args.solve_levels)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_levels)
+        line["cpu_baseline"]["speedup_gpu_over_cpu"] = round(value / line["cpu_baseline"]["value"], 1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

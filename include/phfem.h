@@ -227,11 +227,14 @@ int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra
 /* ---------------------------------------------------------------- profiling --------- */
 /* When enabled, every kernel launch of the library is bracketed by HIP events on its
  * stream.  phfem_profile_query synchronizes those events and returns, for the kernel
- * named `name`, the number of launches and their summed duration (ms) since the last
- * reset.  phfem_profile_names writes the names seen, comma separated. */
+ * named `name`, the number of launches, their summed duration (ms) and their summed
+ * algorithmic bytes (each input read once, each output written once; 0 for kernels
+ * without a count) since the last reset (total_bytes may be NULL).  phfem_profile_names
+ * writes the names seen, comma separated.  Host-side bookkeeping only; not thread safe
+ * against concurrent launches from several threads. */
 void phfem_profile_enable(int32_t on);
 void phfem_profile_reset(void);
-int phfem_profile_query(const char* name, int64_t* launches, double* total_ms);
+int phfem_profile_query(const char* name, int64_t* launches, double* total_ms, double* total_bytes);
 int phfem_profile_names(char* buf, size_t buf_bytes);
 
 #ifdef __cplusplus

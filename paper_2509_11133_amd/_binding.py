@@ -98,7 +98,7 @@ def lib():
         L.phfem_grad.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 7 + [VP] * 4 + [VP] * 3
                                  + [I32, DBL, DBL, I32, VP, SZ] + [VP] * 3 + [VP])
         L.phfem_profile_enable.argtypes = [I32]
-        L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP]
+        L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
         L.phfem_profile_names.argtypes = [C.c_char_p, SZ]
         _lib = L
     return _lib
@@ -183,10 +183,12 @@ def phfem_profile_reset():
 
 
 def phfem_profile_query(name):
+    """(launches, total ms, total algorithmic bytes) of one kernel since the last reset."""
     n = C.c_int64()
     ms = C.c_double()
-    _chk(lib().phfem_profile_query(name.encode(), C.addressof(n), C.addressof(ms)))
-    return n.value, ms.value
+    by = C.c_double()
+    _chk(lib().phfem_profile_query(name.encode(), C.addressof(n), C.addressof(ms), C.addressof(by)))
+    return n.value, ms.value, by.value
 
 
 def phfem_profile_names():

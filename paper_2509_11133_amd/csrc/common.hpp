@@ -54,22 +54,26 @@ struct Arena {
 
 // ------------------------------------------------------------------ launches + profiling
 bool profiling();
-void prof_begin(const char* name, hipStream_t s);
+void prof_begin(const char* name, hipStream_t s, double bytes);
 void prof_end(hipStream_t s);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-#define PH_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                  \
-  do {                                                                            \
-    if ((grid) > 0) {                                                             \
-      if (::ph::profiling()) ::ph::prof_begin(name, stream);                      \
+// Launch with an algorithmic byte count (each input read once, each output written once)
+// recorded by the profiler; PH_LAUNCH for kernels without a meaningful count.
+#define PH_LAUNCH_B(name, bytes, kernel, grid, block, shmem, stream, ...)             \
+  do {                                                                                \
+    if ((grid) > 0) {                                                                 \
+      if (::ph::profiling()) ::ph::prof_begin(name, stream, (double)(bytes));         \
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__); \
-      if (::ph::profiling()) ::ph::prof_end(stream);                              \
-      hipError_t e_ = hipGetLastError();                                          \
-      if (e_ != hipSuccess)                                                       \
+      if (::ph::profiling()) ::ph::prof_end(stream);                                  \
+      hipError_t e_ = hipGetLastError();                                              \
+      if (e_ != hipSuccess)                                                           \
         return ::ph::err(PHFEM_EHIP, std::string("launch ") + name + ": " + hipGetErrorString(e_)); \
-    }                                                                             \
+    }                                                                                 \
   } while (0)
+#define PH_LAUNCH(name, kernel, grid, block, shmem, stream, ...) \
+  PH_LAUNCH_B(name, 0, kernel, grid, block, shmem, stream, __VA_ARGS__)
 
 // ------------------------------------------------------------------ device helpers
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }

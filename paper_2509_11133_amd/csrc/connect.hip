@@ -297,7 +297,7 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   PH_HIP(hipMemsetAsync(w.dflags, 0, sizeof(int), s));
 
   // ---- edges
-  PH_LAUNCH("edge_keys", k_edge_keys, grid_for(nE, CT), CT, 0, s, nE, nC, tetra, nb, w.kA, w.dflags);
+  PH_LAUNCH_B("edge_keys", 64.0 * nE, k_edge_keys, grid_for(nE, CT), CT, 0, s, nE, nC, tetra, nb, w.kA, w.dflags);
   int hflags = 0;
   PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   PH_HIP(hipStreamSynchronize(s));
@@ -308,9 +308,9 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   a.off = sub;
   int rc = radix_sort(w.kA, w.vA, w.kB, w.vB, nullptr, n6, 2 * nb, &sk, &sv, a, s);
   if (rc) return rc;
-  PH_LAUNCH("mark_heads", k_mark_heads, grid_for(n6, CT), CT, 0, s, n6, (const uint64_t*)sk, (const int32_t*)sv,
+  PH_LAUNCH_B("mark_heads", 13.0 * n6, k_mark_heads, grid_for(n6, CT), CT, 0, s, n6, (const uint64_t*)sk, (const int32_t*)sv,
             0xffffffffu, w.first);
-  PH_LAUNCH("count_heads6", k_count_heads<6>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
+  PH_LAUNCH_B("count_heads", 10.0 * nE, k_count_heads<6>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
   a.off = sub;
   rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
   if (rc) return rc;
@@ -319,7 +319,7 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   PH_HIP(hipStreamSynchronize(s));
   const int64_t nEd = nEd32;
   PH_HIP(hipMemcpyAsync(tet_edge_prefix, w.cnt, sizeof(int32_t) * nE, hipMemcpyDeviceToDevice, s));
-  PH_LAUNCH("edge_assign", k_edge_assign, grid_for(n6, CT), CT, 0, s, n6, nE, nEd, nb, (const uint64_t*)sk,
+  PH_LAUNCH_B("edge_assign", 17.0 * n6 + 12.0 * nEd + 4.0 * nE, k_edge_assign, grid_for(n6, CT), CT, 0, s, n6, nE, nEd, nb, (const uint64_t*)sk,
             (const int32_t*)sv, (const uint8_t*)w.first, (const uint32_t*)w.cnt, tet2edge, edges, edge_first_tet,
             w.flag);
   if (want_n2e) {
@@ -340,14 +340,14 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
 
   // ---- faces: key = (min node, opposite edge) of every local face
   const int eb = bits_for(nEd);
-  PH_LAUNCH("face_keys", k_face_keys, grid_for(nE, CT), CT, 0, s, nE, tetra, (const int32_t*)tet2edge, eb, w.kA,
+  PH_LAUNCH_B("face_keys", 88.0 * nE, k_face_keys, grid_for(nE, CT), CT, 0, s, nE, tetra, (const int32_t*)tet2edge, eb, w.kA,
             w.vA);
   a.off = sub;
   rc = radix_sort(w.kA, w.vA, w.kB, w.vB, w.vA, n4, nb + eb, &sk, &sv, a, s);
   if (rc) return rc;
-  PH_LAUNCH("mark_heads", k_mark_heads, grid_for(n4, CT), CT, 0, s, n4, (const uint64_t*)sk, (const int32_t*)sv,
+  PH_LAUNCH_B("mark_heads", 13.0 * n4, k_mark_heads, grid_for(n4, CT), CT, 0, s, n4, (const uint64_t*)sk, (const int32_t*)sv,
             SLOT_MASK, w.first);
-  PH_LAUNCH("count_heads4", k_count_heads<4>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
+  PH_LAUNCH_B("count_heads", 8.0 * nE, k_count_heads<4>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
   a.off = sub;
   rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
   if (rc) return rc;
@@ -355,7 +355,7 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   PH_HIP(hipMemcpyAsync(&nF32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PH_HIP(hipStreamSynchronize(s));
   const int64_t nF = nF32;
-  PH_LAUNCH("face_assign", k_face_assign, grid_for(n4, CT), CT, 0, s, n4, nE, nF, (const uint64_t*)sk,
+  PH_LAUNCH_B("face_assign", 22.0 * n4 + 20.0 * nE + 20.0 * nF, k_face_assign, grid_for(n4, CT), CT, 0, s, n4, nE, nF, (const uint64_t*)sk,
             (const int32_t*)sv, (const uint8_t*)w.first, (const uint32_t*)w.cnt, tetra, faces, tet2face, sigma,
             face2tet, nbr, w.dflags);
   PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -503,21 +503,21 @@ __global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict
 int launch_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f,
                    const int8_t* sigma, const double* kappa, const DevParams& P, const double* lambda,
                    const double* gsrc, double* U, double* res, int* flags, hipStream_t s) {
-  PH_LAUNCH("recover", k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, kappa, P, lambda, gsrc, U,
+  PH_LAUNCH_B("recover", (36.0 + (kappa ? 8.0 : 0.0) + (gsrc ? 32.0 : 0.0) + (U ? 32.0 : 0.0)) * nE + 24.0 * nC + (lambda ? 8.0 : 0.0) * nE + (res ? 16.0 : 0.0) * nE, k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, kappa, P, lambda, gsrc, U,
             res, flags);
   return PHFEM_OK;
 }
 
 int launch_face_init(int64_t nF, int64_t nC, const double* X, const int32_t* faces, const int32_t* face2tet,
                      const DevParams& P, uint32_t* cnt, double* diag, double* rhs, hipStream_t s) {
-  PH_LAUNCH("face_init", k_face_init, grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
+  PH_LAUNCH_B("face_init", 28.0 * nF, k_face_init, grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
   return PHFEM_OK;
 }
 
 int launch_vjp(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f, const int8_t* sigma,
                const int32_t* nbr, const double* kappa, const DevParams& P, const double* U, const double* Pp,
                const double* lambda, const double* Q, double* dlogk, double* dX, hipStream_t s) {
-  PH_LAUNCH("vjp", k_vjp, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q,
+  PH_LAUNCH_B("vjp", (124.0 + (kappa ? 8.0 : 0.0)) * nE + 16.0 * nE + 72.0 * nC, k_vjp, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q,
             dlogk, dX);
   return PHFEM_OK;
 }
@@ -566,11 +566,14 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
   if (rc) return rc;
   rc = scan_exclusive((const uint32_t*)rowptr, (uint32_t*)rowptr, nF + 1, nullptr, a, s);
   if (rc) return rc;
+  // algorithmic bytes: tets, faces, sigma, neighbours (+ kappa) once per tet, coordinates
+  // once per node, row pointers once, every off-diagonal (col + val) and diag/rhs written once
+  const double cbytes = (52.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + 4.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
   if (p->precision == PHFEM_MIXED)
-    PH_LAUNCH("condense_f32", k_condense<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma, nbr,
+    PH_LAUNCH_B("condense_f32", cbytes, k_condense<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma, nbr,
               kappa, P, (const int32_t*)rowptr, col, val, diag, rhs);
   else
-    PH_LAUNCH("condense_f64", k_condense<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma,
+    PH_LAUNCH_B("condense_f64", cbytes, k_condense<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma,
               nbr, kappa, P, (const int32_t*)rowptr, col, val, diag, rhs);
   return PHFEM_OK;
 }

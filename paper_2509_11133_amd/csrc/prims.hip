@@ -37,6 +37,7 @@ int check_params(const phfem_params* p) {
 struct ProfRec {
   const char* name;
   hipEvent_t a, b;
+  double bytes;
 };
 static bool g_prof = false;
 static std::vector<ProfRec> g_recs;
@@ -55,9 +56,9 @@ static hipEvent_t pool_event() {
 
 bool profiling() { return g_prof; }
 
-void prof_begin(const char* name, hipStream_t s) {
+void prof_begin(const char* name, hipStream_t s, double bytes) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  ProfRec r{name, pool_event(), pool_event()};
+  ProfRec r{name, pool_event(), pool_event(), bytes};
   if (r.a) (void)hipEventRecord(r.a, s);
   g_recs.push_back(r);
 }
@@ -286,11 +287,12 @@ int radix_sort(uint64_t* keysA, int32_t* valsA, uint64_t* keysB, int32_t* valsB,
   if (bits <= 0) bits = RS_BITS;  // still run one pass so values are materialised
   for (int shift = 0; shift < bits; shift += RS_BITS) {
     ws.off = mark;
-    PH_LAUNCH("rs_hist", k_rs_hist, (unsigned)nb, RS_THREADS, 0, s, (const uint64_t*)kbuf[cur], n, shift, hist, nb);
+    PH_LAUNCH_B("rs_hist", 8.0 * n, k_rs_hist, (unsigned)nb, RS_THREADS, 0, s, (const uint64_t*)kbuf[cur], n, shift,
+                hist, nb);
     int rc = scan_exclusive(hist, hist, nb * RS_RADIX, nullptr, ws, s);
     if (rc) return rc;
-    PH_LAUNCH("rs_scatter", k_rs_scatter, (unsigned)nb, RS_THREADS, 0, s, (const uint64_t*)kbuf[cur], vsrc, n,
-              shift, (const uint32_t*)hist, nb, kbuf[cur ^ 1], vbuf[cur ^ 1]);
+    PH_LAUNCH_B("rs_scatter", (vsrc ? 24.0 : 20.0) * n, k_rs_scatter, (unsigned)nb, RS_THREADS, 0, s,
+                (const uint64_t*)kbuf[cur], vsrc, n, shift, (const uint32_t*)hist, nb, kbuf[cur ^ 1], vbuf[cur ^ 1]);
     cur ^= 1;
     vsrc = vbuf[cur];
   }
@@ -315,20 +317,22 @@ void phfem_profile_reset(void) {
   ph::g_pool_used = 0;
 }
 
-int phfem_profile_query(const char* name, int64_t* launches, double* total_ms) {
+int phfem_profile_query(const char* name, int64_t* launches, double* total_ms, double* total_bytes) {
   std::lock_guard<std::mutex> lk(ph::g_prof_mu);
   int64_t n = 0;
-  double ms = 0;
+  double ms = 0, by = 0;
   for (auto& r : ph::g_recs) {
     if (std::strcmp(r.name, name) != 0 || !r.a || !r.b) continue;
     if (hipEventSynchronize(r.b) != hipSuccess) return ph::err(PHFEM_EHIP, "event sync");
     float t = 0;
     if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return ph::err(PHFEM_EHIP, "event elapsed");
     ms += t;
+    by += r.bytes;
     ++n;
   }
   *launches = n;
   *total_ms = ms;
+  if (total_bytes) *total_bytes = by;
   return PHFEM_OK;
 }
 

@@ -252,10 +252,10 @@ static int pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const T* va
   int slot = 0, it = 0;
   double rel = 1.0;
   while (it < maxit) {
-    PH_LAUNCH("spmv_dot", k_spmv_dot<T>, G, ST, 0, s, n, rowptr, col, val, diag, (const T*)p, q, w.part_pq);
-    PH_LAUNCH("pcg_update", k_pcg_update<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
+    PH_LAUNCH_B("spmv_dot", (double)n * (4 + 3 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dot<T>, G, ST, 0, s, n, rowptr, col, val, diag, (const T*)p, q, w.part_pq);
+    PH_LAUNCH_B("pcg_update", 8.0 * sizeof(T) * n, k_pcg_update<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
               slot, x, r, (const T*)p, (const T*)q, diag, z, w.part_rz, w.part_rr);
-    PH_LAUNCH("pcg_dir", k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz, (const double*)w.part_rr,
+    PH_LAUNCH_B("pcg_dir", 3.0 * sizeof(T) * n, k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz, (const double*)w.part_rr,
               w.scal, slot, (const T*)z, p);
     slot ^= 1;
     ++it;
