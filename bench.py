@@ -53,19 +53,27 @@ def compulsory_bytes(L):
     return tot
 
 
-def run_pipeline(P, X0, T0, db0, L, prm, kappa=None):
-    X, T, db = X0, T0, db0
-    for _ in range(L):
-        conn = P.connect(T, X.shape[1], faces=False, n2e=True)
-        X, T, db, _ = P.refine(X, T, conn, db)
-    conn = P.connect(T, X.shape[1], faces=True)
+def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False):
+    """One step.  Default: the level-0 mesh is connected by the general sort-based connect,
+    every refinement level derives the refined mesh's connectivity in closed form
+    (phfem_refine_connected), then assemble + condense.  sort_connect=True: per level
+    connect-edges (sort) -> refine (with the Dirichlet face list), then a sort-based full
+    connect of the final mesh."""
+    if sort_connect:
+        X, T, db = X0, T0, db0
+        for _ in range(L):
+            conn = P.connect(T, X.shape[1], faces=False, n2e=True)
+            X, T, db, _ = P.refine(X, T, conn, db)
+        conn = P.connect(T, X.shape[1], faces=True)
+    else:
+        X, T, conn = P.refine_connected_levels(X0, T0, L)
     sysm = P.condense(X, T, conn, kappa, prm)
     return X, T, conn, sysm
 
 
-def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile):
+def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort_connect=False):
     for _ in range(warmup):
-        run_pipeline(P, X0, T0, db0, L, prm)
+        run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
     torch.cuda.synchronize()
     B.phfem_profile_reset()
     B.phfem_profile_enable(profile)
@@ -73,7 +81,7 @@ def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile):
     t0 = time.perf_counter()
     e0.record()
     for _ in range(steps):
-        out = run_pipeline(P, X0, T0, db0, L, prm)
+        out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -163,6 +171,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=5)
     ap.add_argument("--no-profile", action="store_true", help="time without the per-launch HIP events")
+    ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -185,10 +194,12 @@ def main():
     nE, nC, nEd, nF, nB = kuhn_counts(L)
     f = (B.FUN_SIN3, (M.SIN3_AMPLITUDE,))
     res = {}
-    for label, prec in (("mixed", B.MIXED), ("fp64", B.FP64)):
+    for label, prec, sortc in (("mixed", B.MIXED, False), ("fp64", B.FP64, False), ("mixed_sort", B.MIXED, True)):
+        if sortc and args.no_sort_variant:
+            continue
         prm = P.params(c=1.0, kappa=1.0, f=f, precision=prec)
         ms, wall_ms, kern, out = time_pipeline(torch, P, B, X0d, T0d, db0d, L, prm, args.steps, args.warmup,
-                                               not args.no_profile)
+                                               not args.no_profile, sort_connect=sortc)
         assert out[1].shape[1] == nE and out[2]["nF"] == nF
         res[label] = dict(ms=ms, wall_ms=wall_ms, kern=kern)
         log(f"{label}: {ms:.3f} ms/step, {nE / ms * 1e3:.4g} tets/s")
@@ -212,14 +223,22 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"Kuhn cube (6 tets) refined {L} times by the 12-subtet split -> {nE} tets, "
-                               f"{nF} faces; refine+connect per level, full connect + assemble + condense at the "
-                               f"last level; mixed precision (FP32 local/Schur, FP64 dets and face system)",
+                               f"{nF} faces; sort-based connect of level 0, refine with derived connectivity per "
+                               f"level, assemble + condense at the last level; mixed precision (FP32 local/Schur, "
+                               f"FP64 dets and face system)",
                    "levels": L, "nE": nE, "nC": nC, "nEd": nEd, "nF": nF, "nnz_offdiag": 6 * nF - 3 * nB},
         "fp64": {"value": round(nE / (fp64["ms"] * 1e-3), 1), "ms_per_step": round(fp64["ms"], 4),
                  "mixed_speedup": round(fp64["ms"] / mixed["ms"], 3)},
         "useful_hbm_frac": round(comp / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "compulsory_bytes_per_step": comp,
     }
+    if "mixed_sort" in res:
+        ms_ = res["mixed_sort"]
+        line["sort_connect_pipeline"] = {
+            "value": round(nE / (ms_["ms"] * 1e-3), 1), "ms_per_step": round(ms_["ms"], 4),
+            "note": "same workload with sort-based connect at every level (general phfem_connect path)",
+            "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4)
+                                    for k, v in sorted(ms_["kern"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
     if mixed["kern"]:
         name, rl = roofline(mixed["kern"], args.steps)
         line["roofline"] = rl

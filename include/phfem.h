@@ -144,6 +144,25 @@ int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tet
                  const int32_t* db, int64_t nNb, const int32_t* nb, double* coord_out, int32_t* tetra_out,
                  int32_t* db_out, int32_t* nb_out, phfem_stream_t stream);
 
+/* Refinement with connectivity: phfem_refine's outputs plus the refined mesh's full
+ * phfem_connect outputs (edges, tet2edge, edge_first_tet, tet_edge_prefix, faces,
+ * tet2face, sigma, face2tet, nbr) -- the same numbering NumEdges / FacesUp give the
+ * refined mesh (Sections 3.1-3.4), derived in closed form from the coarse numbering with
+ * no sort.  Inputs must be the coarse mesh's own phfem_connect (or phfem_refine_connected)
+ * outputs.  Refined sizes: nC' = nC + nEd + nE, nE' = 12 nE, nEd' = 2 nEd + 3 nF + 6 nE,
+ * nF' = 4 nF + 16 nE, nB' = 2 nF' - 4 nE' (written to counts[3] = {nEd', nF', nB'}); output
+ * arrays are packed SoA with those strides (capacities = these sizes).  No boundary face
+ * lists (use phfem_refine for Db/Nb).  Synchronizes once; EINVAL if the refined counts
+ * disagree with the recurrences (input not a first-appearance numbering). */
+size_t phfem_refine_connected_workspace(int64_t nE, int64_t nEd);
+int phfem_refine_connected(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd, int64_t nF,
+                           const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
+                           const int32_t* tet2face, const int32_t* nbr, void* work, size_t work_bytes,
+                           double* coord_out, int32_t* tetra_out, int32_t* edges_out, int32_t* tet2edge_out,
+                           int32_t* edge_first_tet_out, int32_t* tet_edge_prefix_out, int32_t* faces_out,
+                           int32_t* tet2face_out, int8_t* sigma_out, int32_t* face2tet_out, int32_t* nbr_out,
+                           int64_t* counts, phfem_stream_t stream);
+
 /* ---------------------------------------------------------------- assemble (a5-a6) --- */
 /* Per-tet local blocks (Sections 4.2-4.5; StiffMassPH, Multiplier, the page solves of
  * SchurComplement_vectorization).  kappa[nE] may be NULL (then p->kappa_const).

@@ -100,6 +100,16 @@ __global__ __launch_bounds__(RT) void k_refine_faces(int64_t n, const int32_t* _
   }
 }
 
+int launch_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, const int32_t* t2e,
+                  const int32_t* eft, const int32_t* pre, int64_t nCo, double* coord_out, int32_t* tetra_out,
+                  hipStream_t s) {
+  PH_LAUNCH_B("copy_coords", 48.0 * nC, k_copy_coords, grid_for(nC, RT), RT, 0, s, nC, coord, nCo, coord_out);
+  const int64_t nEd = nCo - nC - nE;
+  PH_LAUNCH_B("refine", 44.0 * nE + 4.0 * nEd + 24.0 * nC + 192.0 * nE + 24.0 * (nE + nEd), k_refine, grid_for(nE, RT),
+              RT, 0, s, nC, coord, nE, tetra, t2e, eft, pre, nCo, coord_out, tetra_out);
+  return PHFEM_OK;
+}
+
 }  // namespace ph
 
 using namespace ph;
@@ -119,9 +129,8 @@ extern "C" int phfem_refine(int64_t nC, const double* coord, int64_t nE, const i
   const bool faces = nDb + nNb > 0;
   if (faces && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "boundary faces need Nodes2Edge");
   if ((nDb > 0 && (!db || !db_out)) || (nNb > 0 && (!nb || !nb_out))) return err(PHFEM_EINVAL, "null face list");
-  PH_LAUNCH_B("copy_coords", 48.0 * nC, k_copy_coords, grid_for(nC, RT), RT, 0, s, nC, coord, nCo, coord_out);
-  PH_LAUNCH_B("refine", 44.0 * nE + 4.0 * nEd + 24.0 * nC + 192.0 * nE + 24.0 * (nE + nEd), k_refine, grid_for(nE, RT), RT, 0, s, nC, coord, nE, tetra, tet2edge, edge_first_tet,
-            tet_edge_prefix, nCo, coord_out, tetra_out);
+  int rc = launch_refine(nC, coord, nE, tetra, tet2edge, edge_first_tet, tet_edge_prefix, nCo, coord_out, tetra_out, s);
+  if (rc) return rc;
   if (!faces) return PHFEM_OK;
   // error flag of the face lookups: a 4-byte device global (calls on one device that
   // overlap in time share it)

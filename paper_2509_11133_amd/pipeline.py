@@ -65,6 +65,43 @@ def refine(coord, tetra, conn, db=None, nb=None):
     return Xo, To, dbo, nbo
 
 
+def refine_connected(coord, tetra, conn):
+    """One refinement level that also returns the refined mesh's full connectivity (same
+    numbering as connect() on it), derived from `conn` (full connectivity of the coarse
+    mesh) without sorting.  Returns (coord, tetra, conn)."""
+    dev = coord.device
+    nC, nE, nEd, nF = coord.shape[1], tetra.shape[1], conn["nEd"], conn["nF"]
+    nC2, nE2 = nC + nEd + nE, 12 * nE
+    nEd2, nF2 = 2 * nEd + 3 * nF + 6 * nE, 4 * nF + 16 * nE
+    work = B.workspace(B.lib().phfem_refine_connected_workspace(nE, nEd), dev)
+    Xo = torch.empty((3, nC2), dtype=F64, device=dev)
+    To = torch.empty((4, nE2), dtype=I32, device=dev)
+    e = torch.empty((2, nEd2), dtype=I32, device=dev)
+    t2e = torch.empty((6, nE2), dtype=I32, device=dev)
+    eft = torch.empty(nEd2, dtype=I32, device=dev)
+    pre = torch.empty(nE2, dtype=I32, device=dev)
+    fa = torch.empty((3, nF2), dtype=I32, device=dev)
+    t2f = torch.empty((4, nE2), dtype=I32, device=dev)
+    sig = torch.empty((4, nE2), dtype=torch.int8, device=dev)
+    f2t = torch.empty((2, nF2), dtype=I32, device=dev)
+    nbr = torch.empty((4, nE2), dtype=I32, device=dev)
+    counts = np.zeros(3, np.int64)
+    B.phfem_refine_connected(nC, coord, nE, tetra, nEd, nF, conn["tet2edge"], conn["edge_first_tet"],
+                             conn["tet_edge_prefix"], conn["tet2face"], conn["nbr"], work, Xo, To, e, t2e, eft, pre,
+                             fa, t2f, sig, f2t, nbr, counts)
+    out = dict(nC=nC2, nE=nE2, nEd=int(counts[0]), edges=e, tet2edge=t2e, edge_first_tet=eft, tet_edge_prefix=pre,
+               nF=int(counts[1]), nB=int(counts[2]), faces=fa, tet2face=t2f, sigma=sig, face2tet=f2t, nbr=nbr)
+    return Xo, To, out
+
+
+def refine_connected_levels(coord, tetra, levels):
+    """connect() on the input mesh, then `levels` x refine_connected.  Returns (coord, tetra, conn)."""
+    conn = connect(tetra, coord.shape[1], faces=True)
+    for _ in range(levels):
+        coord, tetra, conn = refine_connected(coord, tetra, conn)
+    return coord, tetra, conn
+
+
 def assemble(coord, tetra, sigma, kappa, prm):
     """Per-tet blocks: vol, kappa K (16), sigma|F| (4), B (4), S (16), r (4)."""
     dev = coord.device

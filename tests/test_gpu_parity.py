@@ -298,3 +298,54 @@ def test_autograd_function():
     og = O.adjoint(X, T, oc, kap, op, oU, olam, oU, tol=1e-14)
     assert np.abs(host(logk.grad) - og["dlogk"]).max() <= 1e-6 * np.abs(og["dlogk"]).max()
     assert np.abs(host(Xr.grad) - og["dX"]).max() <= 1e-6 * np.abs(og["dX"]).max()
+
+
+# ------------------------------------------------------------------ refinement with connectivity
+def _perm_relabel(X, T, seed):
+    rng = np.random.default_rng(seed)
+    T = T[:, rng.permutation(T.shape[1])]
+    perm = rng.permutation(X.shape[1])
+    X2 = np.zeros_like(X)
+    X2[:, perm] = X
+    return X2, perm[T].astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["kuhn", "fichera", "paper", "single_neg", "fichera_perm", "kuhn1_perm"])
+def test_refine_connected_bitexact(case):
+    """phfem_refine_connected = phfem_refine + oracle connect of the refined mesh, bit for bit,
+    over two levels (the second consumes the first's derived connectivity)."""
+    if case == "kuhn":
+        X, T = M.kuhn_cube()
+    elif case == "fichera":
+        X, T = M.fichera()
+    elif case == "paper":
+        X, T = M.paper_cube()[:2]
+    elif case == "single_neg":
+        X, T = single_tet()
+    elif case == "fichera_perm":
+        X, T = _perm_relabel(*M.fichera(), seed=3)
+    else:
+        X, T, _, _ = O.refine(*M.kuhn_cube())
+        X, T = _perm_relabel(X, T, seed=4)
+    Xd, Td = dev(X), dev(T)
+    conn = P.connect(Td, X.shape[1])
+    for _ in range(2):
+        X, T, _, _ = O.refine(X, T)
+        Xd, Td, conn = P.refine_connected(Xd, Td, conn)
+        assert np.array_equal(host(Td), T) and np.array_equal(host(Xd), X)
+        oc = O.connect(X.shape[1], T)
+        assert conn["nEd"] == oc["nEd"] and conn["nF"] == oc["nF"] and conn["nB"] == oc["nB"]
+        for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma",
+                  "face2tet", "nbr"):
+            assert np.array_equal(host(conn[k]), oc[k]), k
+
+
+def test_refine_connected_matches_sort_connect_L5():
+    """At 1.49M tets (Kuhn, 5 levels): the derived connectivity equals the sort-based
+    phfem_connect of the same refined mesh, bit for bit."""
+    X, T = M.kuhn_cube()
+    Xd, Td, conn = P.refine_connected_levels(dev(X), dev(T), 5)
+    ref = P.connect(Td, Xd.shape[1])
+    for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma", "face2tet",
+              "nbr"):
+        assert torch.equal(conn[k], ref[k]), k
