@@ -180,7 +180,7 @@ int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const int32_t* t
                    double* S, double* r, phfem_stream_t stream);
 
 /* ---------------------------------------------------------------- condense (a5-a7) --- */
-size_t phfem_condense_workspace(int64_t nF);
+size_t phfem_condense_workspace(int64_t nE, int64_t nF, int32_t precision);
 
 /* Condensed face system S+ lambda = r+ with S+ = sum_T P_T' C A^-1 C' P_T and
  * r+ = b_D - sum_T P_T' C A^-1 B, b_D,F = |F| u_D(centroid F) on boundary faces
@@ -188,8 +188,11 @@ size_t phfem_condense_workspace(int64_t nF);
  * Storage: diagonal separate, off-diagonals as CSR with columns ascending:
  *   rowptr[nF+1] (row F holds 6 entries, 3 for a boundary face), col[6 nF] and val[6 nF]
  *   (capacities), diag[nF], rhs[nF]; all float64 (the FP64 sums of FP32 blocks in mixed).
- * Each off-diagonal has exactly one contributing tet; diagonal and rhs entries sum at most
- * two tet contributions (bitwise order independent).  Inputs from phfem_connect.
+ * Each off-diagonal has exactly one contributing tet; a diagonal / rhs entry is the owner
+ * tet's term plus the neighbour's (in that order).  Two coalesced passes: one contiguous
+ * record per tet (element Schur block, C A^-1 B, face ids; FP32 records in mixed
+ * precision), then one thread per face writes its whole row.  Inputs from phfem_connect
+ * (nbr is not read and may be NULL).
  * Errors: EINVAL, ESINGULAR, EWORKSPACE.  Does not synchronize (EDEGEN is reported by
  * phfem_solve). */
 int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,

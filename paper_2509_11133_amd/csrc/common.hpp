@@ -190,6 +190,9 @@ __device__ __forceinline__ void fun_grad(int kind, const double* p, double x, do
 size_t scan_workspace(int64_t n);
 int scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, Arena& ws, hipStream_t s);
 
+// Packed scan: in = count (bits 0..7) | payload << 8, out = exclusive prefix << pb | payload.
+int scan_packed(const uint32_t* in, uint32_t* out, int64_t n, int pb, uint32_t* total, Arena& ws, hipStream_t s);
+
 // Stable LSD radix sort of (uint64 key, int32 value) pairs on key bits [0, bits).
 // vals_in == nullptr means values = index.  Result ends in (*keys_out, *vals_out), which
 // point into one of the two buffer pairs.

@@ -227,6 +227,7 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
   const bool interior = face2tet[nF + f] >= 0;
   if (cnt) cnt[f] = interior ? 6u : 3u;
   if (diag) diag[f] = 0.0;
+  if (!rhs) return;
   double b = 0.0;
   if (!interior && P.uk != PHFEM_FUN_ZERO) {
     double x[3][3];
@@ -302,6 +303,153 @@ __global__ __launch_bounds__(FT) void k_condense(int64_t nC, const double* __res
     }
     atomicAdd(&diag[Fk], (double)E.S(k, k));
     atomicAdd(&rhs[Fk], -(double)r[k]);
+  }
+}
+
+// Condensation in two coalesced passes (no atomics):
+//  k_elem_rec: one tet -> one contiguous record {S (10 unique, row-major upper), r (4), the
+//              tet's 4 face ids};
+//  k_face_rows: one face -> its whole CSR row from the records of its owner and neighbour:
+//              off-diagonals sorted by column, diagonal S_owner + S_neighbour and
+//              rhs (b_D - r_owner) - r_neighbour in that order.
+template <class R>
+struct alignas(16) ElemRec {
+  R s[10];
+  R r[4];
+  int32_t f[4];
+};
+
+__host__ __device__ constexpr int uidx(int k, int l) {
+  return k <= l ? k * 4 - k * (k - 1) / 2 + (l - k) : l * 4 - l * (l - 1) / 2 + (k - l);
+}
+static_assert(uidx(0, 3) == 3 && uidx(1, 1) == 4 && uidx(3, 2) == 8 && uidx(3, 3) == 9, "upper-triangle index");
+
+template <class R>
+__global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                                 const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                                 const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
+                                                 DevParams P, ElemRec<R>* __restrict__ recs, int* __restrict__ flags) {
+  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (t >= nE) return;
+  int v[4], sig[4];
+  ElemRec<R> rec;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    sig[i] = sigma[i * nE + t];
+    rec.f[i] = t2f[i * nE + t];
+  }
+  double x[4][3];
+  gather_x(nC, X, v, x);
+  const double kap = kappa ? kappa[t] : P.kc;
+  Elem<R> E;
+  if (!E.init(x, kap, P.c, sig)) {
+    if (flags) atomicOr(flags, DEV_DEGEN);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) rec.s[i] = (R)0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rec.r[i] = (R)0;
+    recs[t] = rec;
+    return;
+  }
+  R B[4];
+  load_vec<R>(x, E.vol, P, B);
+  E.CAinv(B, rec.r);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int l = k; l < 4; ++l) rec.s[uidx(k, l)] = E.S(k, l);
+  recs[t] = rec;
+}
+
+// The rows of one workgroup's faces form one contiguous range of the CSR arrays: they are
+// assembled in LDS and written out with coalesced stores.
+template <class R>
+__global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const double* __restrict__ X,
+                                                  const int32_t* __restrict__ faces,
+                                                  const int32_t* __restrict__ face2tet, DevParams P,
+                                                  const ElemRec<R>* __restrict__ recs,
+                                                  const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                  double* __restrict__ val, double* __restrict__ diag,
+                                                  double* __restrict__ rhs) {
+  __shared__ int32_t lcol[6 * FT];
+  __shared__ double lval[6 * FT];
+  const int64_t f0 = (int64_t)blockIdx.x * FT;
+  const int64_t f = f0 + threadIdx.x;
+  const int64_t fend = f0 + FT < nF ? f0 + FT : nF;
+  const int blo = rowptr[f0];
+  const int bhi = rowptr[fend];
+  if (f < nF) {
+    const int q0 = face2tet[f], q1 = face2tet[nF + f];
+    int cf[6];
+    double cv[6];
+    int n = 0;
+    double dg = 0.0, rh = 0.0;
+    if (q1 < 0 && P.uk != PHFEM_FUN_ZERO) {  // b_D = |F| u_D(centroid) on a boundary face
+      double xx[3][3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        int vv = faces[m * nF + f];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) xx[m][e] = X[e * nC + vv];
+      }
+      double u0 = xx[2][0] - xx[0][0], u1 = xx[2][1] - xx[0][1], u2 = xx[2][2] - xx[0][2];
+      double s0 = xx[1][0] - xx[0][0], s1 = xx[1][1] - xx[0][1], s2 = xx[1][2] - xx[0][2];
+      double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
+      double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+      rh = area * fun_at<double>(P.uk, P.up, (xx[0][0] + xx[1][0] + xx[2][0]) / 3.0,
+                                 (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
+    }
+    {
+      const ElemRec<R>* a = recs + (q0 >> 2);
+      const int k = q0 & 3;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const R sv = a->s[uidx(k, l)];  // k is a run-time value: direct loads, no register indexing
+        if (l == k) {
+          dg = (double)sv;
+        } else {
+          cf[n] = a->f[l];
+          cv[n] = (double)sv;
+          ++n;
+        }
+      }
+      rh -= (double)a->r[k];
+    }
+    if (q1 >= 0) {
+      const ElemRec<R>* b = recs + (q1 >> 2);
+      const int k = q1 & 3;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const R sv = b->s[uidx(k, l)];
+        if (l == k) {
+          dg += (double)sv;
+        } else {
+          cf[n] = b->f[l];
+          cv[n] = (double)sv;
+          ++n;
+        }
+      }
+      rh -= (double)b->r[k];
+    }
+    const int base = rowptr[f] - blo;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i < n) {
+        int rank = 0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) rank += (j < n && cf[j] < cf[i]) ? 1 : 0;
+        lcol[base + rank] = cf[i];
+        lval[base + rank] = cv[i];
+      }
+    }
+    diag[f] = dg;
+    rhs[f] = rh;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < bhi - blo; i += FT) {
+    col[blo + i] = lcol[i];
+    val[blo + i] = lval[i];
   }
 }
 
@@ -510,7 +658,7 @@ int launch_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, 
 
 int launch_face_init(int64_t nF, int64_t nC, const double* X, const int32_t* faces, const int32_t* face2tet,
                      const DevParams& P, uint32_t* cnt, double* diag, double* rhs, hipStream_t s) {
-  PH_LAUNCH_B("face_init", 28.0 * nF, k_face_init, grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
+  PH_LAUNCH_B("face_init", (8.0 + (cnt ? 4.0 : 0.0) + (diag ? 8.0 : 0.0) + (rhs ? 8.0 : 0.0)) * nF, k_face_init, grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
   return PHFEM_OK;
 }
 
@@ -544,7 +692,15 @@ extern "C" int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const
   return PHFEM_OK;
 }
 
-extern "C" size_t phfem_condense_workspace(int64_t nF) { return scan_workspace(nF + 1); }
+extern "C" size_t phfem_condense_workspace(int64_t nE, int64_t nF, int32_t precision) {
+  Arena a;
+  if (precision == PHFEM_MIXED)
+    a.take<ElemRec<float>>(nE);
+  else
+    a.take<ElemRec<double>>(nE);
+  a.take<int>(16);
+  return a.size() + scan_workspace(nF + 1);
+}
 
 extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
                               const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* nbr,
@@ -555,25 +711,38 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
   hipStream_t s = (hipStream_t)stream_;
   int rc = check_params(p);
   if (rc) return rc;
-  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !nbr || !face2tet ||
-      !rowptr || !col || !val || !diag || !rhs)
+  (void)nbr;
+  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !face2tet || !rowptr ||
+      !col || !val || !diag || !rhs)
     return err(PHFEM_EINVAL, "bad condense arguments");
   if (6 * nF >= (int64_t(1) << 31)) return err(PHFEM_EINVAL, "face system exceeds int32 indexing");
-  if (!work || work_bytes < phfem_condense_workspace(nF)) return err(PHFEM_EWORKSPACE, "condense workspace too small");
+  if (!work || work_bytes < phfem_condense_workspace(nE, nF, p->precision))
+    return err(PHFEM_EWORKSPACE, "condense workspace too small");
   Arena a(work, work_bytes);
+  const bool mixed = p->precision == PHFEM_MIXED;
+  void* recs = mixed ? (void*)a.take<ElemRec<float>>(nE) : (void*)a.take<ElemRec<double>>(nE);
+  a.take<int>(16);
   DevParams P = to_dev(*p);
-  rc = launch_face_init(nF, nC, coord, faces, face2tet, P, (uint32_t*)rowptr, diag, rhs, s);
+  rc = launch_face_init(nF, nC, coord, faces, face2tet, P, (uint32_t*)rowptr, nullptr, nullptr, s);
   if (rc) return rc;
   rc = scan_exclusive((const uint32_t*)rowptr, (uint32_t*)rowptr, nF + 1, nullptr, a, s);
   if (rc) return rc;
-  // algorithmic bytes: tets, faces, sigma, neighbours (+ kappa) once per tet, coordinates
-  // once per node, row pointers once, every off-diagonal (col + val) and diag/rhs written once
-  const double cbytes = (52.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + 4.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
-  if (p->precision == PHFEM_MIXED)
-    PH_LAUNCH_B("condense_f32", cbytes, k_condense<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma, nbr,
-              kappa, P, (const int32_t*)rowptr, col, val, diag, rhs);
-  else
-    PH_LAUNCH_B("condense_f64", cbytes, k_condense<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face, sigma,
-              nbr, kappa, P, (const int32_t*)rowptr, col, val, diag, rhs);
+  // algorithmic bytes: tets, faces, sigma (+ kappa) once per tet, coordinates once per node,
+  // one record per tet written once and read once, face2tet and row pointers once, every
+  // off-diagonal (col + val) and diagonal/rhs entry written once
+  const double rb = (double)(mixed ? sizeof(ElemRec<float>) : sizeof(ElemRec<double>));
+  const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
+  const double fb = rb * nE + 12.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
+  if (mixed) {
+    PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face,
+                sigma, kappa, P, (ElemRec<float>*)recs, nullptr);
+    PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces, face2tet,
+                P, (const ElemRec<float>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
+  } else {
+    PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face,
+                sigma, kappa, P, (ElemRec<double>*)recs, nullptr);
+    PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
+                face2tet, P, (const ElemRec<double>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
+  }
   return PHFEM_OK;
 }

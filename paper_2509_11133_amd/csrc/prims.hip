@@ -164,6 +164,56 @@ int scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total
   return PHFEM_OK;
 }
 
+// Packed variant: in[i] = count (bits 0..7) | payload << 8; out[i] = (exclusive prefix of
+// the counts) << pb | payload.  Used for per-row (first-appearance prefix, mask) records.
+__global__ __launch_bounds__(SC_THREADS) void k_scanp_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                             uint32_t* __restrict__ partial) {
+  __shared__ uint32_t lw[SC_THREADS / 64];
+  int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
+    if (idx < n) s += in[idx] & 0xffu;
+  }
+  uint32_t tot;
+  block_inclusive_scan(s, lw, tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scanp_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                            const uint32_t* __restrict__ partial, int pb,
+                                                            uint32_t* __restrict__ out) {
+  __shared__ uint32_t lw[SC_THREADS / 64];
+  int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+  uint32_t v[SC_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i] & 0xffu;
+  }
+  uint32_t tot;
+  uint32_t inc = block_inclusive_scan(s, lw, tot);
+  uint32_t run = partial[blockIdx.x] + inc - s;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = (run << pb) | (v[i] >> 8);
+    run += v[i] & 0xffu;
+  }
+}
+
+int scan_packed(const uint32_t* in, uint32_t* out, int64_t n, int pb, uint32_t* total, Arena& ws, hipStream_t s) {
+  int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+  uint32_t* partial = ws.take<uint32_t>((size_t)nb + 1);
+  if (n == 0) return PHFEM_OK;
+  PH_LAUNCH_B("scanp_reduce", 4.0 * n, k_scanp_reduce, (unsigned)nb, SC_THREADS, 0, s, in, n, partial);
+  PH_LAUNCH("scan_partials", k_scan_partials, 1, SC_THREADS, 0, s, partial, nb, total);
+  PH_LAUNCH_B("scanp_apply", 8.0 * n, k_scanp_apply, (unsigned)nb, SC_THREADS, 0, s, in, n, (const uint32_t*)partial,
+              pb, out);
+  return PHFEM_OK;
+}
+
 // ------------------------------------------------------------------ radix sort
 constexpr int RS_BITS = 8;
 constexpr int RS_RADIX = 1 << RS_BITS;

@@ -103,26 +103,49 @@ static_assert(first3(0, false) == 4 && first3(3, false) == 5, "first (M, C)");
 
 __device__ __forceinline__ int loc4(const int a[4], int x) { return a[0] == x ? 0 : (a[1] == x ? 1 : (a[2] == x ? 2 : 3)); }
 
-constexpr int RCT = 128;
+// Run-time tables (a thread handles one refined row, so the child index is a run-time value)
+struct RuleTables {
+  int8_t f3c[6], f3j[6];  // first (octahedron child, local edge) holding (M_j, C)
+  int8_t fkind[48];       // per child*4 + local face: 0 inside, 1 corner triangle, 2 middle triangle
+  int8_t fco[48];         // coarse face of a kind-1/2 face
+  int8_t fpart[48];       // partner child*4 + local face of a kind-0 face
+};
+__host__ __device__ constexpr RuleTables make_tables() {
+  RuleTables T{};
+  for (int j = 0; j < 6; ++j) {
+    T.f3c[j] = (int8_t)first3(j, false);
+    T.f3j[j] = (int8_t)first3(j, true);
+  }
+  for (int c = 0; c < 12; ++c)
+    for (int kk = 0; kk < 4; ++kk) {
+      T.fkind[4 * c + kk] = (int8_t)fkind(c, kk);
+      T.fco[4 * c + kk] = (int8_t)(fkind(c, kk) ? fcoarse(c, kk) : 0);
+      T.fpart[4 * c + kk] = (int8_t)(fkind(c, kk) ? 0 : fpartner(c, kk));
+    }
+  return T;
+}
+__constant__ RuleTables c_rt = make_tables();
+
+constexpr int RCT = 256;
 
 struct RCArgs {
   int64_t nC, nE, nE2, nEd, nEd2, nF2;
-  const int32_t* tet;
-  const int32_t* t2e;
+  const int4* T4;  // AoS copies of the coarse tets, faces, neighbours, edges (e0..e3 | e4 e5 - -)
+  const int4* F4;
+  const int4* N4;
+  const int4* E8;
   const int32_t* eft;
   const int32_t* pre;
-  const int32_t* t2f;
-  const int32_t* nbr;
   const int32_t* minI;  // [2 nEd]: (t << 2 | j) of the lowest tet whose vertex I is that end
   const int32_t* efp;   // [nEd]: (6 t0 + j0) << 1 | (node at ev0(j0) is the larger end)
-  uint16_t* mask;       // [12 nE]: first-edge bits (0..5), owned-face bits (6..9)
-  uint32_t* cnt_e;
-  uint32_t* cnt_f;
-  const uint32_t* pre_e;
-  const uint32_t* pre_f;
+  uint32_t* inE;        // pass 1: count | first-edge mask << 8 per refined row
+  uint32_t* inF;        // pass 1: count | owned-face mask << 8
+  const uint32_t* recE; // after the scans: prefix << 6 | first-edge mask
+  const uint32_t* recF; // prefix << 4 | owned-face mask
   int32_t* edges2;
   int32_t* t2e2;
   int32_t* eft2;
+  int32_t* pre2;
   int32_t* faces2;
   int32_t* t2f2;
   int8_t* sig2;
@@ -132,201 +155,234 @@ struct RCArgs {
 
 __global__ __launch_bounds__(RCT) void k_rc_prep(int64_t nE, const int32_t* __restrict__ tet,
                                                  const int32_t* __restrict__ t2e, const int32_t* __restrict__ eft,
-                                                 int32_t* __restrict__ minI, int32_t* __restrict__ efp) {
+                                                 const int32_t* __restrict__ t2f, const int32_t* __restrict__ nbr,
+                                                 int32_t* __restrict__ minI, int32_t* __restrict__ efp,
+                                                 int4* __restrict__ T4, int4* __restrict__ F4, int4* __restrict__ N4,
+                                                 int4* __restrict__ E8) {
   int64_t t = (int64_t)blockIdx.x * RCT + threadIdx.x;
   if (t >= nE) return;
-  int n[4];
+  int n[4], e[6];
 #pragma unroll
   for (int i = 0; i < 4; ++i) n[i] = tet[i * nE + t];
 #pragma unroll
+  for (int j = 0; j < 6; ++j) e[j] = t2e[j * nE + t];
+  T4[t] = make_int4(n[0], n[1], n[2], n[3]);
+  F4[t] = make_int4(t2f[t], t2f[nE + t], t2f[2 * nE + t], t2f[3 * nE + t]);
+  int nb4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int v = nbr[i * nE + t];
+    nb4[i] = (v >= nE) ? -1 : v;  // inputs are trusted; clamps only keep later loads in range
+  }
+  N4[t] = make_int4(nb4[0], nb4[1], nb4[2], nb4[3]);
+  E8[2 * t] = make_int4(e[0], e[1], e[2], e[3]);
+  E8[2 * t + 1] = make_int4(e[4], e[5], 0, 0);
+#pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const int e = t2e[j * nE + t];
     const int a = n[ev0(j)], b = n[ev1(j)];
     const int lo = a < b ? a : b;
-    if (eft[e] == t) efp[e] = (int32_t)(((6 * t + j) << 1) | (a != lo ? 1 : 0));
-    if (j < 3) atomicMin(&minI[2 * e + (n[0] == lo ? 0 : 1)], (int32_t)((t << 2) | j));
+    if (eft[e[j]] == t) efp[e[j]] = (int32_t)(((6 * t + j) << 1) | (a != lo ? 1 : 0));
+    if (j < 3) atomicMin(&minI[2 * e[j] + (n[0] == lo ? 0 : 1)], (int32_t)((t << 2) | j));
   }
 }
 
-// per-coarse-tet state shared by the 12 children
-struct RCTet {
-  int64_t t;
-  int n[4], e[6], f[4], nb[4];
-  int nn[4][4], nf[4][4];  // neighbours' vertices and faces
-  int mI[6][2], ef[6], lo[6];
-  int sym_node[11];
-};
-
 __device__ __forceinline__ int64_t rowof(int64_t nE, int64_t tt, int c) { return c == 0 ? tt : nE + 11 * tt + (c - 1); }
+__device__ __forceinline__ int get4(const int4& v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)); }
+__device__ __forceinline__ int loc4v(const int4& v, int x) { return v.x == x ? 0 : (v.y == x ? 1 : (v.z == x ? 2 : 3)); }
 
-template <int PASS, int c>
-__device__ __forceinline__ void rc_child(const RCArgs& A, const RCTet& S) {
-  const int64_t nE = A.nE, t = S.t;
-  const int64_t r = rowof(nE, t, c);
-  int64_t er[6];
-  int ej[6];
-#pragma unroll
-  for (int jj = 0; jj < 6; ++jj) {
-    const int kind = ekind(c, jj);
-    if (kind == 3) {
-      er[jj] = rowof(nE, t, first3(esym_lo(c, jj) - 4, false));
-      ej[jj] = first3(esym_lo(c, jj) - 4, true);
-    } else if (kind == 1) {
-      const int a = esym_lo(c, jj), j = esym_hi(c, jj) - 4;
-      const int v = S.n[a];
-      const int end = (v == S.lo[j]) ? 0 : 1;
-      const int mi = S.mI[j][end];
-      if (mi != INT_MAX && (mi >> 2) < nE) {
-        er[jj] = mi >> 2;  // child 0 of that tet
-        ej[jj] = mi & 3;   // (I, m_j) is local edge j of child 0
-      } else {
-        int p = S.ef[j];
-        const int flip = p & 1;
-        p >>= 1;
-        const int t0 = p / 6, j0 = p - 6 * t0;
-        const int vl = ((v == S.lo[j]) != (flip != 0)) ? ev0(j0) : ev1(j0);
-        const bool ok = S.ef[j] >= 0 && t0 < nE;  // unset only for inconsistent input
-        er[jj] = ok ? rowof(nE, t0, vl) : r;
-        ej[jj] = ok ? posv(vl, j0) - 1 : jj;
-      }
-    } else {
-      const int i = esym_lo(c, jj) - 4, j = esym_hi(c, jj) - 4;
-      const int v = common_v(i, j), a = other_end(i, v), b = other_end(j, v);
-      const int k = face_with(v, a, b);
-      int64_t rr = rowof(nE, t, v);
-      int jr = eidx(posv(v, i), posv(v, j));
-      if (S.nb[k] >= 0) {
-        const int v2 = loc4(S.nn[k], S.n[v]), a2 = loc4(S.nn[k], S.n[a]), b2 = loc4(S.nn[k], S.n[b]);
-        const int le2 = eidx(posv(v2, eidx(v2, a2)), posv(v2, eidx(v2, b2)));
-        const int64_t r2 = rowof(nE, S.nb[k], v2);
-        if (6 * r2 + le2 < 6 * rr + jr) {
-          rr = r2;
-          jr = le2;
-        }
-      }
-      er[jj] = rr;
-      ej[jj] = jr;
-    }
+// One refined row: its coarse tet and child, the coarse data it needs.
+struct RCRow {
+  int64_t r, t;
+  int c;
+  int4 n, f, nb, e0, e1;  // e0 = edges 0..3, e1.xy = edges 4, 5
+};
+__device__ __forceinline__ int edge_of(const RCRow& R, int j) { return j < 4 ? get4(R.e0, j) : (j == 4 ? R.e1.x : R.e1.y); }
+
+__device__ __forceinline__ void rc_row(const RCArgs& A, int64_t r, RCRow& R) {
+  const int64_t nE = A.nE;
+  R.r = r;
+  if (r < nE) {
+    R.t = r;
+    R.c = 0;
+  } else {
+    const int64_t q = r - nE;
+    R.t = q / 11;
+    R.c = 1 + (int)(q - 11 * R.t);
   }
-  int64_t fr[4];
-  int fk[4];
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    const int kind = fkind(c, kk);
-    if (kind == 0) {
-      fr[kk] = rowof(nE, t, fpartner(c, kk) >> 2);
-      fk[kk] = fpartner(c, kk) & 3;
-    } else {
-      const int k = fcoarse(c, kk);
-      if (S.nb[k] < 0) {
-        fr[kk] = -1;
-        fk[kk] = 0;
-      } else {
-        const int k2 = loc4(S.nf[k], S.f[k]);
-        if (kind == 2) {
-          fr[kk] = rowof(nE, S.nb[k], 8 + k2);
-          fk[kk] = 0;
-        } else {
-          const int v2 = loc4(S.nn[k], S.n[c & 3]);  // corner child c holds vertex V_c
-          fr[kk] = rowof(nE, S.nb[k], v2);
-          fk[kk] = cornerface(v2, k2);
-        }
-      }
-    }
-  }
-  int me = 0, mf = 0;
-#pragma unroll
-  for (int jj = 0; jj < 6; ++jj) me |= (er[jj] == r && ej[jj] == jj) ? (1 << jj) : 0;
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) mf |= (fr[kk] < 0 || 4 * fr[kk] + fk[kk] > 4 * r + kk) ? (1 << kk) : 0;
-  if (PASS == 1) {
-    A.mask[r] = (uint16_t)(me | (mf << 6));
-    A.cnt_e[r] = (uint32_t)__popc(me);
-    A.cnt_f[r] = (uint32_t)__popc(mf);
+  R.n = A.T4[R.t];
+  R.f = A.F4[R.t];
+  R.nb = A.N4[R.t];
+  R.e0 = A.E8[2 * R.t];
+  R.e1 = A.E8[2 * R.t + 1];
+}
+
+__device__ __forceinline__ int ech(int c, int p) { return ch(c, p); }  // run-time c: shifts of packed constants
+
+// first occurrence (row, local edge) of local edge jj of this row's child
+__device__ __forceinline__ void edge_first_rt(const RCArgs& A, const RCRow& R, int jj, int64_t& er, int& ej) {
+  const int64_t nE = A.nE, t = R.t;
+  const int c = R.c;
+  const int s0 = ech(c, ev0(jj)), s1 = ech(c, ev1(jj));
+  const int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
+  if (hi == 10) {  // (M_j, C): inside t
+    er = rowof(nE, t, c_rt.f3c[lo - 4]);
+    ej = c_rt.f3j[lo - 4];
     return;
   }
-  const uint32_t pe = A.pre_e[r], pf = A.pre_f[r];
+  if (lo < 4) {  // (V_a, M_j): half of coarse edge e_j at node v
+    const int j = hi - 4;
+    const int e = edge_of(R, j);
+    const int v = get4(R.n, lo);
+    const int na = get4(R.n, ev0(j)), nb = get4(R.n, ev1(j));
+    const int lon = na < nb ? na : nb;
+    const int mi = A.minI[2 * e + (v == lon ? 0 : 1)];
+    if (mi != INT_MAX && (mi >> 2) < nE) {
+      er = mi >> 2;  // child 0 of that tet, local edge j of (I, m_j)
+      ej = mi & 3;
+      return;
+    }
+    const int p0 = A.efp[e];
+    const int flip = p0 & 1, p = p0 >> 1;
+    const int t0 = p / 6, j0 = p - 6 * t0;
+    const int vl = ((v == lon) != (flip != 0)) ? ev0(j0) : ev1(j0);
+    const bool ok = p0 >= 0 && t0 < nE;  // unset only for inconsistent input
+    er = ok ? rowof(nE, t0, vl) : R.r;
+    ej = ok ? posv(vl, j0) - 1 : jj;
+    return;
+  }
+  // (M_i, M_j) on a coarse face: corner child of the shared vertex, here or in the neighbour
+  const int i = lo - 4, j = hi - 4;
+  const int v = common_v(i, j), a = other_end(i, v), b = other_end(j, v);
+  const int k = face_with(v, a, b);
+  int64_t rr = rowof(nE, t, v);
+  int jr = eidx(posv(v, i), posv(v, j));
+  const int tn = get4(R.nb, k);
+  if (tn >= 0) {
+    const int4 nn = A.T4[tn];
+    const int v2 = loc4v(nn, get4(R.n, v)), a2 = loc4v(nn, get4(R.n, a)), b2 = loc4v(nn, get4(R.n, b));
+    const int le2 = eidx(posv(v2, eidx(v2, a2)), posv(v2, eidx(v2, b2)));
+    const int64_t r2 = rowof(nE, tn, v2);
+    if (6 * r2 + le2 < 6 * rr + jr) {
+      rr = r2;
+      jr = le2;
+    }
+  }
+  er = rr;
+  ej = jr;
+}
+
+// other occurrence (row, local face) of local face kk of this row's child; row -1 on the boundary
+__device__ __forceinline__ void face_other_rt(const RCArgs& A, const RCRow& R, int kk, int64_t& fr, int& fk) {
+  const int64_t nE = A.nE;
+  const int idx = 4 * R.c + kk;
+  const int kind = c_rt.fkind[idx];
+  if (kind == 0) {
+    const int p = c_rt.fpart[idx];
+    fr = rowof(nE, R.t, p >> 2);
+    fk = p & 3;
+    return;
+  }
+  const int k = c_rt.fco[idx];
+  const int tn = get4(R.nb, k);
+  if (tn < 0) {
+    fr = -1;
+    fk = 0;
+    return;
+  }
+  const int k2 = loc4v(A.F4[tn], get4(R.f, k));
+  if (kind == 2) {
+    fr = rowof(nE, tn, 8 + k2);
+    fk = 0;
+  } else {
+    const int v2 = loc4v(A.T4[tn], get4(R.n, R.c & 3));  // corner child c holds vertex V_c
+    fr = rowof(nE, tn, v2);
+    fk = cornerface(v2, k2);
+  }
+}
+
+// pass 1: count | mask << 8 of first edges and owned faces for every refined row
+__global__ __launch_bounds__(RCT) void k_rc_pass1(RCArgs A) {
+  const int64_t r = (int64_t)blockIdx.x * RCT + threadIdx.x;
+  if (r >= A.nE2) return;
+  RCRow R;
+  rc_row(A, r, R);
+  int me = 0, mf = 0;
+#pragma unroll
+  for (int jj = 0; jj < 6; ++jj) {
+    int64_t er;
+    int ej;
+    edge_first_rt(A, R, jj, er, ej);
+    me |= (er == r && ej == jj) ? (1 << jj) : 0;
+  }
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    int64_t fr;
+    int fk;
+    face_other_rt(A, R, kk, fr, fk);
+    mf |= (fr < 0 || 4 * fr + fk > 4 * r + kk) ? (1 << kk) : 0;
+  }
+  A.inE[r] = (uint32_t)__popc(me) | ((uint32_t)me << 8);
+  A.inF[r] = (uint32_t)__popc(mf) | ((uint32_t)mf << 8);
+}
+
+__device__ __forceinline__ int sym_node(const RCArgs& A, const RCRow& R, int sym) {
+  if (sym < 4) return get4(R.n, sym);
+  if (sym < 10) {
+    const int e = edge_of(R, sym - 4);
+    return (int)(A.nC + A.eft[e] + e + 1);
+  }
+  return (int)(A.nC + R.t + A.pre[R.t]);
+}
+
+// pass 2: ids of the refined edges and faces of every row, and all outputs
+__global__ __launch_bounds__(RCT) void k_rc_pass2(RCArgs A) {
+  const int64_t r = (int64_t)blockIdx.x * RCT + threadIdx.x;
+  if (r >= A.nE2) return;
+  RCRow R;
+  rc_row(A, r, R);
+  const int c = R.c;
+  const uint32_t oe = A.recE[r], of = A.recF[r];
+  const int me = oe & 63, mf = of & 15;
+  A.pre2[r] = (int32_t)(oe >> 6);
 #pragma unroll
   for (int jj = 0; jj < 6; ++jj) {
     int32_t id;
     if ((me >> jj) & 1) {
-      id = (int32_t)(pe + __popc(me & ((1 << jj) - 1)));
-      const int na = S.sym_node[ch(c, ev0(jj))], nbn = S.sym_node[ch(c, ev1(jj))];
-      A.edges2[id] = na < nbn ? na : nbn;
-      A.edges2[A.nEd2 + id] = na < nbn ? nbn : na;
+      id = (int32_t)((oe >> 6) + __popc(me & ((1 << jj) - 1)));
+      const int na = sym_node(A, R, ech(c, ev0(jj))), nb = sym_node(A, R, ech(c, ev1(jj)));
+      A.edges2[id] = na < nb ? na : nb;
+      A.edges2[A.nEd2 + id] = na < nb ? nb : na;
       A.eft2[id] = (int32_t)r;
     } else {
-      const int m2 = A.mask[er[jj]] & 63;
-      id = (int32_t)(A.pre_e[er[jj]] + __popc(m2 & ((1 << ej[jj]) - 1)));
+      int64_t er;
+      int ej;
+      edge_first_rt(A, R, jj, er, ej);
+      const uint32_t o = A.recE[er];
+      id = (int32_t)((o >> 6) + __popc((o & 63) & ((1u << ej) - 1)));
     }
     A.t2e2[jj * A.nE2 + r] = id;
   }
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
+    int64_t fr;
+    int fk;
+    face_other_rt(A, R, kk, fr, fk);
     const bool own = (mf >> kk) & 1;
     int32_t id;
     if (own) {
-      id = (int32_t)(pf + __popc(mf & ((1 << kk) - 1)));
+      id = (int32_t)((of >> 4) + __popc(mf & ((1 << kk) - 1)));
       A.f2t2[id] = (int32_t)(4 * r + kk);
-      A.f2t2[A.nF2 + id] = fr[kk] < 0 ? -1 : (int32_t)(4 * fr[kk] + fk[kk]);
+      A.f2t2[A.nF2 + id] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
 #pragma unroll
-      for (int m = 0; m < 3; ++m) A.faces2[m * A.nF2 + id] = S.sym_node[fs(c, kk, m)];
+      for (int m = 0; m < 3; ++m) A.faces2[m * A.nF2 + id] = sym_node(A, R, ech(c, fv(kk, m)));
     } else {
-      const int m2 = A.mask[fr[kk]] >> 6;
-      id = (int32_t)(A.pre_f[fr[kk]] + __popc(m2 & ((1 << fk[kk]) - 1)));
+      const uint32_t o = A.recF[fr];
+      id = (int32_t)((o >> 4) + __popc((o & 15) & ((1u << fk) - 1)));
     }
     A.t2f2[kk * A.nE2 + r] = id;
     A.sig2[kk * A.nE2 + r] = own ? 1 : -1;
-    A.nbr2[kk * A.nE2 + r] = fr[kk] < 0 ? -1 : (int32_t)fr[kk];
+    A.nbr2[kk * A.nE2 + r] = fr < 0 ? -1 : (int32_t)fr;
   }
-}
-
-template <int PASS, int... Cs>
-__device__ __forceinline__ void rc_children(const RCArgs& A, const RCTet& S, std::integer_sequence<int, Cs...>) {
-  (rc_child<PASS, Cs>(A, S), ...);
-}
-
-template <int PASS>
-__global__ __launch_bounds__(RCT) void k_refconn(RCArgs A) {
-  RCTet S;
-  S.t = (int64_t)blockIdx.x * RCT + threadIdx.x;
-  if (S.t >= A.nE) return;
-  const int64_t nE = A.nE, t = S.t;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    S.n[i] = A.tet[i * nE + t];
-    S.f[i] = A.t2f[i * nE + t];
-    const int v = A.nbr[i * nE + t];
-    S.nb[i] = (v >= nE) ? -1 : v;  // inputs are trusted; clamps only keep loads in range
-  }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int v = A.t2e[j * nE + t];
-    S.e[j] = (v < 0 || v >= A.nEd) ? 0 : v;
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      S.nn[k][m] = S.nb[k] >= 0 ? A.tet[m * nE + S.nb[k]] : -1;
-      S.nf[k][m] = S.nb[k] >= 0 ? A.t2f[m * nE + S.nb[k]] : -1;
-    }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int a = S.n[ev0(j)], b = S.n[ev1(j)];
-    S.lo[j] = a < b ? a : b;
-    S.mI[j][0] = A.minI[2 * S.e[j]];
-    S.mI[j][1] = A.minI[2 * S.e[j] + 1];
-    S.ef[j] = A.efp[S.e[j]];
-  }
-  if (PASS == 2) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) S.sym_node[i] = S.n[i];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) S.sym_node[4 + j] = (int)(A.nC + A.eft[S.e[j]] + S.e[j] + 1);
-    S.sym_node[10] = (int)(A.nC + t + A.pre[t]);
-  }
-  rc_children<PASS>(A, S, std::make_integer_sequence<int, 12>{});
 }
 
 __global__ __launch_bounds__(RCT) void k_fill_i32(int64_t n, int32_t v, int32_t* __restrict__ a) {
@@ -335,8 +391,8 @@ __global__ __launch_bounds__(RCT) void k_fill_i32(int64_t n, int32_t v, int32_t*
 
 struct RCWS {
   int32_t *minI, *efp;
-  uint16_t* mask;
-  uint32_t *cnt_e, *cnt_f, *pre_f, *tot;
+  int4 *T4, *F4, *N4, *E8;
+  uint32_t *inE, *inF, *recF, *tot;
   size_t sub;
 };
 
@@ -344,10 +400,13 @@ static void rc_layout(Arena& a, int64_t nE, int64_t nEd, RCWS& w) {
   const int64_t n2 = 12 * nE;
   w.minI = a.take<int32_t>(2 * nEd);
   w.efp = a.take<int32_t>(nEd);
-  w.mask = a.take<uint16_t>(n2);
-  w.cnt_e = a.take<uint32_t>(n2);
-  w.cnt_f = a.take<uint32_t>(n2);
-  w.pre_f = a.take<uint32_t>(n2);
+  w.T4 = a.take<int4>(nE);
+  w.F4 = a.take<int4>(nE);
+  w.N4 = a.take<int4>(nE);
+  w.E8 = a.take<int4>(2 * nE);
+  w.inE = a.take<uint32_t>(n2);
+  w.inF = a.take<uint32_t>(n2);
+  w.recF = a.take<uint32_t>(n2);
   w.tot = a.take<uint32_t>(16);
   w.sub = a.size();
 }
@@ -398,8 +457,8 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   PH_LAUNCH("fill_i32", k_fill_i32, (unsigned)std::min<int64_t>(grid_for(2 * nEd, RCT), 4096), RCT, 0, s, 2 * nEd,
             (int32_t)INT_MAX, w.minI);
   PH_LAUNCH("fill_i32", k_fill_i32, (unsigned)std::min<int64_t>(grid_for(nEd, RCT), 4096), RCT, 0, s, nEd, -1, w.efp);
-  PH_LAUNCH_B("rc_prep", 44.0 * nE + 12.0 * nEd, k_rc_prep, grid_for(nE, RCT), RCT, 0, s, nE, tetra, tet2edge,
-              edge_first_tet, w.minI, w.efp);
+  PH_LAUNCH_B("rc_prep", 60.0 * nE + 12.0 * nEd + 80.0 * nE, k_rc_prep, grid_for(nE, RCT), RCT, 0, s, nE, tetra,
+              tet2edge, edge_first_tet, tet2face, nbr, w.minI, w.efp, w.T4, w.F4, w.N4, w.E8);
   RCArgs A;
   A.nC = nC;
   A.nE = nE;
@@ -407,40 +466,40 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   A.nEd = nEd;
   A.nEd2 = nEd2;
   A.nF2 = nF2;
-  A.tet = tetra;
-  A.t2e = tet2edge;
+  A.T4 = w.T4;
+  A.F4 = w.F4;
+  A.N4 = w.N4;
+  A.E8 = w.E8;
   A.eft = edge_first_tet;
   A.pre = tet_edge_prefix;
-  A.t2f = tet2face;
-  A.nbr = nbr;
   A.minI = w.minI;
   A.efp = w.efp;
-  A.mask = w.mask;
-  A.cnt_e = w.cnt_e;
-  A.cnt_f = w.cnt_f;
-  A.pre_e = (const uint32_t*)tet_edge_prefix_out;
-  A.pre_f = w.pre_f;
+  A.inE = w.inE;
+  A.inF = w.inF;
+  A.recE = w.inE;  // the edge scan writes its records in place
+  A.recF = w.recF;
   A.edges2 = edges_out;
   A.t2e2 = tet2edge_out;
   A.eft2 = edge_first_tet_out;
+  A.pre2 = tet_edge_prefix_out;
   A.faces2 = faces_out;
   A.t2f2 = tet2face_out;
   A.sig2 = sigma_out;
   A.f2t2 = face2tet_out;
   A.nbr2 = nbr_out;
-  // pass 1 reads the coarse tet, faces, neighbours (+ their tets and faces) and edge data;
-  // writes a mask and two counts per refined tet
-  const double b1 = (16.0 + 24 + 16 + 16 + 12) * nE + 12.0 * nEd + 10.0 * nE2;
-  PH_LAUNCH_B("refconn_pass1", b1, k_refconn<1>, grid_for(nE, RCT), RCT, 0, s, A);
+  // pass 1 reads the coarse AoS data once (cache-shared by the 12 rows of a tet) and writes
+  // two words per refined row
+  PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, grid_for(nE2, RCT), RCT, 0, s, A);
   a.off = w.sub;
-  rc = scan_exclusive(w.cnt_e, (uint32_t*)tet_edge_prefix_out, nE2, w.tot, a, s);
+  rc = scan_packed(w.inE, w.inE, nE2, 6, w.tot, a, s);
   if (rc) return rc;
   a.off = w.sub;
-  rc = scan_exclusive(w.cnt_f, w.pre_f, nE2, w.tot + 1, a, s);
+  rc = scan_packed(w.inF, w.recF, nE2, 4, w.tot + 1, a, s);
   if (rc) return rc;
-  // pass 2 also writes every refined connectivity array once
-  const double b2 = b1 - 8.0 * nE2 + 10.0 * nE2 + (24.0 + 16 + 4 + 16) * nE2 + 12.0 * nEd2 + 20.0 * nF2;
-  PH_LAUNCH_B("refconn_pass2", b2, k_refconn<2>, grid_for(nE, RCT), RCT, 0, s, A);
+  // pass 2 writes every refined connectivity array once
+  PH_LAUNCH_B("refconn_pass2", 80.0 * nE + 12.0 * nEd + 8.0 * nE2 + (24.0 + 4 + 16 + 1 * 4 + 16) * nE2 + 12.0 * nEd2 +
+                                   20.0 * nF2,
+              k_rc_pass2, grid_for(nE2, RCT), RCT, 0, s, A);
   uint32_t tot[2] = {0, 0};
   PH_HIP(hipMemcpyAsync(tot, w.tot, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PH_HIP(hipStreamSynchronize(s));
