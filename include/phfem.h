@@ -137,7 +137,9 @@ int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, v
  * nDb + nNb > 0).  Outputs: coord_out[3][nC + nEd + nE], tetra_out[4][12 nE],
  * db_out[3][4 nDb], nb_out[3][4 nNb] (row strides = those counts).  Coordinates are
  * bitwise those of the paper's formulas.  Synchronizes only when nDb + nNb > 0
- * (EINVAL if a boundary face is not a mesh face). */
+ * (EINVAL if a boundary face is not a mesh face).  A tet whose vertex, edge or derived
+ * node ids fall outside the mesh is skipped (its outputs are left unwritten, nothing is
+ * written out of range); phfem_refine_connected reports such input. */
 int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
                  const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
                  const int32_t* n2e_rowptr, const int32_t* n2e_col, const int32_t* n2e_edge, int64_t nDb,
@@ -152,8 +154,16 @@ int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tet
  * outputs.  Refined sizes: nC' = nC + nEd + nE, nE' = 12 nE, nEd' = 2 nEd + 3 nF + 6 nE,
  * nF' = 4 nF + 16 nE, nB' = 2 nF' - 4 nE' (written to counts[3] = {nEd', nF', nB'}); output
  * arrays are packed SoA with those strides (capacities = these sizes).  No boundary face
- * lists (use phfem_refine for Db/Nb).  Synchronizes once; EINVAL if the refined counts
- * disagree with the recurrences (input not a first-appearance numbering). */
+ * lists (use phfem_refine for Db/Nb).
+ * Input check: the refined edge and face totals found by the kernels must equal the
+ * recurrences above (they do exactly when the input is a first-appearance numbering of a
+ * conforming, consistently oriented mesh), and every vertex id, tet2edge id and derived
+ * refined node id must lie in range.
+ * status == NULL: synchronizes once and returns EINVAL on failure.  status != NULL (device
+ * int32, caller-owned): nothing synchronizes; on failure the call ORs 1 (an id out of
+ * range) or 2 (totals differ) into *status, so one zeroed word can collect a whole chain of
+ * levels and be read once at the end.  The outputs of a failed check are unspecified (no
+ * write leaves the output arrays either way). */
 size_t phfem_refine_connected_workspace(int64_t nE, int64_t nEd);
 int phfem_refine_connected(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd, int64_t nF,
                            const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
@@ -161,7 +171,7 @@ int phfem_refine_connected(int64_t nC, const double* coord, int64_t nE, const in
                            double* coord_out, int32_t* tetra_out, int32_t* edges_out, int32_t* tet2edge_out,
                            int32_t* edge_first_tet_out, int32_t* tet_edge_prefix_out, int32_t* faces_out,
                            int32_t* tet2face_out, int8_t* sigma_out, int32_t* face2tet_out, int32_t* nbr_out,
-                           int64_t* counts, phfem_stream_t stream);
+                           int64_t* counts, int32_t* status, phfem_stream_t stream);
 
 /* ---------------------------------------------------------------- assemble (a5-a6) --- */
 /* Per-tet local blocks (Sections 4.2-4.5; StiffMassPH, Multiplier, the page solves of

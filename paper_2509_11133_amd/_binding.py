@@ -90,7 +90,7 @@ def lib():
         L.phfem_solve_workspace.argtypes = [I64, I64, I32]
         L.phfem_grad_workspace.argtypes = [I64, I64, I32]
         L.phfem_refine_connected_workspace.argtypes = [I64, I64]
-        L.phfem_refine_connected.argtypes = [I64, VP, I64, VP, I64, I64] + [VP] * 5 + [VP, SZ] + [VP] * 11 + [VP, VP]
+        L.phfem_refine_connected.argtypes = [I64, VP, I64, VP, I64, I64] + [VP] * 5 + [VP, SZ] + [VP] * 11 + [VP] * 3
         L.phfem_connect.argtypes = [I64, I64, VP, I32, VP, SZ] + [VP] * 12 + [VP, VP]
         L.phfem_refine.argtypes = [I64, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP]
         L.phfem_assemble.argtypes = [I64, VP, I64, VP, VP, VP, VP] + [VP] * 6 + [VP]
@@ -148,13 +148,14 @@ def phfem_refine(nC, coord, nE, tetra, nEd, tet2edge, edge_first_tet, tet_edge_p
 
 def phfem_refine_connected(nC, coord, nE, tetra, nEd, nF, tet2edge, edge_first_tet, tet_edge_prefix, tet2face, nbr,
                            work, coord_out, tetra_out, edges_out, tet2edge_out, edge_first_tet_out,
-                           tet_edge_prefix_out, faces_out, tet2face_out, sigma_out, face2tet_out, nbr_out, counts):
+                           tet_edge_prefix_out, faces_out, tet2face_out, sigma_out, face2tet_out, nbr_out, counts,
+                           status=None):
     _chk(lib().phfem_refine_connected(nC, _p(coord), nE, _p(tetra), nEd, nF, _p(tet2edge), _p(edge_first_tet),
                                       _p(tet_edge_prefix), _p(tet2face), _p(nbr), _p(work), work.numel(),
                                       _p(coord_out), _p(tetra_out), _p(edges_out), _p(tet2edge_out),
                                       _p(edge_first_tet_out), _p(tet_edge_prefix_out), _p(faces_out),
                                       _p(tet2face_out), _p(sigma_out), _p(face2tet_out), _p(nbr_out), _p(counts),
-                                      _stream()))
+                                      _p(status), _stream()))
 
 
 def phfem_assemble(nC, coord, nE, tetra, sigma, kappa, prm, vol, K, d, B, S, r):

@@ -29,7 +29,8 @@ struct Elem {
   R icv;            // 1 / (c vol)
   R kappa, c;
 
-  // x: vertex coordinates (FP64).  Returns false for a zero-volume tet.
+  // x: vertex coordinates (FP64).  Returns false for a zero-volume tet; its d (and with it
+  // every S_kl and r_k) is then zero and the other members are finite placeholders.
   __device__ __forceinline__ bool init(const double x[4][3], double kap, double cc, const int sig[4]) {
     double v[3][3];
 #pragma unroll
@@ -38,8 +39,9 @@ struct Elem {
       for (int e = 0; e < 3; ++e) v[i][e] = x[i + 1][e] - x[0][e];
     det = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) - v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
           v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
-    if (det == 0.0) return false;
-    vol = fabs(det) / 6.0;
+    const bool ok = det != 0.0;
+    if (!ok) det = 1.0;
+    vol = fabs(det) * (1.0 / 6.0);
     kappa = (R)kap;
     c = (R)cc;
     R w[4][3];  // vertex positions relative to vertex 0
@@ -62,14 +64,13 @@ struct Elem {
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e) g[0][e] = -(g[1][e] + g[2][e] + g[3][e]);
-    // |F_k| = 0.5 |(x3 - x1) x (x2 - x1)| for the face tuple [x1 x2 x3]
+    // face k lies opposite vertex opp(k), and |grad lambda_i| = |F_i| / (3 |T|), so
+    // |F_k| = 3 |T| |g_opp(k)|
+    const R v3 = ok ? (R)(3.0 * vol) : (R)0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int a = fv(k, 0), b = fv(k, 1), cc3 = fv(k, 2);
-      R u0 = w[cc3][0] - w[a][0], u1 = w[cc3][1] - w[a][1], u2 = w[cc3][2] - w[a][2];
-      R s0 = w[b][0] - w[a][0], s1 = w[b][1] - w[a][1], s2 = w[b][2] - w[a][2];
-      R n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
-      d[k] = (R)sig[k] * (R)0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+      const R* gk = g[opp(k)];
+      d[k] = (R)sig[k] * v3 * sqrt(gk[0] * gk[0] + gk[1] * gk[1] + gk[2] * gk[2]);
     }
     // W = Q N^-1 Q'
     R gh[3][3];
@@ -79,7 +80,7 @@ struct Elem {
       gh[1][e] = (R)0.5 * (g[0][e] - g[1][e] + g[2][e] - g[3][e]);
       gh[2][e] = (R)0.5 * (g[0][e] - g[1][e] - g[2][e] + g[3][e]);
     }
-    const R kv = kappa * (R)vol, mv = c * (R)vol / (R)20;
+    const R kv = kappa * (R)vol, mv = c * (R)vol * (R)(1.0 / 20.0);
     R N[3][3];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
@@ -121,10 +122,21 @@ struct Elem {
         W[j][i] = W[i][j];
       }
     icv = (R)(1.0 / (cc * vol));
-    return true;
+    return ok;
   }
 
-  __device__ __forceinline__ R S(int k, int l) const { return d[k] * d[l] * (icv + W[opp(k)][opp(l)] / (R)9); }
+  // the 10 distinct entries of the symmetric S(T), row-major upper triangle
+  __device__ __forceinline__ void Supper(R s[10]) const {
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int l = k; l < 4; ++l) s[n++] = S(k, l);
+  }
+
+  __device__ __forceinline__ R S(int k, int l) const {
+    return d[k] * d[l] * (icv + W[opp(k)][opp(l)] * (R)(1.0 / 9.0));
+  }
 
   // r_k = (C A^-1 y)_k for a load-like vector y
   __device__ __forceinline__ void CAinv(const R y[4], R r[4]) const {
@@ -133,34 +145,40 @@ struct Elem {
     for (int k = 0; k < 4; ++k) {
       const int o = opp(k);
       R wy = W[o][0] * y[0] + W[o][1] * y[1] + W[o][2] * y[2] + W[o][3] * y[3];
-      r[k] = d[k] * (sy * icv - wy / (R)3);
+      r[k] = d[k] * (sy * icv - wy * (R)(1.0 / 3.0));
     }
   }
 };
 
-// load vector of one tet (StiffMassPH's face-centroid rule or b = M f(x_i))
+// load vector of one tet (StiffMassPH's face-centroid rule or b = M f(x_i)); the points are
+// formed in the working precision R
 template <class R>
 __device__ __forceinline__ void load_vec(const double x[4][3], double vol, const DevParams& P, R B[4]) {
+  R xr[4][3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) xr[i][e] = (R)x[i][e];
   if (P.quad == PHFEM_QUAD_P1_INTERP) {
     R f[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) f[i] = fun_at<R>(P.fk, P.fp, (R)x[i][0], (R)x[i][1], (R)x[i][2]);
+    for (int i = 0; i < 4; ++i) f[i] = fun_at<R>(P.fk, P.fp, xr[i][0], xr[i][1], xr[i][2]);
     R sf = (f[0] + f[1]) + (f[2] + f[3]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) B[i] = (R)vol / (R)20 * (sf + f[i]);
+    for (int i = 0; i < 4; ++i) B[i] = (R)vol * (R)(1.0 / 20.0) * (sf + f[i]);
     return;
   }
   R fc[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int a = fv(k, 0), b = fv(k, 1), c = fv(k, 2);
-    double cx = (x[a][0] + x[b][0] + x[c][0]) / 3.0;
-    double cy = (x[a][1] + x[b][1] + x[c][1]) / 3.0;
-    double cz = (x[a][2] + x[b][2] + x[c][2]) / 3.0;
-    fc[k] = fun_at<R>(P.fk, P.fp, (R)cx, (R)cy, (R)cz);
+    R cx = (xr[a][0] + xr[b][0] + xr[c][0]) * (R)(1.0 / 3.0);
+    R cy = (xr[a][1] + xr[b][1] + xr[c][1]) * (R)(1.0 / 3.0);
+    R cz = (xr[a][2] + xr[b][2] + xr[c][2]) * (R)(1.0 / 3.0);
+    fc[k] = fun_at<R>(P.fk, P.fp, cx, cy, cz);
   }
   // vertex i lies on the three faces other than the one opposite it (opp(i))
-  const R w = (R)vol / (R)12;
+  const R w = (R)vol * (R)(1.0 / 12.0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) B[i] = w * (((fc[0] + fc[1]) + (fc[2] + fc[3])) - fc[opp(i)]);
 }
@@ -248,118 +266,114 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
   rhs[f] = b;
 }
 
-// One tet: element Schur block, off-diagonals written in place (single writer each),
-// diagonal and rhs summed with FP64 atomics onto exact zeros / b_D (at most two terms).
-template <class R>
-__global__ __launch_bounds__(FT) void k_condense(int64_t nC, const double* __restrict__ X, int64_t nE,
-                                                 const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
-                                                 const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
-                                                 const double* __restrict__ kappa, DevParams P,
-                                                 const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                                                 double* __restrict__ val, double* __restrict__ diag,
-                                                 double* __restrict__ rhs) {
-  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
-  if (t >= nE) return;
-  int v[4], sig[4], F[4], nb[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    v[i] = tet[i * nE + t];
-    sig[i] = sigma[i * nE + t];
-    F[i] = t2f[i * nE + t];
-    nb[i] = nbr[i * nE + t];
-  }
-  double x[4][3];
-  gather_x(nC, X, v, x);
-  const double kap = kappa ? kappa[t] : P.kc;
-  Elem<R> E;
-  if (!E.init(x, kap, P.c, sig)) return;
-  R B[4], r[4];
-  load_vec<R>(x, E.vol, P, B);
-  E.CAinv(B, r);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int Fk = F[k];
-    int o[4] = {-1, -1, -1, -1};
-    if (nb[k] >= 0) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        int g = t2f[m * nE + nb[k]];
-        o[m] = (g == Fk) ? -1 : g;
-      }
-    }
-    const int base = rowptr[Fk];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      if (l == k) continue;
-      const int Fl = F[l];
-      int pos = 0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        pos += (m != k && F[m] < Fl) ? 1 : 0;
-        pos += (o[m] >= 0 && o[m] < Fl) ? 1 : 0;
-      }
-      col[base + pos] = Fl;
-      val[base + pos] = (double)E.S(k, l);
-    }
-    atomicAdd(&diag[Fk], (double)E.S(k, k));
-    atomicAdd(&rhs[Fk], -(double)r[k]);
-  }
-}
-
 // Condensation in two coalesced passes (no atomics):
-//  k_elem_rec: one tet -> one contiguous record {S (10 unique, row-major upper), r (4), the
-//              tet's 4 face ids};
+//  k_elem_rec: one tet -> four slot records (row k of S(T), (C A^-1 B)_k and the ids of the
+//              other three faces), each stored at its face: rec[F] from the owner (sigma = +1),
+//              rec[nF + F] from the neighbour, so the face pass reads both sides contiguously;
 //  k_face_rows: one face -> its whole CSR row from the records of its owner and neighbour:
 //              off-diagonals sorted by column, diagonal S_owner + S_neighbour and
 //              rhs (b_D - r_owner) - r_neighbour in that order.
-template <class R>
-struct alignas(16) ElemRec {
-  R s[10];
-  R r[4];
-  int32_t f[4];
-};
-
+// position of S_kl (either order) in the row-major upper triangle of a 4x4 matrix
 __host__ __device__ constexpr int uidx(int k, int l) {
-  return k <= l ? k * 4 - k * (k - 1) / 2 + (l - k) : l * 4 - l * (l - 1) / 2 + (k - l);
+  return k <= l ? (k * (7 - k)) / 2 + l : (l * (7 - l)) / 2 + k;
 }
-static_assert(uidx(0, 3) == 3 && uidx(1, 1) == 4 && uidx(3, 2) == 8 && uidx(3, 3) == 9, "upper-triangle index");
+static_assert(uidx(0, 0) == 0 && uidx(0, 3) == 3 && uidx(1, 1) == 4 && uidx(2, 1) == 5 && uidx(2, 2) == 7 &&
+                  uidx(3, 3) == 9,
+              "upper-triangle index");
 
+template <class R>
+struct SlotRec {  // row k of one tet's element Schur block S(T) and (C A^-1 B)_k
+  R d;            // S_kk
+  R r;            // (C A^-1 B)_k
+  R o[3];         // S_kl for the three l != k, ascending l
+  int32_t c[3];   // face ids of those three l
+};
+static_assert(sizeof(SlotRec<float>) == 32 && sizeof(SlotRec<double>) == 56, "packed slot records");
+
+// Faces are numbered by (owner tet, local face), so the faces owned by one workgroup's tets
+// form one contiguous id range: the first CAP of their records are staged in LDS and written
+// out with coalesced stores; the rest, and the records of faces owned by another tet
+// (sigma = -1), go out directly.
 template <class R>
 __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double* __restrict__ X, int64_t nE,
                                                  const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                                  const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
-                                                 DevParams P, ElemRec<R>* __restrict__ recs, int* __restrict__ flags) {
-  int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
-  if (t >= nE) return;
-  int v[4], sig[4];
-  ElemRec<R> rec;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    v[i] = tet[i * nE + t];
-    sig[i] = sigma[i * nE + t];
-    rec.f[i] = t2f[i * nE + t];
+                                                 DevParams P, int64_t nF, SlotRec<R>* __restrict__ recs) {
+  constexpr int W = sizeof(SlotRec<R>) / 8;
+  constexpr int CAP = 5 * FT / 2;  // staged records per workgroup (about 2 owned faces per tet)
+  __shared__ uint2 lrec[CAP * W];
+  __shared__ int sbase, scount;
+  const int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
+  const bool valid = t < nE;
+  if (threadIdx.x == 0) {
+    sbase = INT_MAX;
+    scount = 0;
   }
-  double x[4][3];
-  gather_x(nC, X, v, x);
-  const double kap = kappa ? kappa[t] : P.kc;
-  Elem<R> E;
-  if (!E.init(x, kap, P.c, sig)) {
-    if (flags) atomicOr(flags, DEV_DEGEN);
+  int v[4] = {0, 0, 0, 0}, sig[4] = {0, 0, 0, 0}, F[4] = {-1, -1, -1, -1};
+  int mymin = INT_MAX, mycnt = 0;
+  if (valid) {
 #pragma unroll
-    for (int i = 0; i < 10; ++i) rec.s[i] = (R)0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) rec.r[i] = (R)0;
-    recs[t] = rec;
-    return;
+    for (int i = 0; i < 4; ++i) {
+      v[i] = tet[i * nE + t];
+      sig[i] = sigma[i * nE + t];
+      F[i] = t2f[i * nE + t];
+      if ((uint32_t)F[i] >= (uint64_t)nF) F[i] = -1;
+      if (F[i] >= 0 && sig[i] > 0) {
+        mymin = F[i] < mymin ? F[i] : mymin;
+        ++mycnt;
+      }
+    }
   }
-  R B[4];
-  load_vec<R>(x, E.vol, P, B);
-  E.CAinv(B, rec.r);
+  __syncthreads();
+  if (mycnt) {
+    atomicMin(&sbase, mymin);
+    atomicAdd(&scount, mycnt);
+  }
+  __syncthreads();
+  const int base = sbase, cnt = scount;
+  if (valid) {
+    double x[4][3];
+    gather_x(nC, X, v, x);
+    const double kap = kappa ? kappa[t] : P.kc;
+    Elem<R> E;
+    E.init(x, kap, P.c, sig);  // a degenerate tet contributes zeros (d = 0)
+    R B[4], r[4], su[10];
+    load_vec<R>(x, E.vol, P, B);
+    E.CAinv(B, r);
+    E.Supper(su);
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+      if (F[k] < 0) continue;
+      union {
+        SlotRec<R> rec;
+        uint2 w[W];
+      } u;
+      u.rec.d = su[uidx(k, k)];
+      u.rec.r = r[k];
+      int n = 0;
 #pragma unroll
-    for (int l = k; l < 4; ++l) rec.s[uidx(k, l)] = E.S(k, l);
-  recs[t] = rec;
+      for (int l = 0; l < 4; ++l) {
+        if (l == k) continue;
+        u.rec.o[n] = su[uidx(k, l)];
+        u.rec.c[n] = F[l];
+        ++n;
+      }
+      const int li = F[k] - base;
+      if (sig[k] > 0 && li >= 0 && li < CAP) {
+#pragma unroll
+        for (int m = 0; m < W; ++m) lrec[li * W + m] = u.w[m];
+      } else {
+        recs[(sig[k] > 0 ? 0 : nF) + F[k]] = u.rec;
+      }
+    }
+  }
+  __syncthreads();
+  if (cnt > 0) {
+    int64_t n = cnt < CAP ? cnt : CAP;
+    if (base + n > nF) n = nF - base;
+    uint2* out = reinterpret_cast<uint2*>(recs + base);
+    for (int i = threadIdx.x; i < n * W; i += FT) out[i] = lrec[i];
+  }
 }
 
 // The rows of one workgroup's faces form one contiguous range of the CSR arrays: they are
@@ -368,7 +382,7 @@ template <class R>
 __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const double* __restrict__ X,
                                                   const int32_t* __restrict__ faces,
                                                   const int32_t* __restrict__ face2tet, DevParams P,
-                                                  const ElemRec<R>* __restrict__ recs,
+                                                  const SlotRec<R>* __restrict__ recs,
                                                   const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
                                                   double* __restrict__ val, double* __restrict__ diag,
                                                   double* __restrict__ rhs) {
@@ -380,12 +394,12 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
   const int blo = rowptr[f0];
   const int bhi = rowptr[fend];
   if (f < nF) {
-    const int q0 = face2tet[f], q1 = face2tet[nF + f];
+    const bool interior = face2tet[nF + f] >= 0;
     int cf[6];
     double cv[6];
     int n = 0;
     double dg = 0.0, rh = 0.0;
-    if (q1 < 0 && P.uk != PHFEM_FUN_ZERO) {  // b_D = |F| u_D(centroid) on a boundary face
+    if (!interior && P.uk != PHFEM_FUN_ZERO) {  // b_D = |F| u_D(centroid) on a boundary face
       double xx[3][3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
@@ -401,36 +415,32 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
                                  (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
     }
     {
-      const ElemRec<R>* a = recs + (q0 >> 2);
-      const int k = q0 & 3;
+      const SlotRec<R> a = recs[f];  // owner's row of its element block
+      dg = (double)a.d;
+      rh -= (double)a.r;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const R sv = a->s[uidx(k, l)];  // k is a run-time value: direct loads, no register indexing
-        if (l == k) {
-          dg = (double)sv;
-        } else {
-          cf[n] = a->f[l];
-          cv[n] = (double)sv;
-          ++n;
-        }
+      for (int i = 0; i < 3; ++i) {
+        cf[i] = a.c[i];
+        cv[i] = (double)a.o[i];
       }
-      rh -= (double)a->r[k];
+      n = 3;
     }
-    if (q1 >= 0) {
-      const ElemRec<R>* b = recs + (q1 >> 2);
-      const int k = q1 & 3;
+    if (interior) {
+      const SlotRec<R> b = recs[nF + f];  // neighbour's row
+      dg += (double)b.d;
+      rh -= (double)b.r;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const R sv = b->s[uidx(k, l)];
-        if (l == k) {
-          dg += (double)sv;
-        } else {
-          cf[n] = b->f[l];
-          cv[n] = (double)sv;
-          ++n;
-        }
+      for (int i = 0; i < 3; ++i) {
+        cf[3 + i] = b.c[i];
+        cv[3 + i] = (double)b.o[i];
       }
-      rh -= (double)b->r[k];
+      n = 6;
+    } else {
+#pragma unroll
+      for (int i = 3; i < 6; ++i) {
+        cf[i] = 0;
+        cv[i] = 0.0;
+      }
     }
     const int base = rowptr[f] - blo;
 #pragma unroll
@@ -695,9 +705,9 @@ extern "C" int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const
 extern "C" size_t phfem_condense_workspace(int64_t nE, int64_t nF, int32_t precision) {
   Arena a;
   if (precision == PHFEM_MIXED)
-    a.take<ElemRec<float>>(nE);
+    a.take<SlotRec<float>>(2 * nF);
   else
-    a.take<ElemRec<double>>(nE);
+    a.take<SlotRec<double>>(2 * nF);
   a.take<int>(16);
   return a.size() + scan_workspace(nF + 1);
 }
@@ -720,7 +730,7 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
     return err(PHFEM_EWORKSPACE, "condense workspace too small");
   Arena a(work, work_bytes);
   const bool mixed = p->precision == PHFEM_MIXED;
-  void* recs = mixed ? (void*)a.take<ElemRec<float>>(nE) : (void*)a.take<ElemRec<double>>(nE);
+  void* recs = mixed ? (void*)a.take<SlotRec<float>>(2 * nF) : (void*)a.take<SlotRec<double>>(2 * nF);
   a.take<int>(16);
   DevParams P = to_dev(*p);
   rc = launch_face_init(nF, nC, coord, faces, face2tet, P, (uint32_t*)rowptr, nullptr, nullptr, s);
@@ -728,21 +738,22 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
   rc = scan_exclusive((const uint32_t*)rowptr, (uint32_t*)rowptr, nF + 1, nullptr, a, s);
   if (rc) return rc;
   // algorithmic bytes: tets, faces, sigma (+ kappa) once per tet, coordinates once per node,
-  // one record per tet written once and read once, face2tet and row pointers once, every
+  // four records per tet written once and read once, face2tet's neighbour half and the row
+  // pointers once, every
   // off-diagonal (col + val) and diagonal/rhs entry written once
-  const double rb = (double)(mixed ? sizeof(ElemRec<float>) : sizeof(ElemRec<double>));
+  const double rb = 4.0 * (double)(mixed ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>));
   const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
-  const double fb = rb * nE + 12.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
+  const double fb = rb * nE + 8.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
   if (mixed) {
     PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face,
-                sigma, kappa, P, (ElemRec<float>*)recs, nullptr);
+                sigma, kappa, P, nF, (SlotRec<float>*)recs);
     PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces, face2tet,
-                P, (const ElemRec<float>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
+                P, (const SlotRec<float>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
   } else {
     PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face,
-                sigma, kappa, P, (ElemRec<double>*)recs, nullptr);
+                sigma, kappa, P, nF, (SlotRec<double>*)recs);
     PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
-                face2tet, P, (const ElemRec<double>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
+                face2tet, P, (const SlotRec<double>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
   }
   return PHFEM_OK;
 }

@@ -69,149 +69,148 @@ void prof_end(hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ scan
+// Single-pass exclusive scan with decoupled look-back (Merrill & Garland, "Single-pass
+// Parallel Prefix Scan with Decoupled Look-back", 2016).  A workgroup takes the next tile
+// index from a counter (so every earlier tile is already running), loads its 4096 items with
+// coalesced loads, transposes them through LDS to 16 consecutive items per thread, publishes
+// its tile total, and one wave walks back over the predecessors' published totals / inclusive
+// prefixes, 64 tiles at a time, until it meets an inclusive prefix.  Results go back through
+// LDS and out with coalesced stores: one read and one write of the data.
 constexpr int SC_THREADS = 256;
 constexpr int SC_ITEMS = 16;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+constexpr uint64_t SC_AGG = 1ull << 32, SC_INC = 2ull << 32;
 
-// inclusive scan of one value per thread over the 256-thread block; returns the block total
-__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* lds_waves, uint32_t& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ int sc_pad(int k) { return k + (k >> 5); }  // one pad word per 32
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_clear(int64_t nw, uint64_t* __restrict__ st) {
+  for (int64_t i = (int64_t)blockIdx.x * SC_THREADS + threadIdx.x; i < nw; i += (int64_t)gridDim.x * SC_THREADS)
+    st[i] = 0;
+}
+
+// PACKED: in = count (bits 0..7) | payload << 8, out = prefix << pb | payload; else plain sums
+template <bool PACKED>
+__global__ __launch_bounds__(SC_THREADS) void k_scan_lookback(const uint32_t* in, int64_t n, int64_t ntiles,
+                                                              uint64_t* __restrict__ st, int pb, uint32_t* out,
+                                                              uint32_t* __restrict__ total) {
+  __shared__ uint32_t tile[SC_TILE + SC_TILE / 32];
+  __shared__ uint32_t lw[SC_THREADS / 64];
+  __shared__ uint32_t s_tile, s_excl;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) s_tile = atomicAdd(reinterpret_cast<unsigned int*>(st + ntiles), 1u);
+  __syncthreads();
+  const int64_t b = s_tile;
+  const int64_t base = b * SC_TILE;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    const int k = i * SC_THREADS + tid;
+    tile[sc_pad(k)] = base + k < n ? in[base + k] : 0u;
+  }
+  __syncthreads();
+  uint32_t v[SC_ITEMS];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    v[i] = tile[sc_pad(tid * SC_ITEMS + i)];
+    sum += PACKED ? (v[i] & 0xffu) : v[i];
+  }
+  // block-wide inclusive scan of the per-thread sums
+  uint32_t inc = sum;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t u = __shfl_up(v, o, 64);
-    if (lane >= o) v += u;
+    const uint32_t u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
   }
-  if (lane == 63) lds_waves[w] = v;
+  if (lane == 63) lw[w] = inc;
   __syncthreads();
-  uint32_t add = 0;
-  total = 0;
+  uint32_t agg = 0, wpre = 0;
 #pragma unroll
-  for (int i = 0; i < SC_THREADS / 64; ++i) {
-    uint32_t t = lds_waves[i];
-    if (i < w) add += t;
-    total += t;
+  for (int q = 0; q < SC_THREADS / 64; ++q) {
+    const uint32_t t = lw[q];
+    wpre += q < w ? t : 0u;
+    agg += t;
+  }
+  // look-back by wave 0
+  if (w == 0) {
+    if (lane == 0)
+      __hip_atomic_store(st + b, (b == 0 ? SC_INC : SC_AGG) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    int64_t j = b - 1 - lane;
+    while (b > 0) {
+      uint64_t sv;
+      for (;;) {
+        sv = j >= 0 ? __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : SC_INC;
+        if (__ballot((sv >> 32) == 0) == 0) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      const uint64_t incm = __ballot((sv >> 32) == 2);
+      // lanes up to and including the nearest inclusive prefix contribute
+      const int stop = incm ? __ffsll((unsigned long long)incm) - 1 : 63;
+      uint32_t x = lane <= stop ? (uint32_t)sv : 0u;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      excl += x;
+      if (incm) break;
+      j -= 64;
+    }
+    if (lane == 0) {
+      if (b > 0) __hip_atomic_store(st + b, SC_INC | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = excl;
+      if (total && b == ntiles - 1) *total = excl + agg;
+    }
   }
   __syncthreads();
-  return v + add;
-}
-
-__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
-                                                            uint32_t* __restrict__ partial) {
-  __shared__ uint32_t lw[SC_THREADS / 64];
-  int64_t base = (int64_t)blockIdx.x * SC_TILE;
-  uint32_t s = 0;
+  uint32_t run = s_excl + wpre + inc - sum;
 #pragma unroll
   for (int i = 0; i < SC_ITEMS; ++i) {
-    int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
-    if (idx < n) s += in[idx];
+    const uint32_t c = PACKED ? (v[i] & 0xffu) : v[i];
+    tile[sc_pad(tid * SC_ITEMS + i)] = PACKED ? ((run << pb) | (v[i] >> 8)) : run;
+    run += c;
   }
-  uint32_t tot;
-  block_inclusive_scan(s, lw, tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
-// single workgroup: exclusive scan of the tile sums in place
-__global__ __launch_bounds__(SC_THREADS) void k_scan_partials(uint32_t* __restrict__ partial, int64_t nb,
-                                                              uint32_t* __restrict__ total) {
-  __shared__ uint32_t lw[SC_THREADS / 64];
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < nb; base += SC_THREADS) {
-    int64_t idx = base + threadIdx.x;
-    uint32_t v = idx < nb ? partial[idx] : 0;
-    uint32_t tot;
-    uint32_t inc = block_inclusive_scan(v, lw, tot);
-    if (idx < nb) partial[idx] = carry + inc - v;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total) *total = carry;
-}
-
-// blocked per-thread items: thread t of tile b owns [b*TILE + t*ITEMS, +ITEMS)
-__global__ __launch_bounds__(SC_THREADS) void k_scan_apply(const uint32_t* in, int64_t n,
-                                                           const uint32_t* __restrict__ partial, uint32_t* out) {
-  __shared__ uint32_t lw[SC_THREADS / 64];
-  int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
-  uint32_t v[SC_ITEMS];
-  uint32_t s = 0;
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < SC_ITEMS; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : 0;
-    s += v[i];
-  }
-  uint32_t tot;
-  uint32_t inc = block_inclusive_scan(s, lw, tot);
-  uint32_t run = partial[blockIdx.x] + inc - s;
-#pragma unroll
-  for (int i = 0; i < SC_ITEMS; ++i) {
-    if (base + i < n) out[base + i] = run;
-    run += v[i];
+    const int k = i * SC_THREADS + tid;
+    if (base + k < n) out[base + k] = tile[sc_pad(k)];
   }
 }
 
 size_t scan_workspace(int64_t n) {
   Arena a;
-  a.take<uint32_t>((size_t)((n + SC_TILE - 1) / SC_TILE) + 1);
+  a.take<uint64_t>((size_t)((n + SC_TILE - 1) / SC_TILE) + 1);
   return a.size();
 }
 
-int scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, Arena& ws, hipStream_t s) {
-  int64_t nb = (n + SC_TILE - 1) / SC_TILE;
-  uint32_t* partial = ws.take<uint32_t>((size_t)nb + 1);
+int64_t scan_status_words(int64_t n) { return (n + SC_TILE - 1) / SC_TILE + 1; }
+
+static int scan_run(bool packed, const uint32_t* in, uint32_t* out, int64_t n, int pb, uint32_t* total, Arena& ws,
+                    hipStream_t s, uint64_t* cleared) {
+  const int64_t nt = (n + SC_TILE - 1) / SC_TILE;
+  // per-tile status words, then the tile counter: zeroed here, or by the caller (cleared)
+  uint64_t* st = cleared ? cleared : ws.take<uint64_t>((size_t)nt + 1);
   if (n == 0) return PHFEM_OK;
-  PH_LAUNCH("scan_reduce", k_scan_reduce, (unsigned)nb, SC_THREADS, 0, s, in, n, partial);
-  PH_LAUNCH("scan_partials", k_scan_partials, 1, SC_THREADS, 0, s, partial, nb, total);
-  PH_LAUNCH("scan_apply", k_scan_apply, (unsigned)nb, SC_THREADS, 0, s, in, n, (const uint32_t*)partial, out);
+  if (!cleared)
+    PH_LAUNCH("scan_clear", k_scan_clear, (unsigned)std::min<int64_t>((nt + SC_THREADS) / SC_THREADS, 1024),
+              SC_THREADS, 0, s, nt + 1, st);
+  if (packed)
+    PH_LAUNCH_B("scanp", 8.0 * n, k_scan_lookback<true>, (unsigned)nt, SC_THREADS, 0, s, in, n, nt, st, pb, out,
+                total);
+  else
+    PH_LAUNCH_B("scan", 8.0 * n, k_scan_lookback<false>, (unsigned)nt, SC_THREADS, 0, s, in, n, nt, st, 0, out,
+                total);
   return PHFEM_OK;
+}
+
+int scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, Arena& ws, hipStream_t s,
+                   uint64_t* cleared) {
+  return scan_run(false, in, out, n, 0, total, ws, s, cleared);
 }
 
 // Packed variant: in[i] = count (bits 0..7) | payload << 8; out[i] = (exclusive prefix of
 // the counts) << pb | payload.  Used for per-row (first-appearance prefix, mask) records.
-__global__ __launch_bounds__(SC_THREADS) void k_scanp_reduce(const uint32_t* __restrict__ in, int64_t n,
-                                                             uint32_t* __restrict__ partial) {
-  __shared__ uint32_t lw[SC_THREADS / 64];
-  int64_t base = (int64_t)blockIdx.x * SC_TILE;
-  uint32_t s = 0;
-#pragma unroll
-  for (int i = 0; i < SC_ITEMS; ++i) {
-    int64_t idx = base + (int64_t)i * SC_THREADS + threadIdx.x;
-    if (idx < n) s += in[idx] & 0xffu;
-  }
-  uint32_t tot;
-  block_inclusive_scan(s, lw, tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(SC_THREADS) void k_scanp_apply(const uint32_t* __restrict__ in, int64_t n,
-                                                            const uint32_t* __restrict__ partial, int pb,
-                                                            uint32_t* __restrict__ out) {
-  __shared__ uint32_t lw[SC_THREADS / 64];
-  int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
-  uint32_t v[SC_ITEMS];
-  uint32_t s = 0;
-#pragma unroll
-  for (int i = 0; i < SC_ITEMS; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : 0;
-    s += v[i] & 0xffu;
-  }
-  uint32_t tot;
-  uint32_t inc = block_inclusive_scan(s, lw, tot);
-  uint32_t run = partial[blockIdx.x] + inc - s;
-#pragma unroll
-  for (int i = 0; i < SC_ITEMS; ++i) {
-    if (base + i < n) out[base + i] = (run << pb) | (v[i] >> 8);
-    run += v[i] & 0xffu;
-  }
-}
-
-int scan_packed(const uint32_t* in, uint32_t* out, int64_t n, int pb, uint32_t* total, Arena& ws, hipStream_t s) {
-  int64_t nb = (n + SC_TILE - 1) / SC_TILE;
-  uint32_t* partial = ws.take<uint32_t>((size_t)nb + 1);
-  if (n == 0) return PHFEM_OK;
-  PH_LAUNCH_B("scanp_reduce", 4.0 * n, k_scanp_reduce, (unsigned)nb, SC_THREADS, 0, s, in, n, partial);
-  PH_LAUNCH("scan_partials", k_scan_partials, 1, SC_THREADS, 0, s, partial, nb, total);
-  PH_LAUNCH_B("scanp_apply", 8.0 * n, k_scanp_apply, (unsigned)nb, SC_THREADS, 0, s, in, n, (const uint32_t*)partial,
-              pb, out);
-  return PHFEM_OK;
+int scan_packed(const uint32_t* in, uint32_t* out, int64_t n, int pb, uint32_t* total, Arena& ws, hipStream_t s,
+                uint64_t* cleared) {
+  return scan_run(true, in, out, n, pb, total, ws, s, cleared);
 }
 
 // ------------------------------------------------------------------ radix sort

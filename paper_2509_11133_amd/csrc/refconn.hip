@@ -101,31 +101,6 @@ static_assert(fkind(8, 0) == 2 && fcoarse(8, 0) == 0 && fkind(11, 0) == 2 && fco
 static_assert(fkind(1, 1) == 1 && fcoarse(1, 1) == 2 && fkind(2, 2) == 1 && fcoarse(2, 2) == 1, "corners");
 static_assert(first3(0, false) == 4 && first3(3, false) == 5, "first (M, C)");
 
-__device__ __forceinline__ int loc4(const int a[4], int x) { return a[0] == x ? 0 : (a[1] == x ? 1 : (a[2] == x ? 2 : 3)); }
-
-// Run-time tables (a thread handles one refined row, so the child index is a run-time value)
-struct RuleTables {
-  int8_t f3c[6], f3j[6];  // first (octahedron child, local edge) holding (M_j, C)
-  int8_t fkind[48];       // per child*4 + local face: 0 inside, 1 corner triangle, 2 middle triangle
-  int8_t fco[48];         // coarse face of a kind-1/2 face
-  int8_t fpart[48];       // partner child*4 + local face of a kind-0 face
-};
-__host__ __device__ constexpr RuleTables make_tables() {
-  RuleTables T{};
-  for (int j = 0; j < 6; ++j) {
-    T.f3c[j] = (int8_t)first3(j, false);
-    T.f3j[j] = (int8_t)first3(j, true);
-  }
-  for (int c = 0; c < 12; ++c)
-    for (int kk = 0; kk < 4; ++kk) {
-      T.fkind[4 * c + kk] = (int8_t)fkind(c, kk);
-      T.fco[4 * c + kk] = (int8_t)(fkind(c, kk) ? fcoarse(c, kk) : 0);
-      T.fpart[4 * c + kk] = (int8_t)(fkind(c, kk) ? 0 : fpartner(c, kk));
-    }
-  return T;
-}
-__constant__ RuleTables c_rt = make_tables();
-
 constexpr int RCT = 256;
 
 struct RCArgs {
@@ -153,19 +128,27 @@ struct RCArgs {
   int32_t* nbr2;
 };
 
-__global__ __launch_bounds__(RCT) void k_rc_prep(int64_t nE, const int32_t* __restrict__ tet,
+__global__ __launch_bounds__(RCT) void k_rc_prep(int64_t nE, int64_t nEd, const int32_t* __restrict__ tet,
                                                  const int32_t* __restrict__ t2e, const int32_t* __restrict__ eft,
                                                  const int32_t* __restrict__ t2f, const int32_t* __restrict__ nbr,
                                                  int32_t* __restrict__ minI, int32_t* __restrict__ efp,
                                                  int4* __restrict__ T4, int4* __restrict__ F4, int4* __restrict__ N4,
-                                                 int4* __restrict__ E8) {
+                                                 int4* __restrict__ E8, uint32_t* __restrict__ bad) {
   int64_t t = (int64_t)blockIdx.x * RCT + threadIdx.x;
   if (t >= nE) return;
   int n[4], e[6];
 #pragma unroll
   for (int i = 0; i < 4; ++i) n[i] = tet[i * nE + t];
+  bool oob = false;
 #pragma unroll
-  for (int j = 0; j < 6; ++j) e[j] = t2e[j * nE + t];
+  for (int j = 0; j < 6; ++j) {
+    e[j] = t2e[j * nE + t];
+    if ((uint32_t)e[j] >= (uint64_t)nEd) {  // edge ids index the per-edge tables below
+      oob = true;
+      e[j] = 0;
+    }
+  }
+  if (oob) atomicOr(bad, 1u);
   T4[t] = make_int4(n[0], n[1], n[2], n[3]);
   F4[t] = make_int4(t2f[t], t2f[nE + t], t2f[2 * nE + t], t2f[3 * nE + t]);
   int nb4[4];
@@ -187,53 +170,57 @@ __global__ __launch_bounds__(RCT) void k_rc_prep(int64_t nE, const int32_t* __re
 }
 
 __device__ __forceinline__ int64_t rowof(int64_t nE, int64_t tt, int c) { return c == 0 ? tt : nE + 11 * tt + (c - 1); }
-__device__ __forceinline__ int get4(const int4& v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w)); }
+template <int C>
+__device__ __forceinline__ int64_t rowc(int64_t nE, int64_t tt) { return C == 0 ? tt : nE + 11 * tt + (C - 1); }
+// order of the rows of one tet's children: child 0 first, then 1..11
+__host__ __device__ constexpr int rord(int c) { return c == 0 ? -1 : c; }
 __device__ __forceinline__ int loc4v(const int4& v, int x) { return v.x == x ? 0 : (v.y == x ? 1 : (v.z == x ? 2 : 3)); }
 
-// One refined row: its coarse tet and child, the coarse data it needs.
-struct RCRow {
-  int64_t r, t;
-  int c;
-  int4 n, f, nb, e0, e1;  // e0 = edges 0..3, e1.xy = edges 4, 5
-};
-__device__ __forceinline__ int edge_of(const RCRow& R, int j) { return j < 4 ? get4(R.e0, j) : (j == 4 ? R.e1.x : R.e1.y); }
+// Both passes run one workgroup per RCW coarse tets: wave c handles child c of all of them,
+// so the child index is uniform across a wave and every rule above resolves at compile time
+// (one specialised code path per child, selected by a scalar branch).  A workgroup's rows
+// are rows [t0, t0 + RCW) and [nE + 11 t0, nE + 11 (t0 + RCW)): per-row outputs are staged
+// in LDS and written out as two contiguous ranges.
+constexpr int RCW = 64;
+constexpr int RCB = 12 * RCW;
+constexpr int RCS = 13;  // LDS stride of one tet's 12 child slots (odd: no bank conflicts)
 
-__device__ __forceinline__ void rc_row(const RCArgs& A, int64_t r, RCRow& R) {
-  const int64_t nE = A.nE;
-  R.r = r;
-  if (r < nE) {
-    R.t = r;
-    R.c = 0;
-  } else {
-    const int64_t q = r - nE;
-    R.t = q / 11;
-    R.c = 1 + (int)(q - 11 * R.t);
-  }
-  R.n = A.T4[R.t];
-  R.f = A.F4[R.t];
-  R.nb = A.N4[R.t];
-  R.e0 = A.E8[2 * R.t];
-  R.e1 = A.E8[2 * R.t + 1];
+template <class F, int... I>
+__device__ __forceinline__ void sfor_(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_(f, std::make_integer_sequence<int, N>{});
 }
 
-__device__ __forceinline__ int ech(int c, int p) { return ch(c, p); }  // run-time c: shifts of packed constants
+// coarse tet data of one lane
+struct CT {
+  int64_t t;
+  int n[4], f[4], nb[4], e[6];
+};
+__device__ __forceinline__ void load_ct(const RCArgs& A, int64_t t, CT& T) {
+  const int4 a = A.T4[t], b = A.F4[t], c = A.N4[t], d = A.E8[2 * t], e = A.E8[2 * t + 1];
+  T.t = t;
+  T.n[0] = a.x, T.n[1] = a.y, T.n[2] = a.z, T.n[3] = a.w;
+  T.f[0] = b.x, T.f[1] = b.y, T.f[2] = b.z, T.f[3] = b.w;
+  T.nb[0] = c.x, T.nb[1] = c.y, T.nb[2] = c.z, T.nb[3] = c.w;
+  T.e[0] = d.x, T.e[1] = d.y, T.e[2] = d.z, T.e[3] = d.w, T.e[4] = e.x, T.e[5] = e.y;
+}
 
-// first occurrence (row, local edge) of local edge jj of this row's child
-__device__ __forceinline__ void edge_first_rt(const RCArgs& A, const RCRow& R, int jj, int64_t& er, int& ej) {
-  const int64_t nE = A.nE, t = R.t;
-  const int c = R.c;
-  const int s0 = ech(c, ev0(jj)), s1 = ech(c, ev1(jj));
-  const int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
-  if (hi == 10) {  // (M_j, C): inside t
-    er = rowof(nE, t, c_rt.f3c[lo - 4]);
-    ej = c_rt.f3j[lo - 4];
-    return;
-  }
-  if (lo < 4) {  // (V_a, M_j): half of coarse edge e_j at node v
-    const int j = hi - 4;
-    const int e = edge_of(R, j);
-    const int v = get4(R.n, lo);
-    const int na = get4(R.n, ev0(j)), nb = get4(R.n, ev1(j));
+// first occurrence (row, local edge) of local edge J of child C
+template <int C, int J>
+__device__ __forceinline__ void efirst(const RCArgs& A, const CT& T, int64_t& er, int& ej) {
+  constexpr int s0 = ch(C, ev0(J)), s1 = ch(C, ev1(J));
+  constexpr int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
+  const int64_t nE = A.nE;
+  if constexpr (hi == 10) {  // (M_j, C): inside t
+    er = rowc<first3(lo - 4, false)>(nE, T.t);
+    ej = first3(lo - 4, true);
+  } else if constexpr (lo < 4) {  // (V_lo, M_j): half of coarse edge e_j at node v
+    constexpr int j = hi - 4;
+    const int e = T.e[j], v = T.n[lo];
+    const int na = T.n[ev0(j)], nb = T.n[ev1(j)];
     const int lon = na < nb ? na : nb;
     const int mi = A.minI[2 * e + (v == lon ? 0 : 1)];
     if (mi != INT_MAX && (mi >> 2) < nE) {
@@ -246,153 +233,280 @@ __device__ __forceinline__ void edge_first_rt(const RCArgs& A, const RCRow& R, i
     const int t0 = p / 6, j0 = p - 6 * t0;
     const int vl = ((v == lon) != (flip != 0)) ? ev0(j0) : ev1(j0);
     const bool ok = p0 >= 0 && t0 < nE;  // unset only for inconsistent input
-    er = ok ? rowof(nE, t0, vl) : R.r;
-    ej = ok ? posv(vl, j0) - 1 : jj;
-    return;
-  }
-  // (M_i, M_j) on a coarse face: corner child of the shared vertex, here or in the neighbour
-  const int i = lo - 4, j = hi - 4;
-  const int v = common_v(i, j), a = other_end(i, v), b = other_end(j, v);
-  const int k = face_with(v, a, b);
-  int64_t rr = rowof(nE, t, v);
-  int jr = eidx(posv(v, i), posv(v, j));
-  const int tn = get4(R.nb, k);
-  if (tn >= 0) {
-    const int4 nn = A.T4[tn];
-    const int v2 = loc4v(nn, get4(R.n, v)), a2 = loc4v(nn, get4(R.n, a)), b2 = loc4v(nn, get4(R.n, b));
-    const int le2 = eidx(posv(v2, eidx(v2, a2)), posv(v2, eidx(v2, b2)));
-    const int64_t r2 = rowof(nE, tn, v2);
-    if (6 * r2 + le2 < 6 * rr + jr) {
-      rr = r2;
-      jr = le2;
+    er = ok ? rowof(nE, t0, vl) : rowc<C>(nE, T.t);
+    ej = ok ? posv(vl, j0) - 1 : J;
+  } else {  // (M_i, M_j) on a coarse face: corner child of the shared vertex, here or in the neighbour
+    constexpr int i = lo - 4, j = hi - 4;
+    constexpr int v = common_v(i, j), a = other_end(i, v), b = other_end(j, v);
+    constexpr int k = face_with(v, a, b);
+    constexpr int jr = eidx(posv(v, i), posv(v, j));
+    int64_t rr = rowc<v>(nE, T.t);
+    int jj = jr;
+    const int tn = T.nb[k];
+    if (tn >= 0) {
+      const int4 nn = A.T4[tn];
+      const int v2 = loc4v(nn, T.n[v]), a2 = loc4v(nn, T.n[a]), b2 = loc4v(nn, T.n[b]);
+      const int le2 = eidx(posv(v2, eidx(v2, a2)), posv(v2, eidx(v2, b2)));
+      const int64_t r2 = rowof(nE, tn, v2);
+      if (6 * r2 + le2 < 6 * rr + jr) {
+        rr = r2;
+        jj = le2;
+      }
     }
+    er = rr;
+    ej = jj;
   }
-  er = rr;
-  ej = jr;
 }
 
-// other occurrence (row, local face) of local face kk of this row's child; row -1 on the boundary
-__device__ __forceinline__ void face_other_rt(const RCArgs& A, const RCRow& R, int kk, int64_t& fr, int& fk) {
-  const int64_t nE = A.nE;
-  const int idx = 4 * R.c + kk;
-  const int kind = c_rt.fkind[idx];
-  if (kind == 0) {
-    const int p = c_rt.fpart[idx];
-    fr = rowof(nE, R.t, p >> 2);
-    fk = p & 3;
-    return;
-  }
-  const int k = c_rt.fco[idx];
-  const int tn = get4(R.nb, k);
-  if (tn < 0) {
-    fr = -1;
-    fk = 0;
-    return;
-  }
-  const int k2 = loc4v(A.F4[tn], get4(R.f, k));
-  if (kind == 2) {
-    fr = rowof(nE, tn, 8 + k2);
-    fk = 0;
+// is local edge J of child C first seen in this row?
+template <int C, int J>
+__device__ __forceinline__ bool efirst_here(const RCArgs& A, const CT& T) {
+  constexpr int s0 = ch(C, ev0(J)), s1 = ch(C, ev1(J));
+  constexpr int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
+  if constexpr (hi == 10) {
+    return first3(lo - 4, false) == C && first3(lo - 4, true) == J;
+  } else if constexpr (lo >= 4 && common_v(lo - 4, hi - 4) != C) {
+    return false;  // an octahedron child never holds the first (M, M) occurrence
   } else {
-    const int v2 = loc4v(A.T4[tn], get4(R.n, R.c & 3));  // corner child c holds vertex V_c
-    fr = rowof(nE, tn, v2);
-    fk = cornerface(v2, k2);
+    int64_t er;
+    int ej;
+    efirst<C, J>(A, T, er, ej);
+    return er == rowc<C>(A.nE, T.t) && ej == J;
   }
+}
+
+// other occurrence (row, local face) of local face K of child C; row -1 on the boundary
+template <int C, int K>
+__device__ __forceinline__ void fother(const RCArgs& A, const CT& T, int64_t& fr, int& fk) {
+  constexpr int kind = fkind(C, K);
+  const int64_t nE = A.nE;
+  if constexpr (kind == 0) {
+    constexpr int p = fpartner(C, K);
+    fr = rowc<(p >> 2)>(nE, T.t);
+    fk = p & 3;
+  } else {
+    constexpr int k = fcoarse(C, K);
+    const int tn = T.nb[k];
+    if (tn < 0) {
+      fr = -1;
+      fk = 0;
+      return;
+    }
+    const int k2 = loc4v(A.F4[tn], T.f[k]);
+    if constexpr (kind == 2) {
+      fr = rowof(nE, tn, 8 + k2);
+      fk = 0;
+    } else {
+      const int v2 = loc4v(A.T4[tn], T.n[C]);  // corner child C holds vertex V_C
+      fr = rowof(nE, tn, v2);
+      fk = cornerface(v2, k2);
+    }
+  }
+}
+
+template <int C, int K>
+__device__ __forceinline__ bool fown(const RCArgs& A, const CT& T, int64_t r, int64_t& fr, int& fk) {
+  fother<C, K>(A, T, fr, fk);
+  if constexpr (fkind(C, K) == 0)
+    return rord(fpartner(C, K) >> 2) > rord(C);
+  else
+    return fr < 0 || 4 * fr + fk > 4 * r + K;
+}
+
+template <int S>
+__device__ __forceinline__ int sym_node(const RCArgs& A, const CT& T) {
+  if constexpr (S < 4) {
+    return T.n[S];
+  } else if constexpr (S < 10) {
+    const int e = T.e[S - 4];
+    return (int)(A.nC + A.eft[e] + e + 1);
+  } else {
+    return (int)(A.nC + T.t + A.pre[T.t]);
+  }
+}
+
+// the rows of a workgroup: LDS slot l * RCS + c of (lane l, child c) <-> global row
+struct RCBlock {
+  int64_t t0;
+  int nb;  // tets in this workgroup
+};
+__device__ __forceinline__ RCBlock rc_block(const RCArgs& A) {
+  RCBlock B;
+  B.t0 = (int64_t)blockIdx.x * RCW;
+  const int64_t rest = A.nE - B.t0;
+  B.nb = rest < RCW ? (int)rest : RCW;
+  return B;
+}
+// flush slot of thread i: row and LDS slot, or false
+__device__ __forceinline__ bool rc_flush_slot(const RCArgs& A, const RCBlock& B, int i, int64_t& row, int& slot) {
+  if (i < 11 * B.nb) {  // children 1..11, rows nE + 11 t0 + i
+    const int l = i / 11;
+    row = A.nE + 11 * B.t0 + i;
+    slot = l * RCS + 1 + (i - 11 * l);
+    return true;
+  }
+  if (i >= 11 * RCW && i - 11 * RCW < B.nb) {  // child 0, rows t0 + l
+    const int l = i - 11 * RCW;
+    row = B.t0 + l;
+    slot = l * RCS;
+    return true;
+  }
+  return false;
 }
 
 // pass 1: count | mask << 8 of first edges and owned faces for every refined row
-__global__ __launch_bounds__(RCT) void k_rc_pass1(RCArgs A) {
-  const int64_t r = (int64_t)blockIdx.x * RCT + threadIdx.x;
-  if (r >= A.nE2) return;
-  RCRow R;
-  rc_row(A, r, R);
-  int me = 0, mf = 0;
-#pragma unroll
-  for (int jj = 0; jj < 6; ++jj) {
-    int64_t er;
-    int ej;
-    edge_first_rt(A, R, jj, er, ej);
-    me |= (er == r && ej == jj) ? (1 << jj) : 0;
+__global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
+  __shared__ uint32_t sE[RCW * RCS], sF[RCW * RCS];
+  const RCBlock B = rc_block(A);
+  const int lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (lane < B.nb) {
+    CT T;
+    load_ct(A, B.t0 + lane, T);
+    sfor<12>([&](auto Cc) {
+      constexpr int C = decltype(Cc)::value;
+      if (c != C) return;
+      const int64_t r = rowc<C>(A.nE, T.t);
+      int me = 0, mf = 0;
+      sfor<6>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        if (efirst_here<C, J>(A, T)) me |= 1 << J;
+      });
+      sfor<4>([&](auto Kc) {
+        constexpr int K = decltype(Kc)::value;
+        int64_t fr;
+        int fk;
+        if (fown<C, K>(A, T, r, fr, fk)) mf |= 1 << K;
+      });
+      sE[lane * RCS + C] = (uint32_t)__popc(me) | ((uint32_t)me << 8);
+      sF[lane * RCS + C] = (uint32_t)__popc(mf) | ((uint32_t)mf << 8);
+    });
   }
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    int64_t fr;
-    int fk;
-    face_other_rt(A, R, kk, fr, fk);
-    mf |= (fr < 0 || 4 * fr + fk > 4 * r + kk) ? (1 << kk) : 0;
+  __syncthreads();
+  int64_t row;
+  int slot;
+  if (rc_flush_slot(A, B, threadIdx.x, row, slot)) {
+    A.inE[row] = sE[slot];
+    A.inF[row] = sF[slot];
   }
-  A.inE[r] = (uint32_t)__popc(me) | ((uint32_t)me << 8);
-  A.inF[r] = (uint32_t)__popc(mf) | ((uint32_t)mf << 8);
-}
-
-__device__ __forceinline__ int sym_node(const RCArgs& A, const RCRow& R, int sym) {
-  if (sym < 4) return get4(R.n, sym);
-  if (sym < 10) {
-    const int e = edge_of(R, sym - 4);
-    return (int)(A.nC + A.eft[e] + e + 1);
-  }
-  return (int)(A.nC + R.t + A.pre[R.t]);
 }
 
 // pass 2: ids of the refined edges and faces of every row, and all outputs
-__global__ __launch_bounds__(RCT) void k_rc_pass2(RCArgs A) {
-  const int64_t r = (int64_t)blockIdx.x * RCT + threadIdx.x;
-  if (r >= A.nE2) return;
-  RCRow R;
-  rc_row(A, r, R);
-  const int c = R.c;
-  const uint32_t oe = A.recE[r], of = A.recF[r];
-  const int me = oe & 63, mf = of & 15;
-  A.pre2[r] = (int32_t)(oe >> 6);
-#pragma unroll
-  for (int jj = 0; jj < 6; ++jj) {
-    int32_t id;
-    if ((me >> jj) & 1) {
-      id = (int32_t)((oe >> 6) + __popc(me & ((1 << jj) - 1)));
-      const int na = sym_node(A, R, ech(c, ev0(jj))), nb = sym_node(A, R, ech(c, ev1(jj)));
-      A.edges2[id] = na < nb ? na : nb;
-      A.edges2[A.nEd2 + id] = na < nb ? nb : na;
-      A.eft2[id] = (int32_t)r;
-    } else {
-      int64_t er;
-      int ej;
-      edge_first_rt(A, R, jj, er, ej);
-      const uint32_t o = A.recE[er];
-      id = (int32_t)((o >> 6) + __popc((o & 63) & ((1u << ej) - 1)));
-    }
-    A.t2e2[jj * A.nE2 + r] = id;
+constexpr int RCO = 16;  // staged words per row: pre, 6 edges, 4 faces, 4 neighbours, 4 packed signs
+__global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
+  __shared__ int32_t sW[RCO * RCW * RCS];
+  const RCBlock B = rc_block(A);
+  const int lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t nEd2 = A.nEd2, nF2 = A.nF2;
+  if (lane < B.nb) {
+    CT T;
+    load_ct(A, B.t0 + lane, T);
+    sfor<12>([&](auto Cc) {
+      constexpr int C = decltype(Cc)::value;
+      if (c != C) return;
+      const int64_t r = rowc<C>(A.nE, T.t);
+      int32_t* w = sW + lane * RCS + C;
+      const uint32_t oe = A.recE[r], of = A.recF[r];
+      const int me = oe & 63, mf = of & 15;
+      w[0] = (int32_t)(oe >> 6);
+      sfor<6>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        int32_t id;
+        if ((me >> J) & 1) {
+          id = (int32_t)((oe >> 6) + __popc(me & ((1 << J) - 1)));
+          const int na = sym_node<ch(C, ev0(J))>(A, T), nb = sym_node<ch(C, ev1(J))>(A, T);
+          if ((uint32_t)id < (uint64_t)nEd2) {
+            A.edges2[id] = na < nb ? na : nb;
+            A.edges2[nEd2 + id] = na < nb ? nb : na;
+            A.eft2[id] = (int32_t)r;
+          }
+        } else {
+          int64_t er;
+          int ej;
+          efirst<C, J>(A, T, er, ej);
+          const uint32_t o = A.recE[er];
+          id = (int32_t)((o >> 6) + __popc((o & 63) & ((1u << ej) - 1)));
+        }
+        w[(1 + J) * RCW * RCS] = id;
+      });
+      uint32_t sg = 0;
+      sfor<4>([&](auto Kc) {
+        constexpr int K = decltype(Kc)::value;
+        int64_t fr;
+        int fk;
+        fother<C, K>(A, T, fr, fk);
+        const bool own = (mf >> K) & 1;
+        int32_t id;
+        if (own) {
+          id = (int32_t)((of >> 4) + __popc(mf & ((1 << K) - 1)));
+          if ((uint32_t)id < (uint64_t)nF2) {
+            A.f2t2[id] = (int32_t)(4 * r + K);
+            A.f2t2[nF2 + id] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
+            A.faces2[id] = sym_node<ch(C, fv(K, 0))>(A, T);
+            A.faces2[nF2 + id] = sym_node<ch(C, fv(K, 1))>(A, T);
+            A.faces2[2 * nF2 + id] = sym_node<ch(C, fv(K, 2))>(A, T);
+          }
+        } else if (fr >= 0) {
+          const uint32_t o = A.recF[fr];
+          id = (int32_t)((o >> 4) + __popc((o & 15) & ((1u << fk) - 1)));
+        } else {
+          id = -1;  // inconsistent input only
+        }
+        w[(7 + K) * RCW * RCS] = id;
+        w[(11 + K) * RCW * RCS] = fr < 0 ? -1 : (int32_t)fr;
+        sg |= (own ? 0x01u : 0xffu) << (8 * K);
+      });
+      w[15 * RCW * RCS] = (int32_t)sg;
+    });
   }
+  __syncthreads();
+  int64_t row;
+  int slot;
+  if (rc_flush_slot(A, B, threadIdx.x, row, slot)) {
+    const int64_t n2 = A.nE2;
+    const int32_t* v = sW + slot;
+    A.pre2[row] = v[0];
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    int64_t fr;
-    int fk;
-    face_other_rt(A, R, kk, fr, fk);
-    const bool own = (mf >> kk) & 1;
-    int32_t id;
-    if (own) {
-      id = (int32_t)((of >> 4) + __popc(mf & ((1 << kk) - 1)));
-      A.f2t2[id] = (int32_t)(4 * r + kk);
-      A.f2t2[A.nF2 + id] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
+    for (int j = 0; j < 6; ++j) A.t2e2[j * n2 + row] = v[(1 + j) * RCW * RCS];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) A.faces2[m * A.nF2 + id] = sym_node(A, R, ech(c, fv(kk, m)));
-    } else {
-      const uint32_t o = A.recF[fr];
-      id = (int32_t)((o >> 4) + __popc((o & 15) & ((1u << fk) - 1)));
+    for (int k = 0; k < 4; ++k) {
+      A.t2f2[k * n2 + row] = v[(7 + k) * RCW * RCS];
+      A.nbr2[k * n2 + row] = v[(11 + k) * RCW * RCS];
+      A.sig2[k * n2 + row] = (int8_t)(((uint32_t)v[15 * RCW * RCS] >> (8 * k)) & 0xffu);
     }
-    A.t2f2[kk * A.nE2 + r] = id;
-    A.sig2[kk * A.nE2 + r] = own ? 1 : -1;
-    A.nbr2[kk * A.nE2 + r] = fr < 0 ? -1 : (int32_t)fr;
   }
 }
 
-__global__ __launch_bounds__(RCT) void k_fill_i32(int64_t n, int32_t v, int32_t* __restrict__ a) {
-  for (int64_t i = (int64_t)blockIdx.x * RCT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RCT) a[i] = v;
+// every per-call buffer that must start from a known value, in one launch: minI = INT_MAX
+// [2 nEd], efp = -1 [nEd], the input-check flag and both scans' status words = 0 [nz]
+__global__ __launch_bounds__(RCT) void k_rc_init(int64_t nEd, int32_t* __restrict__ minI, int32_t* __restrict__ efp,
+                                                 int64_t nz, uint32_t* __restrict__ z) {
+  const int64_t stride = (int64_t)gridDim.x * RCT;
+  for (int64_t i = (int64_t)blockIdx.x * RCT + threadIdx.x; i < 2 * nEd; i += stride) {
+    minI[i] = INT_MAX;
+    if (i < nEd) efp[i] = -1;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * RCT + threadIdx.x; i < nz; i += stride) z[i] = 0;
+}
+
+// input ids out of range (flag) and refined totals against the recurrences; ORs a code
+// into *status (device)
+__global__ void k_rc_check(const uint32_t* __restrict__ tot, int64_t nEd2, int64_t nF2, int32_t* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t code = 0;
+  if (tot[2]) code |= 1;
+  if ((int64_t)tot[0] != nEd2 || (int64_t)tot[1] != nF2) code |= 2;
+  if (code) atomicOr(status, code);
 }
 
 struct RCWS {
   int32_t *minI, *efp;
   int4 *T4, *F4, *N4, *E8;
-  uint32_t *inE, *inF, *recF, *tot;
+  uint32_t *inE, *inF, *recF;
+  uint32_t* z;          // zeroed together: tot[4] (edge total, face total, input flag, pad), then
+  uint64_t *stE, *stF;  // the two scans' status words
+  int64_t nz;           // uint32 words from z
   size_t sub;
 };
 
@@ -407,13 +521,17 @@ static void rc_layout(Arena& a, int64_t nE, int64_t nEd, RCWS& w) {
   w.inE = a.take<uint32_t>(n2);
   w.inF = a.take<uint32_t>(n2);
   w.recF = a.take<uint32_t>(n2);
-  w.tot = a.take<uint32_t>(16);
+  const int64_t sw = scan_status_words(n2);
+  w.z = a.take<uint32_t>(4 + 4 * sw);  // contiguous: tot, stE, stF
+  w.stE = reinterpret_cast<uint64_t*>(w.z + 4);
+  w.stF = w.stE + sw;
+  w.nz = 4 + 4 * sw;
   w.sub = a.size();
 }
 
 int launch_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, const int32_t* t2e,
                   const int32_t* eft, const int32_t* pre, int64_t nCo, double* coord_out, int32_t* tetra_out,
-                  hipStream_t s);
+                  hipStream_t s, uint32_t* bad);
 
 }  // namespace ph
 
@@ -434,13 +552,13 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
                                       int32_t* edges_out, int32_t* tet2edge_out, int32_t* edge_first_tet_out,
                                       int32_t* tet_edge_prefix_out, int32_t* faces_out, int32_t* tet2face_out,
                                       int8_t* sigma_out, int32_t* face2tet_out, int32_t* nbr_out, int64_t* counts,
-                                      phfem_stream_t stream_) {
+                                      int32_t* status, phfem_stream_t stream_) {
   clear_error();
   hipStream_t s = (hipStream_t)stream_;
   if (nC <= 0 || nE <= 0 || nEd <= 0 || nF <= 0) return err(PHFEM_EINVAL, "bad sizes");
   const int64_t nE2 = 12 * nE, nC2 = nC + nEd + nE;
   const int64_t nEd2 = 2 * nEd + 3 * nF + 6 * nE, nF2 = 4 * nF + 16 * nE;
-  if (6 * nE2 >= (int64_t(1) << 31) || nC2 >= (int64_t(1) << 31) || 4 * nF2 >= (int64_t(1) << 31))
+  if (2 * nEd2 >= (int64_t(1) << 31) || 6 * nE2 >= (int64_t(1) << 31) || nC2 >= (int64_t(1) << 31) || 4 * nF2 >= (int64_t(1) << 31))
     return err(PHFEM_EINVAL, "refined mesh exceeds int32 positions");
   if (!coord || !tetra || !tet2edge || !edge_first_tet || !tet_edge_prefix || !tet2face || !nbr || !coord_out ||
       !tetra_out || !edges_out || !tet2edge_out || !edge_first_tet_out || !tet_edge_prefix_out || !faces_out ||
@@ -451,14 +569,14 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   Arena a(work, work_bytes);
   RCWS w;
   rc_layout(a, nE, nEd, w);
+  PH_LAUNCH_B("rc_init", 12.0 * nEd + 4.0 * w.nz, k_rc_init,
+              (unsigned)std::min<int64_t>(grid_for(std::max<int64_t>(2 * nEd, w.nz), RCT), 4096), RCT, 0, s, nEd,
+              w.minI, w.efp, w.nz, w.z);
   int rc = launch_refine(nC, coord, nE, tetra, tet2edge, edge_first_tet, tet_edge_prefix, nC2, coord_out, tetra_out,
-                         s);
+                         s, w.z + 2);
   if (rc) return rc;
-  PH_LAUNCH("fill_i32", k_fill_i32, (unsigned)std::min<int64_t>(grid_for(2 * nEd, RCT), 4096), RCT, 0, s, 2 * nEd,
-            (int32_t)INT_MAX, w.minI);
-  PH_LAUNCH("fill_i32", k_fill_i32, (unsigned)std::min<int64_t>(grid_for(nEd, RCT), 4096), RCT, 0, s, nEd, -1, w.efp);
-  PH_LAUNCH_B("rc_prep", 60.0 * nE + 12.0 * nEd + 80.0 * nE, k_rc_prep, grid_for(nE, RCT), RCT, 0, s, nE, tetra,
-              tet2edge, edge_first_tet, tet2face, nbr, w.minI, w.efp, w.T4, w.F4, w.N4, w.E8);
+  PH_LAUNCH_B("rc_prep", 60.0 * nE + 12.0 * nEd + 80.0 * nE, k_rc_prep, grid_for(nE, RCT), RCT, 0, s, nE, nEd, tetra,
+              tet2edge, edge_first_tet, tet2face, nbr, w.minI, w.efp, w.T4, w.F4, w.N4, w.E8, w.z + 2);
   RCArgs A;
   A.nC = nC;
   A.nE = nE;
@@ -489,23 +607,28 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   A.nbr2 = nbr_out;
   // pass 1 reads the coarse AoS data once (cache-shared by the 12 rows of a tet) and writes
   // two words per refined row
-  PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, grid_for(nE2, RCT), RCT, 0, s, A);
+  PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, grid_for(nE, RCW), RCB, 0, s, A);
   a.off = w.sub;
-  rc = scan_packed(w.inE, w.inE, nE2, 6, w.tot, a, s);
+  rc = scan_packed(w.inE, w.inE, nE2, 6, w.z, a, s, w.stE);
   if (rc) return rc;
   a.off = w.sub;
-  rc = scan_packed(w.inF, w.recF, nE2, 4, w.tot + 1, a, s);
+  rc = scan_packed(w.inF, w.recF, nE2, 4, w.z + 1, a, s, w.stF);
   if (rc) return rc;
   // pass 2 writes every refined connectivity array once
   PH_LAUNCH_B("refconn_pass2", 80.0 * nE + 12.0 * nEd + 8.0 * nE2 + (24.0 + 4 + 16 + 1 * 4 + 16) * nE2 + 12.0 * nEd2 +
                                    20.0 * nF2,
-              k_rc_pass2, grid_for(nE2, RCT), RCT, 0, s, A);
-  uint32_t tot[2] = {0, 0};
-  PH_HIP(hipMemcpyAsync(tot, w.tot, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  PH_HIP(hipStreamSynchronize(s));
-  if ((int64_t)tot[0] != nEd2 || (int64_t)tot[1] != nF2)
-    return err(PHFEM_EINVAL, "input connectivity is not the first-appearance numbering of a conforming, "
-                             "consistently oriented mesh (refined counts differ from 2nEd+3nF+6nE, 4nF+16nE)");
+              k_rc_pass2, grid_for(nE, RCW), RCB, 0, s, A);
+  if (status) {  // checked on the device: no synchronization
+    PH_LAUNCH("rc_check", k_rc_check, 1, 64, 0, s, w.z, nEd2, nF2, status);
+  } else {
+    uint32_t tot[3] = {0, 0, 0};
+    PH_HIP(hipMemcpyAsync(tot, w.z, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (tot[2]) return err(PHFEM_EINVAL, "an input id lies outside the mesh (vertex, edge or refined node)");
+    if ((int64_t)tot[0] != nEd2 || (int64_t)tot[1] != nF2)
+      return err(PHFEM_EINVAL, "input connectivity is not the first-appearance numbering of a conforming, "
+                               "consistently oriented mesh (refined counts differ from 2nEd+3nF+6nE, 4nF+16nE)");
+  }
   counts[0] = nEd2;
   counts[1] = nF2;
   counts[2] = 2 * nF2 - 4 * nE2;

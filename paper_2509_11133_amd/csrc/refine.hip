@@ -27,19 +27,34 @@ __global__ __launch_bounds__(RT) void k_copy_coords(int64_t nC, const double* __
 __global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restrict__ X, int64_t nE,
                                                const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
                                                const int32_t* __restrict__ eft, const int32_t* __restrict__ pre,
-                                               int64_t nCo, double* __restrict__ Xo, int32_t* __restrict__ To) {
+                                               int64_t nCo, double* __restrict__ Xo, int32_t* __restrict__ To,
+                                               uint32_t* __restrict__ bad) {
   int64_t t = (int64_t)blockIdx.x * RT + threadIdx.x;
   if (t >= nE) return;
+  const int64_t nEd = nCo - nC - nE;
   int v[4], e[6], m[6];
+  bool ok = true;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
-  const int C = (int)(nC + t + pre[t]);
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    ok = ok && (uint32_t)v[i] < (uint64_t)nC;
+  }
+  const int64_t C64 = nC + t + pre[t];
+  ok = ok && C64 >= nC && C64 < nCo;
+  const int C = (int)C64;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     e[j] = t2e[j * nE + t];
-    int ft = eft[e[j]];
-    m[j] = (int)(nC + ft + e[j] + 1);
+    const bool eok = (uint32_t)e[j] < (uint64_t)nEd;
+    const int ft = eok ? eft[e[j]] : 0;
+    const int64_t mj = nC + (int64_t)ft + e[j] + 1;
+    ok = ok && eok && mj > nC && mj < nCo;
+    m[j] = (int)mj;
     e[j] = (ft == t) ? 1 : 0;  // reuse: does the edge first appear in this tet?
+  }
+  if (!ok) {  // ids outside the mesh: nothing is written for this tet
+    if (bad) atomicOr(bad, 1u);
+    return;
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -83,6 +98,10 @@ __global__ __launch_bounds__(RT) void k_refine_faces(int64_t n, const int32_t* _
   int64_t f = (int64_t)blockIdx.x * RT + threadIdx.x;
   if (f >= n) return;
   int n1 = F[f], n2 = F[n + f], n3 = F[2 * n + f];
+  if ((uint32_t)n1 >= (uint64_t)nC || (uint32_t)n2 >= (uint64_t)nC || (uint32_t)n3 >= (uint64_t)nC) {
+    atomicOr(flags, DEV_NOFACE);
+    return;
+  }
   int e12 = n2e_lookup(n1, n2, nC, rp, col, eid), e23 = n2e_lookup(n2, n3, nC, rp, col, eid),
       e13 = n2e_lookup(n1, n3, nC, rp, col, eid);
   if (e12 < 0 || e23 < 0 || e13 < 0) {
@@ -102,11 +121,11 @@ __global__ __launch_bounds__(RT) void k_refine_faces(int64_t n, const int32_t* _
 
 int launch_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, const int32_t* t2e,
                   const int32_t* eft, const int32_t* pre, int64_t nCo, double* coord_out, int32_t* tetra_out,
-                  hipStream_t s) {
+                  hipStream_t s, uint32_t* bad) {
   PH_LAUNCH_B("copy_coords", 48.0 * nC, k_copy_coords, grid_for(nC, RT), RT, 0, s, nC, coord, nCo, coord_out);
   const int64_t nEd = nCo - nC - nE;
   PH_LAUNCH_B("refine", 44.0 * nE + 4.0 * nEd + 24.0 * nC + 192.0 * nE + 24.0 * (nE + nEd), k_refine, grid_for(nE, RT),
-              RT, 0, s, nC, coord, nE, tetra, t2e, eft, pre, nCo, coord_out, tetra_out);
+              RT, 0, s, nC, coord, nE, tetra, t2e, eft, pre, nCo, coord_out, tetra_out, bad);
   return PHFEM_OK;
 }
 
@@ -129,7 +148,8 @@ extern "C" int phfem_refine(int64_t nC, const double* coord, int64_t nE, const i
   const bool faces = nDb + nNb > 0;
   if (faces && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "boundary faces need Nodes2Edge");
   if ((nDb > 0 && (!db || !db_out)) || (nNb > 0 && (!nb || !nb_out))) return err(PHFEM_EINVAL, "null face list");
-  int rc = launch_refine(nC, coord, nE, tetra, tet2edge, edge_first_tet, tet_edge_prefix, nCo, coord_out, tetra_out, s);
+  int rc = launch_refine(nC, coord, nE, tetra, tet2edge, edge_first_tet, tet_edge_prefix, nCo, coord_out, tetra_out, s,
+                         nullptr);
   if (rc) return rc;
   if (!faces) return PHFEM_OK;
   // error flag of the face lookups: a 4-byte device global (calls on one device that

@@ -65,10 +65,12 @@ def refine(coord, tetra, conn, db=None, nb=None):
     return Xo, To, dbo, nbo
 
 
-def refine_connected(coord, tetra, conn):
+def refine_connected(coord, tetra, conn, status=None):
     """One refinement level that also returns the refined mesh's full connectivity (same
     numbering as connect() on it), derived from `conn` (full connectivity of the coarse
-    mesh) without sorting.  Returns (coord, tetra, conn)."""
+    mesh) without sorting.  Returns (coord, tetra, conn).  With `status` (a zeroed device
+    int32 tensor) the input check is left on the device (nothing synchronizes): read it
+    with check_status()."""
     dev = coord.device
     nC, nE, nEd, nF = coord.shape[1], tetra.shape[1], conn["nEd"], conn["nF"]
     nC2, nE2 = nC + nEd + nE, 12 * nE
@@ -88,17 +90,29 @@ def refine_connected(coord, tetra, conn):
     counts = np.zeros(3, np.int64)
     B.phfem_refine_connected(nC, coord, nE, tetra, nEd, nF, conn["tet2edge"], conn["edge_first_tet"],
                              conn["tet_edge_prefix"], conn["tet2face"], conn["nbr"], work, Xo, To, e, t2e, eft, pre,
-                             fa, t2f, sig, f2t, nbr, counts)
+                             fa, t2f, sig, f2t, nbr, counts, status)
     out = dict(nC=nC2, nE=nE2, nEd=int(counts[0]), edges=e, tet2edge=t2e, edge_first_tet=eft, tet_edge_prefix=pre,
                nF=int(counts[1]), nB=int(counts[2]), faces=fa, tet2face=t2f, sigma=sig, face2tet=f2t, nbr=nbr)
     return Xo, To, out
 
 
+def check_status(status):
+    """Raise if a device-side refine_connected check failed (one synchronization)."""
+    code = int(status.item())
+    if code:
+        raise B.PhfemError(B.EINVAL, "refine_connected input check failed (code %d: %s)" % (
+            code, "edge id out of range" if code & 1 else "refined totals differ from the recurrences"))
+
+
 def refine_connected_levels(coord, tetra, levels):
-    """connect() on the input mesh, then `levels` x refine_connected.  Returns (coord, tetra, conn)."""
+    """connect() on the input mesh, then `levels` x refine_connected, checked once at the end.
+    Returns (coord, tetra, conn)."""
     conn = connect(tetra, coord.shape[1], faces=True)
+    status = torch.zeros(1, dtype=I32, device=coord.device)
     for _ in range(levels):
-        coord, tetra, conn = refine_connected(coord, tetra, conn)
+        coord, tetra, conn = refine_connected(coord, tetra, conn, status)
+    if levels:
+        check_status(status)
     return coord, tetra, conn
 
 

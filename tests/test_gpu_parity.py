@@ -48,6 +48,17 @@ def single_tet():
     return X, np.array([[0, 2, 1, 3]], np.int32).T.copy()
 
 
+def disjoint_tets(n=700, seed=5):
+    """n separate, positively oriented tets: every face is a boundary face owned by its tet
+    (4 owned faces per tet, more than the record staging of one workgroup holds)."""
+    rng = np.random.default_rng(seed)
+    ref = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    P4 = 0.3 * (ref[None] + 0.2 * rng.random((n, 4, 3))) + 3.0 * rng.random((n, 1, 3))
+    X = P4.reshape(-1, 3).T.copy()
+    T = np.arange(4 * n, dtype=np.int32).reshape(n, 4).T.copy()
+    return X, T
+
+
 # ------------------------------------------------------------------ connectivity (a1-a3)
 @pytest.mark.parametrize("make,L", MESHES + [(single_tet, 0), (single_tet, 2)])
 def test_connect_bitexact(make, L):
@@ -195,7 +206,7 @@ def full_csr(sysm, nF):
 
 
 @pytest.mark.parametrize("make,L,kind", [(M.kuhn_cube, 1, "sin3"), (M.kuhn_cube, 3, "sin3"), (M.fichera, 1, "rough"),
-                                         (M.kuhn_cube, 2, "p1")])
+                                         (M.kuhn_cube, 2, "p1"), (disjoint_tets, 0, "rough")])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
 def test_condense_parity(make, L, kind, precision, tol):
     X, T, _, _ = levels(make, L)
@@ -338,6 +349,29 @@ def test_refine_connected_bitexact(case):
         for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma",
                   "face2tet", "nbr"):
             assert np.array_equal(host(conn[k]), oc[k]), k
+
+
+def test_refine_connected_input_check():
+    """An edge id outside [0, nEd) is caught (clamped in the kernels, reported): EINVAL when
+    synchronous, status bit 1 when checked on the device; a valid level leaves status 0."""
+    from paper_2509_11133_amd import _binding as B
+    X, T, _, _ = levels(M.kuhn_cube, 1)
+    Xd, Td = dev(X), dev(T)
+    conn = P.connect(Td, X.shape[1], faces=True)
+    bad = dict(conn)
+    t2e = conn["tet2edge"].clone()
+    t2e[2, 5] = conn["nEd"] + 7
+    bad["tet2edge"] = t2e
+    with pytest.raises(B.PhfemError):
+        P.refine_connected(Xd, Td, bad)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    P.refine_connected(Xd, Td, bad, st)
+    assert int(st.item()) & 1
+    with pytest.raises(B.PhfemError):
+        P.check_status(st)
+    st.zero_()
+    P.refine_connected(Xd, Td, conn, st)
+    assert int(st.item()) == 0
 
 
 def test_refine_connected_matches_sort_connect_L5():
