@@ -190,11 +190,11 @@ int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const int32_t* t
                    double* S, double* r, phfem_stream_t stream);
 
 /* ---------------------------------------------------------------- condense (a5-a7) --- */
-size_t phfem_condense_workspace(int64_t nE, int64_t nF, int32_t precision);
+size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision);
 
 /* Condensed face system S+ lambda = r+ with S+ = sum_T P_T' C A^-1 C' P_T and
  * r+ = b_D - sum_T P_T' C A^-1 B, b_D,F = |F| u_D(centroid F) on boundary faces
- * (Algorithm 1 lines "Assemble", Listing 8; sign-flipped to SPD form).
+ * (the assembly step of Algorithm 1, Listing 8; sign-flipped to SPD form).
  * Storage: diagonal separate, off-diagonals as CSR with columns ascending:
  *   rowptr[nF+1] (row F holds 6 entries, 3 for a boundary face), col[6 nF] and val[6 nF]
  *   (capacities), diag[nF], rhs[nF]; all float64 (the FP64 sums of FP32 blocks in mixed).

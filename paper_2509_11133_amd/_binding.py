@@ -86,7 +86,7 @@ def lib():
                   "phfem_grad_workspace", "phfem_refine_connected_workspace"):
             getattr(L, n).restype = SZ
         L.phfem_connect_workspace.argtypes = [I64, I64, I32]
-        L.phfem_condense_workspace.argtypes = [I64, I64, I32]
+        L.phfem_condense_workspace.argtypes = [I64, I64, I64, I32]
         L.phfem_solve_workspace.argtypes = [I64, I64, I32]
         L.phfem_grad_workspace.argtypes = [I64, I64, I32]
         L.phfem_refine_connected_workspace.argtypes = [I64, I64]

@@ -183,6 +183,24 @@ __device__ __forceinline__ void load_vec(const double x[4][3], double vol, const
   for (int i = 0; i < 4; ++i) B[i] = w * (((fc[0] + fc[1]) + (fc[2] + fc[3])) - fc[opp(i)]);
 }
 
+// AoS copy of the coordinates, one 32-byte (x, y, z, 0) record per node: a tet's gather
+// then touches 4 cache lines instead of 12
+__global__ __launch_bounds__(FT) void k_coords_aos(int64_t nC, const double* __restrict__ X, double4* __restrict__ XA) {
+  const int64_t v = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (v >= nC) return;
+  XA[v] = make_double4(X[v], X[nC + v], X[2 * nC + v], 0.0);
+}
+
+__device__ __forceinline__ void gather_xa(const double4* __restrict__ XA, const int v[4], double x[4][3]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double4 p = XA[v[i]];
+    x[i][0] = p.x;
+    x[i][1] = p.y;
+    x[i][2] = p.z;
+  }
+}
+
 __device__ __forceinline__ void gather_x(int64_t nC, const double* __restrict__ X, const int v[4], double x[4][3]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -266,13 +284,15 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
   rhs[f] = b;
 }
 
-// Condensation in two coalesced passes (no atomics):
-//  k_elem_rec: one tet -> four slot records (row k of S(T), (C A^-1 B)_k and the ids of the
-//              other three faces), each stored at its face: rec[F] from the owner (sigma = +1),
-//              rec[nF + F] from the neighbour, so the face pass reads both sides contiguously;
-//  k_face_rows: one face -> its whole CSR row from the records of its owner and neighbour:
-//              off-diagonals sorted by column, diagonal S_owner + S_neighbour and
-//              rhs (b_D - r_owner) - r_neighbour in that order.
+// Condensation in two passes (no atomics):
+//  k_elem_rec: one tet -> four slot records (slot 4t+k: row k of S(T), (C A^-1 B)_k and the
+//              ids of the other three faces), staged in LDS and stored with coalesced
+//              full-line writes;
+//  k_face_rows: one face -> its whole CSR row from the slots of its owner and neighbour
+//              (face2tet): off-diagonals sorted by column, diagonal S_owner + S_neighbour
+//              and rhs (b_D - r_owner) - r_neighbour in that order.
+// The neighbour slot is a random read; scattering the records to face order instead would
+// turn it into a random partial-line write, which costs more.
 // position of S_kl (either order) in the row-major upper triangle of a 4x4 matrix
 __host__ __device__ constexpr int uidx(int k, int l) {
   return k <= l ? (k * (7 - k)) / 2 + l : (l * (7 - l)) / 2 + k;
@@ -290,60 +310,35 @@ struct SlotRec {  // row k of one tet's element Schur block S(T) and (C A^-1 B)_
 };
 static_assert(sizeof(SlotRec<float>) == 32 && sizeof(SlotRec<double>) == 56, "packed slot records");
 
-// Faces are numbered by (owner tet, local face), so the faces owned by one workgroup's tets
-// form one contiguous id range: the first CAP of their records are staged in LDS and written
-// out with coalesced stores; the rest, and the records of faces owned by another tet
-// (sigma = -1), go out directly.
 template <class R>
-__global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double* __restrict__ X, int64_t nE,
+__global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __restrict__ XA, int64_t nE,
                                                  const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                                  const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
                                                  DevParams P, int64_t nF, SlotRec<R>* __restrict__ recs) {
   constexpr int W = sizeof(SlotRec<R>) / 8;
-  constexpr int CAP = 5 * FT / 2;  // staged records per workgroup (about 2 owned faces per tet)
-  __shared__ uint2 lrec[CAP * W];
-  __shared__ int sbase, scount;
-  const int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
-  const bool valid = t < nE;
-  if (threadIdx.x == 0) {
-    sbase = INT_MAX;
-    scount = 0;
-  }
-  int v[4] = {0, 0, 0, 0}, sig[4] = {0, 0, 0, 0}, F[4] = {-1, -1, -1, -1};
-  int mymin = INT_MAX, mycnt = 0;
-  if (valid) {
+  __shared__ uint2 lrec[4 * FT * W];
+  const int64_t t0 = (int64_t)blockIdx.x * FT;
+  const int64_t t = t0 + threadIdx.x;
+  if (t < nE) {
+    int v[4], sig[4], F[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       v[i] = tet[i * nE + t];
+      if ((uint32_t)v[i] >= (uint64_t)nC) v[i] = 0;
       sig[i] = sigma[i * nE + t];
       F[i] = t2f[i * nE + t];
-      if ((uint32_t)F[i] >= (uint64_t)nF) F[i] = -1;
-      if (F[i] >= 0 && sig[i] > 0) {
-        mymin = F[i] < mymin ? F[i] : mymin;
-        ++mycnt;
-      }
     }
-  }
-  __syncthreads();
-  if (mycnt) {
-    atomicMin(&sbase, mymin);
-    atomicAdd(&scount, mycnt);
-  }
-  __syncthreads();
-  const int base = sbase, cnt = scount;
-  if (valid) {
     double x[4][3];
-    gather_x(nC, X, v, x);
+    gather_xa(XA, v, x);
     const double kap = kappa ? kappa[t] : P.kc;
     Elem<R> E;
-    E.init(x, kap, P.c, sig);  // a degenerate tet contributes zeros (d = 0)
+    E.init(x, kap, P.c, sig);
     R B[4], r[4], su[10];
     load_vec<R>(x, E.vol, P, B);
     E.CAinv(B, r);
     E.Supper(su);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (F[k] < 0) continue;
       union {
         SlotRec<R> rec;
         uint2 w[W];
@@ -358,22 +353,14 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double* __res
         u.rec.c[n] = F[l];
         ++n;
       }
-      const int li = F[k] - base;
-      if (sig[k] > 0 && li >= 0 && li < CAP) {
 #pragma unroll
-        for (int m = 0; m < W; ++m) lrec[li * W + m] = u.w[m];
-      } else {
-        recs[(sig[k] > 0 ? 0 : nF) + F[k]] = u.rec;
-      }
+      for (int m = 0; m < W; ++m) lrec[(4 * threadIdx.x + k) * W + m] = u.w[m];
     }
   }
   __syncthreads();
-  if (cnt > 0) {
-    int64_t n = cnt < CAP ? cnt : CAP;
-    if (base + n > nF) n = nF - base;
-    uint2* out = reinterpret_cast<uint2*>(recs + base);
-    for (int i = threadIdx.x; i < n * W; i += FT) out[i] = lrec[i];
-  }
+  const int64_t nb = nE - t0 < FT ? nE - t0 : FT;
+  uint2* out = reinterpret_cast<uint2*>(recs + 4 * t0);
+  for (int i = threadIdx.x; i < 4 * nb * W; i += FT) out[i] = lrec[i];
 }
 
 // The rows of one workgroup's faces form one contiguous range of the CSR arrays: they are
@@ -394,7 +381,8 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
   const int blo = rowptr[f0];
   const int bhi = rowptr[fend];
   if (f < nF) {
-    const bool interior = face2tet[nF + f] >= 0;
+    const int q0 = face2tet[f], q1 = face2tet[nF + f];
+    const bool interior = q1 >= 0;
     int cf[6];
     double cv[6];
     int n = 0;
@@ -415,7 +403,7 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
                                  (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
     }
     {
-      const SlotRec<R> a = recs[f];  // owner's row of its element block
+      const SlotRec<R> a = recs[q0];
       dg = (double)a.d;
       rh -= (double)a.r;
 #pragma unroll
@@ -426,7 +414,7 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
       n = 3;
     }
     if (interior) {
-      const SlotRec<R> b = recs[nF + f];  // neighbour's row
+      const SlotRec<R> b = recs[q1];
       dg += (double)b.d;
       rh -= (double)b.r;
 #pragma unroll
@@ -702,12 +690,13 @@ extern "C" int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const
   return PHFEM_OK;
 }
 
-extern "C" size_t phfem_condense_workspace(int64_t nE, int64_t nF, int32_t precision) {
+extern "C" size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision) {
   Arena a;
+  a.take<double4>(nC);
   if (precision == PHFEM_MIXED)
-    a.take<SlotRec<float>>(2 * nF);
+    a.take<SlotRec<float>>(4 * nE);
   else
-    a.take<SlotRec<double>>(2 * nF);
+    a.take<SlotRec<double>>(4 * nE);
   a.take<int>(16);
   return a.size() + scan_workspace(nF + 1);
 }
@@ -726,11 +715,12 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
       !col || !val || !diag || !rhs)
     return err(PHFEM_EINVAL, "bad condense arguments");
   if (6 * nF >= (int64_t(1) << 31)) return err(PHFEM_EINVAL, "face system exceeds int32 indexing");
-  if (!work || work_bytes < phfem_condense_workspace(nE, nF, p->precision))
+  if (!work || work_bytes < phfem_condense_workspace(nC, nE, nF, p->precision))
     return err(PHFEM_EWORKSPACE, "condense workspace too small");
   Arena a(work, work_bytes);
   const bool mixed = p->precision == PHFEM_MIXED;
-  void* recs = mixed ? (void*)a.take<SlotRec<float>>(2 * nF) : (void*)a.take<SlotRec<double>>(2 * nF);
+  double4* XA = a.take<double4>(nC);
+  void* recs = mixed ? (void*)a.take<SlotRec<float>>(4 * nE) : (void*)a.take<SlotRec<double>>(4 * nE);
   a.take<int>(16);
   DevParams P = to_dev(*p);
   rc = launch_face_init(nF, nC, coord, faces, face2tet, P, (uint32_t*)rowptr, nullptr, nullptr, s);
@@ -744,13 +734,14 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
   const double rb = 4.0 * (double)(mixed ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>));
   const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
   const double fb = rb * nE + 8.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
+  PH_LAUNCH_B("coords_aos", 56.0 * nC, k_coords_aos, grid_for(nC, FT), FT, 0, s, nC, coord, XA);
   if (mixed) {
-    PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face,
+    PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
                 sigma, kappa, P, nF, (SlotRec<float>*)recs);
     PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces, face2tet,
                 P, (const SlotRec<float>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
   } else {
-    PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, FT), FT, 0, s, nC, coord, nE, tetra, tet2face,
+    PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
                 sigma, kappa, P, nF, (SlotRec<double>*)recs);
     PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
                 face2tet, P, (const SlotRec<double>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);

@@ -391,21 +391,53 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
   }
 }
 
-// pass 2: ids of the refined edges and faces of every row, and all outputs
+// pass 2: ids of the refined edges and faces of every row, and all outputs.  Phase 1 stages
+// the per-row outputs in LDS and writes them as two contiguous row ranges; phase 2 reuses
+// the LDS for the records of the edges and faces first seen in the workgroup's rows, whose
+// ids form one contiguous range per row range, and writes those out contiguously too.
 constexpr int RCO = 16;  // staged words per row: pre, 6 edges, 4 faces, 4 neighbours, 4 packed signs
+constexpr int RCL = RCO * RCW * RCS;  // LDS words
+// phase-2 capacities (entities per row range): child-0 rows exactly (<= 6 edges, 4 faces
+// each), the other rows about 1.2 edges and 2 faces per row; overflow goes out directly
+constexpr int CE1 = 6 * RCW, CF1 = 4 * RCW, CE2 = 1024;
+constexpr int CF2 = (RCL - 3 * CE1 - 5 * CF1 - 3 * CE2) / 5;
+static_assert(CF2 >= 2 * 11 * RCW + 64, "room for the typical face count of a workgroup");
+constexpr int OE1 = 0, OF1 = OE1 + 3 * CE1, OE2 = OF1 + 5 * CF1, OF2 = OE2 + 3 * CE2;  // SoA blocks
+
+struct RCRange {  // one row range's first-seen edges and faces: [e0, e0 + ne), [f0, f0 + nf)
+  int64_t e0, f0;
+  int ne, nf;
+};
+
 __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
-  __shared__ int32_t sW[RCO * RCW * RCS];
+  __shared__ int32_t sW[RCL];
+  __shared__ RCRange sR[2];
   const RCBlock B = rc_block(A);
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t nEd2 = A.nEd2, nF2 = A.nF2;
+  const int64_t nE = A.nE, nEd2 = A.nEd2, nF2 = A.nF2;
+  if (threadIdx.x < 2) {  // ranges from the prefix records (exact for consistent input)
+    const bool r2 = threadIdx.x == 1;
+    const int64_t lo = r2 ? nE + 11 * B.t0 : B.t0;
+    const int64_t hi = r2 ? nE + 11 * (B.t0 + B.nb) : B.t0 + B.nb;  // row after the range
+    const bool last = r2 && hi == A.nE2;
+    const int64_t e0 = A.recE[lo] >> 6, f0 = A.recF[lo] >> 4;
+    const int64_t e1 = last ? nEd2 : (int64_t)(A.recE[hi] >> 6), f1 = last ? nF2 : (int64_t)(A.recF[hi] >> 4);
+    RCRange R;
+    R.e0 = e0;
+    R.f0 = f0;
+    R.ne = (int)(e1 > e0 ? e1 - e0 : 0);
+    R.nf = (int)(f1 > f0 ? f1 - f0 : 0);
+    sR[threadIdx.x] = R;
+  }
+  CT T;
+  int32_t fnb[4] = {-1, -1, -1, -1};  // f2t slot of the other side, per owned local face
   if (lane < B.nb) {
-    CT T;
     load_ct(A, B.t0 + lane, T);
     sfor<12>([&](auto Cc) {
       constexpr int C = decltype(Cc)::value;
       if (c != C) return;
-      const int64_t r = rowc<C>(A.nE, T.t);
+      const int64_t r = rowc<C>(nE, T.t);
       int32_t* w = sW + lane * RCS + C;
       const uint32_t oe = A.recE[r], of = A.recF[r];
       const int me = oe & 63, mf = of & 15;
@@ -415,12 +447,6 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
         int32_t id;
         if ((me >> J) & 1) {
           id = (int32_t)((oe >> 6) + __popc(me & ((1 << J) - 1)));
-          const int na = sym_node<ch(C, ev0(J))>(A, T), nb = sym_node<ch(C, ev1(J))>(A, T);
-          if ((uint32_t)id < (uint64_t)nEd2) {
-            A.edges2[id] = na < nb ? na : nb;
-            A.edges2[nEd2 + id] = na < nb ? nb : na;
-            A.eft2[id] = (int32_t)r;
-          }
         } else {
           int64_t er;
           int ej;
@@ -440,13 +466,7 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
         int32_t id;
         if (own) {
           id = (int32_t)((of >> 4) + __popc(mf & ((1 << K) - 1)));
-          if ((uint32_t)id < (uint64_t)nF2) {
-            A.f2t2[id] = (int32_t)(4 * r + K);
-            A.f2t2[nF2 + id] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
-            A.faces2[id] = sym_node<ch(C, fv(K, 0))>(A, T);
-            A.faces2[nF2 + id] = sym_node<ch(C, fv(K, 1))>(A, T);
-            A.faces2[2 * nF2 + id] = sym_node<ch(C, fv(K, 2))>(A, T);
-          }
+          fnb[K] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
         } else if (fr >= 0) {
           const uint32_t o = A.recF[fr];
           id = (int32_t)((o >> 4) + __popc((o & 15) & ((1u << fk) - 1)));
@@ -474,6 +494,82 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
       A.t2f2[k * n2 + row] = v[(7 + k) * RCW * RCS];
       A.nbr2[k * n2 + row] = v[(11 + k) * RCW * RCS];
       A.sig2[k * n2 + row] = (int8_t)(((uint32_t)v[15 * RCW * RCS] >> (8 * k)) & 0xffu);
+    }
+  }
+  __syncthreads();
+  // phase 2: records of the edges and faces first seen in these rows
+  if (lane < B.nb) {
+    sfor<12>([&](auto Cc) {
+      constexpr int C = decltype(Cc)::value;
+      if (c != C) return;
+      const int64_t r = rowc<C>(nE, T.t);
+      const RCRange R = sR[C == 0 ? 0 : 1];
+      constexpr int oe_ = C == 0 ? OE1 : OE2, ce = C == 0 ? CE1 : CE2;
+      constexpr int of_ = C == 0 ? OF1 : OF2, cf = C == 0 ? CF1 : CF2;
+      const uint32_t oe = A.recE[r], of = A.recF[r];
+      const int me = oe & 63, mf = of & 15;
+      sfor<6>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        if (!((me >> J) & 1)) return;
+        const int64_t id = (oe >> 6) + __popc(me & ((1 << J) - 1));
+        const int na = sym_node<ch(C, ev0(J))>(A, T), nb = sym_node<ch(C, ev1(J))>(A, T);
+        const int lo = na < nb ? na : nb, hi = na < nb ? nb : na;
+        const int64_t li = id - R.e0;
+        if (li >= 0 && li < ce && li < R.ne) {
+          sW[oe_ + li] = lo;
+          sW[oe_ + ce + li] = hi;
+          sW[oe_ + 2 * ce + li] = (int32_t)r;
+        } else if (id < nEd2) {
+          A.edges2[id] = lo;
+          A.edges2[nEd2 + id] = hi;
+          A.eft2[id] = (int32_t)r;
+        }
+      });
+      sfor<4>([&](auto Kc) {
+        constexpr int K = decltype(Kc)::value;
+        if (!((mf >> K) & 1)) return;
+        const int64_t id = (of >> 4) + __popc(mf & ((1 << K) - 1));
+        const int n0 = sym_node<ch(C, fv(K, 0))>(A, T), n1 = sym_node<ch(C, fv(K, 1))>(A, T),
+                  n2 = sym_node<ch(C, fv(K, 2))>(A, T);
+        const int64_t li = id - R.f0;
+        if (li >= 0 && li < cf && li < R.nf) {
+          sW[of_ + li] = (int32_t)(4 * r + K);
+          sW[of_ + cf + li] = fnb[K];
+          sW[of_ + 2 * cf + li] = n0;
+          sW[of_ + 3 * cf + li] = n1;
+          sW[of_ + 4 * cf + li] = n2;
+        } else if (id < nF2) {
+          A.f2t2[id] = (int32_t)(4 * r + K);
+          A.f2t2[nF2 + id] = fnb[K];
+          A.faces2[id] = n0;
+          A.faces2[nF2 + id] = n1;
+          A.faces2[2 * nF2 + id] = n2;
+        }
+      });
+    });
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const RCRange R = sR[g];
+    const int oe_ = g == 0 ? OE1 : OE2, ce = g == 0 ? CE1 : CE2;
+    const int of_ = g == 0 ? OF1 : OF2, cf = g == 0 ? CF1 : CF2;
+    int ne = R.ne < ce ? R.ne : ce, nf = R.nf < cf ? R.nf : cf;
+    if (R.e0 + ne > nEd2) ne = R.e0 < nEd2 ? (int)(nEd2 - R.e0) : 0;  // inconsistent input only
+    if (R.f0 + nf > nF2) nf = R.f0 < nF2 ? (int)(nF2 - R.f0) : 0;
+    for (int i = threadIdx.x; i < ne; i += RCB) {
+      const int64_t id = R.e0 + i;
+      A.edges2[id] = sW[oe_ + i];
+      A.edges2[nEd2 + id] = sW[oe_ + ce + i];
+      A.eft2[id] = sW[oe_ + 2 * ce + i];
+    }
+    for (int i = threadIdx.x; i < nf; i += RCB) {
+      const int64_t id = R.f0 + i;
+      A.f2t2[id] = sW[of_ + i];
+      A.f2t2[nF2 + id] = sW[of_ + cf + i];
+      A.faces2[id] = sW[of_ + 2 * cf + i];
+      A.faces2[nF2 + id] = sW[of_ + 3 * cf + i];
+      A.faces2[2 * nF2 + id] = sW[of_ + 4 * cf + i];
     }
   }
 }

@@ -132,7 +132,7 @@ def condense(coord, tetra, conn, kappa, prm):
     """Condensed face system (a5-a7): diag, off-diagonal CSR (rowptr, col, val), rhs."""
     dev = coord.device
     nC, nE, nF, nB = coord.shape[1], tetra.shape[1], conn["nF"], conn["nB"]
-    work = B.workspace(B.lib().phfem_condense_workspace(nE, nF, prm.precision), dev)
+    work = B.workspace(B.lib().phfem_condense_workspace(nC, nE, nF, prm.precision), dev)
     nnz = 6 * nF - 3 * nB
     rowptr = torch.empty(nF + 1, dtype=I32, device=dev)
     col = torch.empty(max(nnz, 1), dtype=I32, device=dev)

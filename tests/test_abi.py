@@ -35,8 +35,8 @@ def test_workspace_queries():
     assert L.phfem_connect_workspace(8, 6, 7) > 0
     assert L.phfem_connect_workspace(0, 6, 7) == 0
     assert L.phfem_connect_workspace(10 ** 6, 10 ** 6, 1) > 10 ** 6 * 6 * 20
-    assert L.phfem_condense_workspace(50, 100, 1) > 0
-    assert L.phfem_condense_workspace(50, 100, 0) > L.phfem_condense_workspace(50, 100, 1)
+    assert L.phfem_condense_workspace(20, 50, 100, 1) > 0
+    assert L.phfem_condense_workspace(20, 50, 100, 0) > L.phfem_condense_workspace(20, 50, 100, 1)
     assert L.phfem_solve_workspace(100, 200, 1) > L.phfem_solve_workspace(100, 200, 0)
     assert L.phfem_grad_workspace(100, 200, 0) > L.phfem_solve_workspace(100, 200, 0)
 
