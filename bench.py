@@ -72,11 +72,12 @@ def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False):
 
 
 def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort_connect=False):
+    """ms per step (HIP events around `steps` steps, profiler off), host wall ms per step,
+    and -- from a second, separately run set of `steps` steps with the per-launch event
+    profiler on -- per-kernel launches / ms / algorithmic bytes."""
     for _ in range(warmup):
         run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
     torch.cuda.synchronize()
-    B.phfem_profile_reset()
-    B.phfem_profile_enable(profile)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
@@ -85,10 +86,16 @@ def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    B.phfem_profile_enable(False)
     ms = e0.elapsed_time(e1) / steps
     kern = {}
     if profile:
+        del out
+        B.phfem_profile_reset()
+        B.phfem_profile_enable(True)
+        for _ in range(steps):
+            out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
+        torch.cuda.synchronize()
+        B.phfem_profile_enable(False)
         for name in B.phfem_profile_names():
             n, tms, by = B.phfem_profile_query(name)
             kern[name] = dict(launches=n, ms=tms, bytes=by)
@@ -170,7 +177,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=5)
-    ap.add_argument("--no-profile", action="store_true", help="time without the per-launch HIP events")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (per-kernel HIP events)")
     ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -173,6 +173,27 @@ int phfem_refine_connected(int64_t nC, const double* coord, int64_t nE, const in
                            int32_t* tet2face_out, int8_t* sigma_out, int32_t* face2tet_out, int32_t* nbr_out,
                            int64_t* counts, int32_t* status, phfem_stream_t stream);
 
+/* Mesh sizes after `levels` refinements: out[4] = {nC, nE, nEd, nF} by the recurrences of
+ * phfem_refine_connected (host only).  EINVAL for levels < 0 or non-positive sizes. */
+int phfem_refined_sizes(int64_t nC, int64_t nE, int64_t nEd, int64_t nF, int32_t levels, int64_t* out);
+
+/* `levels` (1..16) chained phfem_refine_connected calls in one call: the intermediate
+ * meshes live in the workspace (two buffers sized for level levels-1), only the last
+ * level's mesh and connectivity are written to the outputs (capacities: the sizes of
+ * phfem_refined_sizes(..., levels)), counts[3] as for one level.  Results are bitwise those
+ * of the chained calls.  status as for phfem_refine_connected (one word collects every
+ * level); with status == NULL the call synchronizes once at the end and returns EINVAL if
+ * any level's check failed.  Workspace bytes: phfem_refine_connected_levels_workspace. */
+size_t phfem_refine_connected_levels_workspace(int64_t nC, int64_t nE, int64_t nEd, int64_t nF, int32_t levels);
+int phfem_refine_connected_levels(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
+                                  int64_t nF, const int32_t* tet2edge, const int32_t* edge_first_tet,
+                                  const int32_t* tet_edge_prefix, const int32_t* tet2face, const int32_t* nbr,
+                                  int32_t levels, void* work, size_t work_bytes, double* coord_out, int32_t* tetra_out,
+                                  int32_t* edges_out, int32_t* tet2edge_out, int32_t* edge_first_tet_out,
+                                  int32_t* tet_edge_prefix_out, int32_t* faces_out, int32_t* tet2face_out,
+                                  int8_t* sigma_out, int32_t* face2tet_out, int32_t* nbr_out, int64_t* counts,
+                                  int32_t* status, phfem_stream_t stream);
+
 /* ---------------------------------------------------------------- assemble (a5-a6) --- */
 /* Per-tet local blocks (Sections 4.2-4.5; StiffMassPH, Multiplier, the page solves of
  * SchurComplement_vectorization).  kappa[nE] may be NULL (then p->kappa_const).

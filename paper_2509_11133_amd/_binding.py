@@ -26,7 +26,8 @@ EXPORTS = [
     "phfem_last_error", "phfem_abi_version", "phfem_connect_workspace", "phfem_connect", "phfem_refine",
     "phfem_assemble", "phfem_condense_workspace", "phfem_condense", "phfem_solve_workspace", "phfem_solve",
     "phfem_grad_workspace", "phfem_grad", "phfem_profile_enable", "phfem_profile_reset", "phfem_profile_query",
-    "phfem_profile_names", "phfem_refine_connected_workspace", "phfem_refine_connected",
+    "phfem_profile_names", "phfem_refine_connected_workspace", "phfem_refine_connected", "phfem_refined_sizes",
+    "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels",
 ]
 
 
@@ -83,13 +84,18 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.phfem_last_error.restype = C.c_char_p
         for n in ("phfem_connect_workspace", "phfem_condense_workspace", "phfem_solve_workspace",
-                  "phfem_grad_workspace", "phfem_refine_connected_workspace"):
+                  "phfem_grad_workspace", "phfem_refine_connected_workspace",
+                  "phfem_refine_connected_levels_workspace"):
             getattr(L, n).restype = SZ
         L.phfem_connect_workspace.argtypes = [I64, I64, I32]
         L.phfem_condense_workspace.argtypes = [I64, I64, I64, I32]
         L.phfem_solve_workspace.argtypes = [I64, I64, I32]
         L.phfem_grad_workspace.argtypes = [I64, I64, I32]
         L.phfem_refine_connected_workspace.argtypes = [I64, I64]
+        L.phfem_refine_connected_levels_workspace.argtypes = [I64, I64, I64, I64, I32]
+        L.phfem_refined_sizes.argtypes = [I64, I64, I64, I64, I32, VP]
+        L.phfem_refine_connected_levels.argtypes = ([I64, VP, I64, VP, I64, I64] + [VP] * 5 + [I32, VP, SZ]
+                                                    + [VP] * 11 + [VP] * 3)
         L.phfem_refine_connected.argtypes = [I64, VP, I64, VP, I64, I64] + [VP] * 5 + [VP, SZ] + [VP] * 11 + [VP] * 3
         L.phfem_connect.argtypes = [I64, I64, VP, I32, VP, SZ] + [VP] * 12 + [VP, VP]
         L.phfem_refine.argtypes = [I64, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP]
@@ -156,6 +162,23 @@ def phfem_refine_connected(nC, coord, nE, tetra, nEd, nF, tet2edge, edge_first_t
                                       _p(edge_first_tet_out), _p(tet_edge_prefix_out), _p(faces_out),
                                       _p(tet2face_out), _p(sigma_out), _p(face2tet_out), _p(nbr_out), _p(counts),
                                       _p(status), _stream()))
+
+
+def phfem_refined_sizes(nC, nE, nEd, nF, levels):
+    out = np.zeros(4, np.int64)
+    _chk(lib().phfem_refined_sizes(nC, nE, nEd, nF, levels, out.ctypes.data))
+    return tuple(int(v) for v in out)
+
+
+def phfem_refine_connected_levels(nC, coord, nE, tetra, nEd, nF, tet2edge, edge_first_tet, tet_edge_prefix, tet2face,
+                                  nbr, levels, work, coord_out, tetra_out, edges_out, tet2edge_out,
+                                  edge_first_tet_out, tet_edge_prefix_out, faces_out, tet2face_out, sigma_out,
+                                  face2tet_out, nbr_out, counts, status=None):
+    _chk(lib().phfem_refine_connected_levels(
+        nC, _p(coord), nE, _p(tetra), nEd, nF, _p(tet2edge), _p(edge_first_tet), _p(tet_edge_prefix), _p(tet2face),
+        _p(nbr), levels, _p(work), work.numel(), _p(coord_out), _p(tetra_out), _p(edges_out), _p(tet2edge_out),
+        _p(edge_first_tet_out), _p(tet_edge_prefix_out), _p(faces_out), _p(tet2face_out), _p(sigma_out),
+        _p(face2tet_out), _p(nbr_out), _p(counts), _p(status), _stream()))
 
 
 def phfem_assemble(nC, coord, nE, tetra, sigma, kappa, prm, vol, K, d, B, S, r):

@@ -730,3 +730,138 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   counts[2] = 2 * nF2 - 4 * nE2;
   return PHFEM_OK;
 }
+
+// ---------------------------------------------------------------- several levels in one call
+namespace ph {
+
+struct MeshSizes {
+  int64_t nC, nE, nEd, nF;
+};
+static MeshSizes refined(const MeshSizes& m) {
+  return {m.nC + m.nEd + m.nE, 12 * m.nE, 2 * m.nEd + 3 * m.nF + 6 * m.nE, 4 * m.nF + 16 * m.nE};
+}
+
+// the arrays of one mesh with its connectivity, carved from an arena
+struct MeshBufs {
+  double* coord;
+  int32_t *tetra, *edges, *t2e, *eft, *pre, *faces, *t2f, *f2t, *nbr;
+  int8_t* sigma;
+};
+static void mesh_layout(Arena& a, const MeshSizes& m, MeshBufs& b) {
+  b.coord = a.take<double>(3 * m.nC);
+  b.tetra = a.take<int32_t>(4 * m.nE);
+  b.edges = a.take<int32_t>(2 * m.nEd);
+  b.t2e = a.take<int32_t>(6 * m.nE);
+  b.eft = a.take<int32_t>(m.nEd);
+  b.pre = a.take<int32_t>(m.nE);
+  b.faces = a.take<int32_t>(3 * m.nF);
+  b.t2f = a.take<int32_t>(4 * m.nE);
+  b.sigma = a.take<int8_t>(4 * m.nE);
+  b.f2t = a.take<int32_t>(2 * m.nF);
+  b.nbr = a.take<int32_t>(4 * m.nE);
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+struct LevelsWS {
+  MeshBufs m[2];  // ping-pong intermediate meshes (levels 1 .. L-1), sized for level L-1
+  int32_t* status;
+  void* sub;
+  size_t sub_bytes;
+};
+static size_t levels_layout(Arena& a, MeshSizes m, int L, LevelsWS* w) {
+  MeshSizes mid = m;  // largest intermediate: level L-1
+  size_t inner = 0;
+  for (int l = 0; l < L; ++l) {
+    inner = std::max(inner, phfem_refine_connected_workspace(mid.nE, mid.nEd));
+    if (l < L - 1) mid = refined(mid);
+  }
+  MeshBufs b[2];
+  for (int i = 0; i < 2; ++i) mesh_layout(a, L > 1 ? mid : MeshSizes{0, 0, 0, 0}, b[i]);
+  int32_t* st = a.take<int32_t>(64);
+  void* sub = a.take<uint8_t>(inner);
+  if (w) {
+    w->m[0] = b[0];
+    w->m[1] = b[1];
+    w->status = st;
+    w->sub = sub;
+    w->sub_bytes = inner;
+  }
+  return a.size();
+}
+
+}  // namespace ph
+
+extern "C" int phfem_refined_sizes(int64_t nC, int64_t nE, int64_t nEd, int64_t nF, int32_t levels, int64_t* out) {
+  clear_error();
+  if (!out || levels < 0 || nC <= 0 || nE <= 0 || nEd <= 0 || nF <= 0) return err(PHFEM_EINVAL, "bad arguments");
+  MeshSizes m{nC, nE, nEd, nF};
+  for (int l = 0; l < levels; ++l) {
+    m = refined(m);
+    if (m.nE > (int64_t(1) << 40)) return err(PHFEM_EINVAL, "sizes overflow");
+  }
+  out[0] = m.nC;
+  out[1] = m.nE;
+  out[2] = m.nEd;
+  out[3] = m.nF;
+  return PHFEM_OK;
+}
+
+extern "C" size_t phfem_refine_connected_levels_workspace(int64_t nC, int64_t nE, int64_t nEd, int64_t nF,
+                                                          int32_t levels) {
+  if (nC <= 0 || nE <= 0 || nEd <= 0 || nF <= 0 || levels < 1 || levels > 16) return 0;
+  Arena a;
+  return levels_layout(a, MeshSizes{nC, nE, nEd, nF}, levels, nullptr);
+}
+
+extern "C" int phfem_refine_connected_levels(
+    int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd, int64_t nF,
+    const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix, const int32_t* tet2face,
+    const int32_t* nbr, int32_t levels, void* work, size_t work_bytes, double* coord_out, int32_t* tetra_out,
+    int32_t* edges_out, int32_t* tet2edge_out, int32_t* edge_first_tet_out, int32_t* tet_edge_prefix_out,
+    int32_t* faces_out, int32_t* tet2face_out, int8_t* sigma_out, int32_t* face2tet_out, int32_t* nbr_out,
+    int64_t* counts, int32_t* status, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  if (levels < 1 || levels > 16) return err(PHFEM_EINVAL, "levels must be in [1, 16]");
+  if (nC <= 0 || nE <= 0 || nEd <= 0 || nF <= 0) return err(PHFEM_EINVAL, "bad sizes");
+  const size_t need = phfem_refine_connected_levels_workspace(nC, nE, nEd, nF, levels);
+  if (!work || work_bytes < need) return err(PHFEM_EWORKSPACE, "refine_connected_levels workspace too small");
+  Arena a(work, work_bytes);
+  LevelsWS w;
+  levels_layout(a, MeshSizes{nC, nE, nEd, nF}, levels, &w);
+  int32_t* st = status ? status : w.status;
+  if (!status) PH_LAUNCH("zero_i32", k_zero_i32, 1, 64, 0, s, st);
+  MeshSizes m{nC, nE, nEd, nF};
+  MeshBufs in{const_cast<double*>(coord), const_cast<int32_t*>(tetra), nullptr, const_cast<int32_t*>(tet2edge),
+              const_cast<int32_t*>(edge_first_tet), const_cast<int32_t*>(tet_edge_prefix), nullptr,
+              const_cast<int32_t*>(tet2face), nullptr, const_cast<int32_t*>(nbr), nullptr};
+  for (int l = 0; l < levels; ++l) {
+    const bool last = l == levels - 1;
+    MeshBufs out = last ? MeshBufs{coord_out, tetra_out, edges_out, tet2edge_out, edge_first_tet_out,
+                                   tet_edge_prefix_out, faces_out, tet2face_out, face2tet_out, nbr_out, sigma_out}
+                        : w.m[l & 1];
+    int64_t c3[3];
+    int rc = phfem_refine_connected(m.nC, in.coord, m.nE, in.tetra, m.nEd, m.nF, in.t2e, in.eft, in.pre, in.t2f,
+                                    in.nbr, w.sub, w.sub_bytes, out.coord, out.tetra, out.edges, out.t2e, out.eft,
+                                    out.pre, out.faces, out.t2f, out.sigma, out.f2t, out.nbr, c3, st, stream_);
+    if (rc) return rc;
+    m = refined(m);
+    in = out;
+    if (last && counts) {
+      counts[0] = c3[0];
+      counts[1] = c3[1];
+      counts[2] = c3[2];
+    }
+  }
+  if (!status) {
+    int32_t h = 0;
+    PH_HIP(hipMemcpyAsync(&h, st, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (h) return err(PHFEM_EINVAL, "input connectivity check failed (ids out of range or not a first-appearance "
+                                    "numbering of a conforming, consistently oriented mesh)");
+  }
+  return PHFEM_OK;
+}

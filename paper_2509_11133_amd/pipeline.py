@@ -104,16 +104,37 @@ def check_status(status):
             code, "edge id out of range" if code & 1 else "refined totals differ from the recurrences"))
 
 
-def refine_connected_levels(coord, tetra, levels):
-    """connect() on the input mesh, then `levels` x refine_connected, checked once at the end.
-    Returns (coord, tetra, conn)."""
-    conn = connect(tetra, coord.shape[1], faces=True)
-    status = torch.zeros(1, dtype=I32, device=coord.device)
-    for _ in range(levels):
-        coord, tetra, conn = refine_connected(coord, tetra, conn, status)
-    if levels:
-        check_status(status)
-    return coord, tetra, conn
+def refine_connected_levels(coord, tetra, levels, conn=None, status=None):
+    """connect() on the input mesh (unless `conn` is given), then `levels` refinements with
+    derived connectivity in one library call (phfem_refine_connected_levels).  Without
+    `status` the call checks its input and synchronizes once; with a zeroed device int32
+    `status` nothing synchronizes (read it with check_status).  Returns (coord, tetra, conn)."""
+    if conn is None:
+        conn = connect(tetra, coord.shape[1], faces=True)
+    if levels == 0:
+        return coord, tetra, conn
+    dev = coord.device
+    nC, nE, nEd, nF = coord.shape[1], tetra.shape[1], conn["nEd"], conn["nF"]
+    nC2, nE2, nEd2, nF2 = B.phfem_refined_sizes(nC, nE, nEd, nF, levels)
+    work = B.workspace(B.lib().phfem_refine_connected_levels_workspace(nC, nE, nEd, nF, levels), dev)
+    Xo = torch.empty((3, nC2), dtype=F64, device=dev)
+    To = torch.empty((4, nE2), dtype=I32, device=dev)
+    e = torch.empty((2, nEd2), dtype=I32, device=dev)
+    t2e = torch.empty((6, nE2), dtype=I32, device=dev)
+    eft = torch.empty(nEd2, dtype=I32, device=dev)
+    pre = torch.empty(nE2, dtype=I32, device=dev)
+    fa = torch.empty((3, nF2), dtype=I32, device=dev)
+    t2f = torch.empty((4, nE2), dtype=I32, device=dev)
+    sig = torch.empty((4, nE2), dtype=torch.int8, device=dev)
+    f2t = torch.empty((2, nF2), dtype=I32, device=dev)
+    nbr = torch.empty((4, nE2), dtype=I32, device=dev)
+    counts = np.zeros(3, np.int64)
+    B.phfem_refine_connected_levels(nC, coord, nE, tetra, nEd, nF, conn["tet2edge"], conn["edge_first_tet"],
+                                    conn["tet_edge_prefix"], conn["tet2face"], conn["nbr"], levels, work, Xo, To, e,
+                                    t2e, eft, pre, fa, t2f, sig, f2t, nbr, counts, status)
+    out = dict(nC=nC2, nE=nE2, nEd=int(counts[0]), edges=e, tet2edge=t2e, edge_first_tet=eft, tet_edge_prefix=pre,
+               nF=int(counts[1]), nB=int(counts[2]), faces=fa, tet2face=t2f, sigma=sig, face2tet=f2t, nbr=nbr)
+    return Xo, To, out
 
 
 def assemble(coord, tetra, sigma, kappa, prm):

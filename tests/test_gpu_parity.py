@@ -374,6 +374,27 @@ def test_refine_connected_input_check():
     assert int(st.item()) == 0
 
 
+@pytest.mark.parametrize("make,L", [(M.kuhn_cube, 1), (M.kuhn_cube, 4), (M.fichera, 3), (single_tet, 3)])
+def test_refine_connected_levels_equals_chained(make, L):
+    """One multi-level call = L chained single-level calls, bit for bit."""
+    X, T = make()[:2]
+    Xd, Td = dev(X), dev(T)
+    conn0 = P.connect(Td, X.shape[1], faces=True)
+    Xa, Ta, ca = Xd, Td, conn0
+    for _ in range(L):
+        Xa, Ta, ca = P.refine_connected(Xa, Ta, ca)
+    Xb, Tb, cb = P.refine_connected_levels(Xd, Td, L, conn=conn0)
+    assert torch.equal(Xa, Xb) and torch.equal(Ta, Tb)
+    for k in ("nEd", "nF", "nB"):
+        assert ca[k] == cb[k], k
+    for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma", "face2tet",
+              "nbr"):
+        assert torch.equal(ca[k], cb[k]), k
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    Xc, Tc, cc = P.refine_connected_levels(Xd, Td, L, conn=conn0, status=st)
+    assert int(st.item()) == 0 and torch.equal(cc["face2tet"], cb["face2tet"])
+
+
 def test_refine_connected_matches_sort_connect_L5():
     """At 1.49M tets (Kuhn, 5 levels): the derived connectivity equals the sort-based
     phfem_connect of the same refined mesh, bit for bit."""
