@@ -233,7 +233,8 @@ def main():
                                f"{nF} faces; sort-based connect of level 0, refine with derived connectivity per "
                                f"level, assemble + condense at the last level; mixed precision (FP32 local/Schur, "
                                f"FP64 dets and face system)",
-                   "levels": L, "nE": nE, "nC": nC, "nEd": nEd, "nF": nF, "nnz_offdiag": 6 * nF - 3 * nB},
+                   "levels": L, "nE": nE, "nC": nC, "nEd": nEd, "nF": nF, "nnz_offdiag": 6 * nF - 3 * nB,
+                   "stored_offdiag": 6 * nF},
         "fp64": {"value": round(nE / (fp64["ms"] * 1e-3), 1), "ms_per_step": round(fp64["ms"], 4),
                  "mixed_speedup": round(fp64["ms"] / mixed["ms"], 3)},
         "useful_hbm_frac": round(comp / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),

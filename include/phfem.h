@@ -216,14 +216,17 @@ size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t prec
 /* Condensed face system S+ lambda = r+ with S+ = sum_T P_T' C A^-1 C' P_T and
  * r+ = b_D - sum_T P_T' C A^-1 B, b_D,F = |F| u_D(centroid F) on boundary faces
  * (the assembly step of Algorithm 1, Listing 8; sign-flipped to SPD form).
- * Storage: diagonal separate, off-diagonals as CSR with columns ascending:
- *   rowptr[nF+1] (row F holds 6 entries, 3 for a boundary face), col[6 nF] and val[6 nF]
- *   (capacities), diag[nF], rhs[nF]; all float64 (the FP64 sums of FP32 blocks in mixed).
+ * Storage: diagonal separate, off-diagonals as CSR with a fixed 6 slots per row:
+ *   rowptr[nF+1] = 6 F, col[6 nF], val[6 nF], diag[nF], rhs[nF]; all float64 (the FP64
+ *   sums of FP32 blocks in mixed).  An interior face's row holds the 6 faces its two tets
+ *   couple it to, columns ascending; a boundary face's row holds its 3, ascending, then 3
+ *   explicit zeros in column F (boundary faces are O(nF^(2/3)), so the padding is a
+ *   vanishing fraction and the row pointers need no scan).
  * Each off-diagonal has exactly one contributing tet; a diagonal / rhs entry is the owner
- * tet's term plus the neighbour's (in that order).  Two coalesced passes: one contiguous
- * record per tet (element Schur block, C A^-1 B, face ids; FP32 records in mixed
- * precision), then one thread per face writes its whole row.  Inputs from phfem_connect
- * (nbr is not read and may be NULL).
+ * tet's term plus the neighbour's (in that order).  Two coalesced passes: four slot records
+ * per tet (row k of the element Schur block, (C A^-1 B)_k, the other face ids; FP32 records
+ * in mixed precision), then one thread per face writes its whole row.  Inputs from
+ * phfem_connect (nbr is not read and may be NULL).
  * Errors: EINVAL, ESINGULAR, EWORKSPACE.  Does not synchronize (EDEGEN is reported by
  * phfem_solve). */
 int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,

@@ -193,6 +193,73 @@ __device__ __forceinline__ void fun_grad(int kind, const double* p, double x, do
   }
 }
 
+// ------------------------------------------------------------------ decoupled look-back
+// Chained-scan tile protocol (Merrill & Garland 2016): st[tile] = flag << 32 | value with
+// flag 1 = tile total published, 2 = inclusive prefix published; st[ntiles] = tile counter.
+// All words start at zero.  A workgroup takes its tile index from the counter (so every
+// earlier tile is already running), and wave 0 calls lookback_wave with the tile total:
+// it publishes the total, sums the predecessors' published values 64 tiles at a time back
+// to the nearest inclusive prefix, publishes its own inclusive prefix and returns the
+// exclusive prefix (in every lane of wave 0).  Every wait ends: tile 0 publishes an
+// inclusive prefix at once and every tile does after a finite walk.
+constexpr uint64_t LB_AGG = 1ull << 32, LB_INC = 2ull << 32;
+
+__device__ __forceinline__ uint32_t lookback_tile(uint64_t* st, int64_t ntiles) {
+  return atomicAdd(reinterpret_cast<unsigned int*>(st + ntiles), 1u);
+}
+
+__device__ __forceinline__ uint32_t lookback_wave(uint64_t* st, int64_t b, uint32_t agg) {
+  const int lane = threadIdx.x & 63;
+  if (lane == 0)
+    __hip_atomic_store(st + b, (b == 0 ? LB_INC : LB_AGG) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t excl = 0;
+  int64_t j = b - 1 - lane;
+  while (b > 0) {
+    uint64_t sv;
+    for (;;) {
+      sv = j >= 0 ? __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_INC;
+      if (__ballot((sv >> 32) == 0) == 0) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    const uint64_t incm = __ballot((sv >> 32) == 2);
+    const int stop = incm ? __ffsll((unsigned long long)incm) - 1 : 63;  // nearest inclusive prefix
+    uint32_t x = lane <= stop ? (uint32_t)sv : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    excl += x;
+    if (incm) break;
+    j -= 64;
+  }
+  if (lane == 0 && b > 0)
+    __hip_atomic_store(st + b, LB_INC | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim.x = 64 * NW); returns the
+// thread's exclusive prefix, *agg = block total.  lw: NW words of LDS.  Contains barriers.
+template <int NW>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lw, uint32_t& agg) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) lw[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  agg = 0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const uint32_t t = lw[q];
+    pre += q < w ? t : 0u;
+    agg += t;
+  }
+  __syncthreads();
+  return pre + inc - v;
+}
+
 // ------------------------------------------------------------------ primitives (prims.hip)
 // Exclusive scan of n uint32 (in may alias out); *total (device) = sum, may be null.
 // Status: scan_status_words(n) uint64 words, taken from ws and zeroed by the scan, or

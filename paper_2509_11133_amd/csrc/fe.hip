@@ -14,6 +14,8 @@
 //       r_k  = d_k (sum B / (c vol) - (W B)[opp k] / 3),
 //       U    = 1 (sum B + sum mu) / (c vol) + W (B - Pi' mu / 3),   mu_k = d_k lambda_k.
 //   This split keeps the FP32 path accurate: A itself has cond ~ h^-2, N does not.
+#include <climits>
+
 #include "common.hpp"
 
 namespace ph {
@@ -363,29 +365,27 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __re
   for (int i = threadIdx.x; i < 4 * nb * W; i += FT) out[i] = lrec[i];
 }
 
-// The rows of one workgroup's faces form one contiguous range of the CSR arrays: they are
-// assembled in LDS and written out with coalesced stores.
+// Every face row has 6 off-diagonal slots (rowptr[F] = 6 F): an interior face fills them
+// with the 6 faces its two tets share it with, ascending; a boundary face (about 2 nF^(2/3)
+// of nF) has 3, ascending, followed by 3 explicit zeros in column F.  A workgroup's rows
+// are one contiguous range: assembled in LDS, written out with coalesced stores.
 template <class R>
 __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const double* __restrict__ X,
                                                   const int32_t* __restrict__ faces,
                                                   const int32_t* __restrict__ face2tet, DevParams P,
-                                                  const SlotRec<R>* __restrict__ recs,
-                                                  const int32_t* __restrict__ rowptr, int32_t* __restrict__ col,
-                                                  double* __restrict__ val, double* __restrict__ diag,
-                                                  double* __restrict__ rhs) {
+                                                  const SlotRec<R>* __restrict__ recs, int32_t* __restrict__ rowptr,
+                                                  int32_t* __restrict__ col, double* __restrict__ val,
+                                                  double* __restrict__ diag, double* __restrict__ rhs) {
   __shared__ int32_t lcol[6 * FT];
   __shared__ double lval[6 * FT];
   const int64_t f0 = (int64_t)blockIdx.x * FT;
   const int64_t f = f0 + threadIdx.x;
-  const int64_t fend = f0 + FT < nF ? f0 + FT : nF;
-  const int blo = rowptr[f0];
-  const int bhi = rowptr[fend];
+  const int nb = nF - f0 < FT ? (int)(nF - f0) : FT;
   if (f < nF) {
     const int q0 = face2tet[f], q1 = face2tet[nF + f];
     const bool interior = q1 >= 0;
     int cf[6];
     double cv[6];
-    int n = 0;
     double dg = 0.0, rh = 0.0;
     if (!interior && P.uk != PHFEM_FUN_ZERO) {  // b_D = |F| u_D(centroid) on a boundary face
       double xx[3][3];
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
                                  (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
     }
     {
-      const SlotRec<R> a = recs[q0];
+      const SlotRec<R> a = recs[q0];  // owner's slot: row k of its element block
       dg = (double)a.d;
       rh -= (double)a.r;
 #pragma unroll
@@ -411,43 +411,41 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
         cf[i] = a.c[i];
         cv[i] = (double)a.o[i];
       }
-      n = 3;
     }
     if (interior) {
-      const SlotRec<R> b = recs[q1];
-      dg += (double)b.d;
-      rh -= (double)b.r;
+      const SlotRec<R> bq = recs[q1];  // neighbour's slot
+      dg += (double)bq.d;
+      rh -= (double)bq.r;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        cf[3 + i] = b.c[i];
-        cv[3 + i] = (double)b.o[i];
+        cf[3 + i] = bq.c[i];
+        cv[3 + i] = (double)bq.o[i];
       }
-      n = 6;
     } else {
 #pragma unroll
       for (int i = 3; i < 6; ++i) {
-        cf[i] = 0;
+        cf[i] = INT_MAX;  // sorts last; written as column F with value 0
         cv[i] = 0.0;
       }
     }
-    const int base = rowptr[f] - blo;
+    const int base = 6 * (int)(f - f0);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      if (i < n) {
-        int rank = 0;
+      int rank = 0;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) rank += (j < n && cf[j] < cf[i]) ? 1 : 0;
-        lcol[base + rank] = cf[i];
-        lval[base + rank] = cv[i];
-      }
+      for (int j = 0; j < 6; ++j) rank += (cf[j] < cf[i] || (cf[j] == cf[i] && j < i)) ? 1 : 0;
+      lcol[base + rank] = cf[i] == INT_MAX ? (int32_t)f : cf[i];
+      lval[base + rank] = cv[i];
     }
     diag[f] = dg;
     rhs[f] = rh;
+    rowptr[f] = (int32_t)(6 * f);
+    if (f == nF - 1) rowptr[nF] = (int32_t)(6 * nF);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < bhi - blo; i += FT) {
-    col[blo + i] = lcol[i];
-    val[blo + i] = lval[i];
+  for (int i = threadIdx.x; i < 6 * nb; i += FT) {
+    col[6 * f0 + i] = lcol[i];
+    val[6 * f0 + i] = lval[i];
   }
 }
 
@@ -697,8 +695,7 @@ extern "C" size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, i
     a.take<SlotRec<float>>(4 * nE);
   else
     a.take<SlotRec<double>>(4 * nE);
-  a.take<int>(16);
-  return a.size() + scan_workspace(nF + 1);
+  return a.size();
 }
 
 extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
@@ -721,30 +718,24 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
   const bool mixed = p->precision == PHFEM_MIXED;
   double4* XA = a.take<double4>(nC);
   void* recs = mixed ? (void*)a.take<SlotRec<float>>(4 * nE) : (void*)a.take<SlotRec<double>>(4 * nE);
-  a.take<int>(16);
   DevParams P = to_dev(*p);
-  rc = launch_face_init(nF, nC, coord, faces, face2tet, P, (uint32_t*)rowptr, nullptr, nullptr, s);
-  if (rc) return rc;
-  rc = scan_exclusive((const uint32_t*)rowptr, (uint32_t*)rowptr, nF + 1, nullptr, a, s);
-  if (rc) return rc;
   // algorithmic bytes: tets, faces, sigma (+ kappa) once per tet, coordinates once per node,
-  // four records per tet written once and read once, face2tet's neighbour half and the row
-  // pointers once, every
-  // off-diagonal (col + val) and diagonal/rhs entry written once
+  // four records per tet written once and read once, face2tet once, every off-diagonal slot
+  // (col + val), diagonal, rhs and row pointer written once
   const double rb = 4.0 * (double)(mixed ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>));
   const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
-  const double fb = rb * nE + 8.0 * nF + 12.0 * (6.0 * nF) + 16.0 * nF;
+  const double fb = rb * nE + 8.0 * nF + 12.0 * (6.0 * nF) + 20.0 * nF;
   PH_LAUNCH_B("coords_aos", 56.0 * nC, k_coords_aos, grid_for(nC, FT), FT, 0, s, nC, coord, XA);
   if (mixed) {
     PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
                 sigma, kappa, P, nF, (SlotRec<float>*)recs);
-    PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces, face2tet,
-                P, (const SlotRec<float>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
+    PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
+                face2tet, P, (const SlotRec<float>*)recs, rowptr, col, val, diag, rhs);
   } else {
     PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
                 sigma, kappa, P, nF, (SlotRec<double>*)recs);
     PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
-                face2tet, P, (const SlotRec<double>*)recs, (const int32_t*)rowptr, col, val, diag, rhs);
+                face2tet, P, (const SlotRec<double>*)recs, rowptr, col, val, diag, rhs);
   }
   return PHFEM_OK;
 }

@@ -79,7 +79,6 @@ void prof_end(hipStream_t s) {
 constexpr int SC_THREADS = 256;
 constexpr int SC_ITEMS = 16;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
-constexpr uint64_t SC_AGG = 1ull << 32, SC_INC = 2ull << 32;
 
 __device__ __forceinline__ int sc_pad(int k) { return k + (k >> 5); }  // one pad word per 32
 
@@ -97,7 +96,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_lookback(const uint32_t* in
   __shared__ uint32_t lw[SC_THREADS / 64];
   __shared__ uint32_t s_tile, s_excl;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) s_tile = atomicAdd(reinterpret_cast<unsigned int*>(st + ntiles), 1u);
+  if (tid == 0) s_tile = lookback_tile(st, ntiles);
   __syncthreads();
   const int64_t b = s_tile;
   const int64_t base = b * SC_TILE;
@@ -114,53 +113,17 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_lookback(const uint32_t* in
     v[i] = tile[sc_pad(tid * SC_ITEMS + i)];
     sum += PACKED ? (v[i] & 0xffu) : v[i];
   }
-  // block-wide inclusive scan of the per-thread sums
-  uint32_t inc = sum;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t u = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += u;
-  }
-  if (lane == 63) lw[w] = inc;
-  __syncthreads();
-  uint32_t agg = 0, wpre = 0;
-#pragma unroll
-  for (int q = 0; q < SC_THREADS / 64; ++q) {
-    const uint32_t t = lw[q];
-    wpre += q < w ? t : 0u;
-    agg += t;
-  }
-  // look-back by wave 0
+  uint32_t agg;
+  const uint32_t tpre = block_excl_scan<SC_THREADS / 64>(sum, lw, agg);
   if (w == 0) {
-    if (lane == 0)
-      __hip_atomic_store(st + b, (b == 0 ? SC_INC : SC_AGG) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
-    int64_t j = b - 1 - lane;
-    while (b > 0) {
-      uint64_t sv;
-      for (;;) {
-        sv = j >= 0 ? __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : SC_INC;
-        if (__ballot((sv >> 32) == 0) == 0) break;
-        __builtin_amdgcn_s_sleep(1);
-      }
-      const uint64_t incm = __ballot((sv >> 32) == 2);
-      // lanes up to and including the nearest inclusive prefix contribute
-      const int stop = incm ? __ffsll((unsigned long long)incm) - 1 : 63;
-      uint32_t x = lane <= stop ? (uint32_t)sv : 0u;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-      excl += x;
-      if (incm) break;
-      j -= 64;
-    }
+    const uint32_t excl = lookback_wave(st, b, agg);
     if (lane == 0) {
-      if (b > 0) __hip_atomic_store(st + b, SC_INC | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_excl = excl;
       if (total && b == ntiles - 1) *total = excl + agg;
     }
   }
   __syncthreads();
-  uint32_t run = s_excl + wpre + inc - sum;
+  uint32_t run = s_excl + tpre;
 #pragma unroll
   for (int i = 0; i < SC_ITEMS; ++i) {
     const uint32_t c = PACKED ? (v[i] & 0xffu) : v[i];

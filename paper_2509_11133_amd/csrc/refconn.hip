@@ -113,10 +113,13 @@ struct RCArgs {
   const int32_t* pre;
   const int32_t* minI;  // [2 nEd]: (t << 2 | j) of the lowest tet whose vertex I is that end
   const int32_t* efp;   // [nEd]: (6 t0 + j0) << 1 | (node at ev0(j0) is the larger end)
-  uint32_t* inE;        // pass 1: count | first-edge mask << 8 per refined row
-  uint32_t* inF;        // pass 1: count | owned-face mask << 8
-  const uint32_t* recE; // after the scans: prefix << 6 | first-edge mask
-  const uint32_t* recF; // prefix << 4 | owned-face mask
+  // per refined row, written by pass 1: (prefix within its workgroup's row range) << 6 |
+  // first-edge mask and << 4 | owned-face mask; the ranges' offsets are in tpre
+  uint32_t* recE;
+  uint32_t* recF;
+  uint32_t* tagg;  // [4][ntiles] per-workgroup totals: edges of the child-0 rows, of the other
+  uint32_t* tpre;  // rows, faces of the child-0 rows, of the other rows; tpre = their offsets
+  int64_t ntiles;  // (exclusive scans of [edges | edges], [faces | faces]), then the two totals
   int32_t* edges2;
   int32_t* t2e2;
   int32_t* eft2;
@@ -354,9 +357,11 @@ __device__ __forceinline__ bool rc_flush_slot(const RCArgs& A, const RCBlock& B,
   return false;
 }
 
-// pass 1: count | mask << 8 of first edges and owned faces for every refined row
+// pass 1: the first-edge and owned-face masks of every refined row with their prefix counts
+// inside the workgroup's two row ranges, and the ranges' totals
 __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
   __shared__ uint32_t sE[RCW * RCS], sF[RCW * RCS];
+  __shared__ uint32_t lw[RCB / 64];
   const RCBlock B = rc_block(A);
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -378,17 +383,44 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
         int fk;
         if (fown<C, K>(A, T, r, fr, fk)) mf |= 1 << K;
       });
-      sE[lane * RCS + C] = (uint32_t)__popc(me) | ((uint32_t)me << 8);
-      sF[lane * RCS + C] = (uint32_t)__popc(mf) | ((uint32_t)mf << 8);
+      sE[lane * RCS + C] = (uint32_t)me;
+      sF[lane * RCS + C] = (uint32_t)mf;
     });
   }
   __syncthreads();
+  // rows in flush order: threads 0 .. 11 RCW - 1 the other rows, the last RCW the child-0 rows
   int64_t row;
   int slot;
-  if (rc_flush_slot(A, B, threadIdx.x, row, slot)) {
-    A.inE[row] = sE[slot];
-    A.inF[row] = sF[slot];
+  const bool has = rc_flush_slot(A, B, threadIdx.x, row, slot);
+  const uint32_t me = has ? sE[slot] : 0u, mf = has ? sF[slot] : 0u;
+  const bool first = threadIdx.x >= 11 * RCW;
+  const uint32_t pk = (uint32_t)__popc(me) | ((uint32_t)__popc(mf) << 16);  // < 2^16 each per block
+  uint32_t agg1, agg2;
+  const uint32_t p2 = block_excl_scan<RCB / 64>(first ? 0u : pk, lw, agg2);
+  const uint32_t p1 = block_excl_scan<RCB / 64>(first ? pk : 0u, lw, agg1);
+  if (has) {
+    const uint32_t p = first ? p1 : p2;
+    A.recE[row] = ((p & 0xffffu) << 6) | me;
+    A.recF[row] = ((p >> 16) << 4) | mf;
   }
+  if (threadIdx.x == 0) {
+    const int64_t b = blockIdx.x, n = A.ntiles;
+    A.tagg[b] = agg1 & 0xffffu;
+    A.tagg[n + b] = agg2 & 0xffffu;
+    A.tagg[2 * n + b] = agg1 >> 16;
+    A.tagg[3 * n + b] = agg2 >> 16;
+  }
+}
+
+// absolute prefix of a row's record: its workgroup range's offset + the in-range prefix
+__device__ __forceinline__ int64_t row_tile(int64_t nE, int64_t row) {
+  return (row < nE ? row : (row - nE) / 11) / RCW;
+}
+__device__ __forceinline__ uint32_t pre_e(const RCArgs& A, int64_t row, uint32_t rec) {
+  return A.tpre[(row < A.nE ? 0 : 1) * A.ntiles + row_tile(A.nE, row)] + (rec >> 6);
+}
+__device__ __forceinline__ uint32_t pre_f(const RCArgs& A, int64_t row, uint32_t rec) {
+  return A.tpre[(row < A.nE ? 2 : 3) * A.ntiles + row_tile(A.nE, row)] + (rec >> 4);
 }
 
 // pass 2: ids of the refined edges and faces of every row, and all outputs.  Phase 1 stages
@@ -421,8 +453,9 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
     const int64_t lo = r2 ? nE + 11 * B.t0 : B.t0;
     const int64_t hi = r2 ? nE + 11 * (B.t0 + B.nb) : B.t0 + B.nb;  // row after the range
     const bool last = r2 && hi == A.nE2;
-    const int64_t e0 = A.recE[lo] >> 6, f0 = A.recF[lo] >> 4;
-    const int64_t e1 = last ? nEd2 : (int64_t)(A.recE[hi] >> 6), f1 = last ? nF2 : (int64_t)(A.recF[hi] >> 4);
+    const int64_t e0 = pre_e(A, lo, A.recE[lo]), f0 = pre_f(A, lo, A.recF[lo]);
+    const int64_t e1 = last ? nEd2 : (int64_t)pre_e(A, hi, A.recE[hi]);
+    const int64_t f1 = last ? nF2 : (int64_t)pre_f(A, hi, A.recF[hi]);
     RCRange R;
     R.e0 = e0;
     R.f0 = f0;
@@ -441,18 +474,19 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
       int32_t* w = sW + lane * RCS + C;
       const uint32_t oe = A.recE[r], of = A.recF[r];
       const int me = oe & 63, mf = of & 15;
-      w[0] = (int32_t)(oe >> 6);
+      const uint32_t pe = pre_e(A, r, oe), pf = pre_f(A, r, of);
+      w[0] = (int32_t)pe;
       sfor<6>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         int32_t id;
         if ((me >> J) & 1) {
-          id = (int32_t)((oe >> 6) + __popc(me & ((1 << J) - 1)));
+          id = (int32_t)(pe + __popc(me & ((1 << J) - 1)));
         } else {
           int64_t er;
           int ej;
           efirst<C, J>(A, T, er, ej);
           const uint32_t o = A.recE[er];
-          id = (int32_t)((o >> 6) + __popc((o & 63) & ((1u << ej) - 1)));
+          id = (int32_t)(pre_e(A, er, o) + __popc((o & 63) & ((1u << ej) - 1)));
         }
         w[(1 + J) * RCW * RCS] = id;
       });
@@ -465,11 +499,11 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
         const bool own = (mf >> K) & 1;
         int32_t id;
         if (own) {
-          id = (int32_t)((of >> 4) + __popc(mf & ((1 << K) - 1)));
+          id = (int32_t)(pf + __popc(mf & ((1 << K) - 1)));
           fnb[K] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
         } else if (fr >= 0) {
           const uint32_t o = A.recF[fr];
-          id = (int32_t)((o >> 4) + __popc((o & 15) & ((1u << fk) - 1)));
+          id = (int32_t)(pre_f(A, fr, o) + __popc((o & 15) & ((1u << fk) - 1)));
         } else {
           id = -1;  // inconsistent input only
         }
@@ -508,10 +542,11 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
       constexpr int of_ = C == 0 ? OF1 : OF2, cf = C == 0 ? CF1 : CF2;
       const uint32_t oe = A.recE[r], of = A.recF[r];
       const int me = oe & 63, mf = of & 15;
+      const uint32_t pe = pre_e(A, r, oe), pf = pre_f(A, r, of);
       sfor<6>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         if (!((me >> J) & 1)) return;
-        const int64_t id = (oe >> 6) + __popc(me & ((1 << J) - 1));
+        const int64_t id = pe + __popc(me & ((1 << J) - 1));
         const int na = sym_node<ch(C, ev0(J))>(A, T), nb = sym_node<ch(C, ev1(J))>(A, T);
         const int lo = na < nb ? na : nb, hi = na < nb ? nb : na;
         const int64_t li = id - R.e0;
@@ -528,7 +563,7 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
       sfor<4>([&](auto Kc) {
         constexpr int K = decltype(Kc)::value;
         if (!((mf >> K) & 1)) return;
-        const int64_t id = (of >> 4) + __popc(mf & ((1 << K) - 1));
+        const int64_t id = pf + __popc(mf & ((1 << K) - 1));
         const int n0 = sym_node<ch(C, fv(K, 0))>(A, T), n1 = sym_node<ch(C, fv(K, 1))>(A, T),
                   n2 = sym_node<ch(C, fv(K, 2))>(A, T);
         const int64_t li = id - R.f0;
@@ -586,23 +621,32 @@ __global__ __launch_bounds__(RCT) void k_rc_init(int64_t nEd, int32_t* __restric
   for (int64_t i = (int64_t)blockIdx.x * RCT + threadIdx.x; i < nz; i += stride) z[i] = 0;
 }
 
-// input ids out of range (flag) and refined totals against the recurrences; ORs a code
-// into *status (device)
-__global__ void k_rc_check(const uint32_t* __restrict__ tot, int64_t nEd2, int64_t nF2, int32_t* __restrict__ status) {
+// input ids out of range (flag) and refined totals against the recurrences: ORs a code into
+// *status (device), and writes out[3] = {edges, faces, flag} when out != null
+__global__ void k_rc_check(const uint32_t* __restrict__ tot, const uint32_t* __restrict__ flag, int64_t nEd2,
+                           int64_t nF2, int32_t* __restrict__ status, int64_t* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t ne = tot[0], nf = tot[1];
   int32_t code = 0;
-  if (tot[2]) code |= 1;
-  if ((int64_t)tot[0] != nEd2 || (int64_t)tot[1] != nF2) code |= 2;
-  if (code) atomicOr(status, code);
+  if (*flag) code |= 1;
+  if (ne != nEd2 || nf != nF2) code |= 2;
+  if (code && status) atomicOr(status, code);
+  if (out) {
+    out[0] = ne;
+    out[1] = nf;
+    out[2] = *flag;
+  }
 }
 
 struct RCWS {
   int32_t *minI, *efp;
   int4 *T4, *F4, *N4, *E8;
-  uint32_t *inE, *inF, *recF;
-  uint32_t* z;          // zeroed together: tot[4] (edge total, face total, input flag, pad), then
-  uint64_t *stE, *stF;  // the two scans' status words
-  int64_t nz;           // uint32 words from z
+  uint32_t *recE, *recF;
+  uint32_t* z;  // zeroed by the init kernel: 4 words (input flag z[2]), the scans' status
+  uint64_t *stE, *stF;
+  uint32_t *tagg, *tpre;
+  int64_t ntiles, nz;
+  int64_t* chk;  // {edges, faces, flag} read back by the synchronous check
   size_t sub;
 };
 
@@ -614,14 +658,17 @@ static void rc_layout(Arena& a, int64_t nE, int64_t nEd, RCWS& w) {
   w.F4 = a.take<int4>(nE);
   w.N4 = a.take<int4>(nE);
   w.E8 = a.take<int4>(2 * nE);
-  w.inE = a.take<uint32_t>(n2);
-  w.inF = a.take<uint32_t>(n2);
+  w.recE = a.take<uint32_t>(n2);
   w.recF = a.take<uint32_t>(n2);
-  const int64_t sw = scan_status_words(n2);
-  w.z = a.take<uint32_t>(4 + 4 * sw);  // contiguous: tot, stE, stF
+  w.ntiles = (nE + RCW - 1) / RCW;
+  const int64_t sw = scan_status_words(2 * w.ntiles);
+  w.z = a.take<uint32_t>(4 + 4 * sw);
   w.stE = reinterpret_cast<uint64_t*>(w.z + 4);
   w.stF = w.stE + sw;
   w.nz = 4 + 4 * sw;
+  w.tagg = a.take<uint32_t>(4 * w.ntiles);
+  w.tpre = a.take<uint32_t>(4 * w.ntiles + 2);
+  w.chk = a.take<int64_t>(4);
   w.sub = a.size();
 }
 
@@ -638,7 +685,7 @@ extern "C" size_t phfem_refine_connected_workspace(int64_t nE, int64_t nEd) {
   Arena a;
   RCWS w;
   rc_layout(a, nE, nEd, w);
-  return w.sub + scan_workspace(12 * nE);
+  return w.sub;
 }
 
 extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
@@ -654,8 +701,10 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   if (nC <= 0 || nE <= 0 || nEd <= 0 || nF <= 0) return err(PHFEM_EINVAL, "bad sizes");
   const int64_t nE2 = 12 * nE, nC2 = nC + nEd + nE;
   const int64_t nEd2 = 2 * nEd + 3 * nF + 6 * nE, nF2 = 4 * nF + 16 * nE;
-  if (2 * nEd2 >= (int64_t(1) << 31) || 6 * nE2 >= (int64_t(1) << 31) || nC2 >= (int64_t(1) << 31) || 4 * nF2 >= (int64_t(1) << 31))
-    return err(PHFEM_EINVAL, "refined mesh exceeds int32 positions");
+  // int32 positions; the per-row records pack the edge prefix in 26 bits, the face prefix in 28
+  if (nEd2 >= (int64_t(1) << 26) || nF2 >= (int64_t(1) << 28) || 6 * nE2 >= (int64_t(1) << 31) ||
+      nC2 >= (int64_t(1) << 31))
+    return err(PHFEM_EINVAL, "refined mesh exceeds the index ranges (nEd' < 2^26, nF' < 2^28, 6 nE' < 2^31)");
   if (!coord || !tetra || !tet2edge || !edge_first_tet || !tet_edge_prefix || !tet2face || !nbr || !coord_out ||
       !tetra_out || !edges_out || !tet2edge_out || !edge_first_tet_out || !tet_edge_prefix_out || !faces_out ||
       !tet2face_out || !sigma_out || !face2tet_out || !nbr_out || !counts)
@@ -688,10 +737,11 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   A.pre = tet_edge_prefix;
   A.minI = w.minI;
   A.efp = w.efp;
-  A.inE = w.inE;
-  A.inF = w.inF;
-  A.recE = w.inE;  // the edge scan writes its records in place
+  A.recE = w.recE;
   A.recF = w.recF;
+  A.tagg = w.tagg;
+  A.tpre = w.tpre;
+  A.ntiles = w.ntiles;
   A.edges2 = edges_out;
   A.t2e2 = tet2edge_out;
   A.eft2 = edge_first_tet_out;
@@ -702,26 +752,26 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   A.f2t2 = face2tet_out;
   A.nbr2 = nbr_out;
   // pass 1 reads the coarse AoS data once (cache-shared by the 12 rows of a tet) and writes
-  // two words per refined row
-  PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, grid_for(nE, RCW), RCB, 0, s, A);
-  a.off = w.sub;
-  rc = scan_packed(w.inE, w.inE, nE2, 6, w.z, a, s, w.stE);
+  // one record word per refined row and count
+  PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, (unsigned)w.ntiles, RCB, 0, s, A);
+  // offsets of the workgroups' row ranges: other rows after all child-0 rows
+  rc = scan_exclusive(w.tagg, w.tpre, 2 * w.ntiles, w.tpre + 4 * w.ntiles, a, s, w.stE);
   if (rc) return rc;
-  a.off = w.sub;
-  rc = scan_packed(w.inF, w.recF, nE2, 4, w.z + 1, a, s, w.stF);
+  rc = scan_exclusive(w.tagg + 2 * w.ntiles, w.tpre + 2 * w.ntiles, 2 * w.ntiles, w.tpre + 4 * w.ntiles + 1, a, s,
+                      w.stF);
   if (rc) return rc;
   // pass 2 writes every refined connectivity array once
   PH_LAUNCH_B("refconn_pass2", 80.0 * nE + 12.0 * nEd + 8.0 * nE2 + (24.0 + 4 + 16 + 1 * 4 + 16) * nE2 + 12.0 * nEd2 +
                                    20.0 * nF2,
-              k_rc_pass2, grid_for(nE, RCW), RCB, 0, s, A);
-  if (status) {  // checked on the device: no synchronization
-    PH_LAUNCH("rc_check", k_rc_check, 1, 64, 0, s, w.z, nEd2, nF2, status);
-  } else {
-    uint32_t tot[3] = {0, 0, 0};
-    PH_HIP(hipMemcpyAsync(tot, w.z, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+              k_rc_pass2, (unsigned)w.ntiles, RCB, 0, s, A);
+  PH_LAUNCH("rc_check", k_rc_check, 1, 64, 0, s, w.tpre + 4 * w.ntiles, w.z + 2, nEd2, nF2, status,
+            status ? nullptr : w.chk);
+  if (!status) {  // synchronous check
+    int64_t chk[3] = {0, 0, 0};
+    PH_HIP(hipMemcpyAsync(chk, w.chk, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PH_HIP(hipStreamSynchronize(s));
-    if (tot[2]) return err(PHFEM_EINVAL, "an input id lies outside the mesh (vertex, edge or refined node)");
-    if ((int64_t)tot[0] != nEd2 || (int64_t)tot[1] != nF2)
+    if (chk[2]) return err(PHFEM_EINVAL, "an input id lies outside the mesh (vertex, edge or refined node)");
+    if (chk[0] != nEd2 || chk[1] != nF2)
       return err(PHFEM_EINVAL, "input connectivity is not the first-appearance numbering of a conforming, "
                                "consistently oriented mesh (refined counts differ from 2nEd+3nF+6nE, 4nF+16nE)");
   }

@@ -154,7 +154,7 @@ def condense(coord, tetra, conn, kappa, prm):
     dev = coord.device
     nC, nE, nF, nB = coord.shape[1], tetra.shape[1], conn["nF"], conn["nB"]
     work = B.workspace(B.lib().phfem_condense_workspace(nC, nE, nF, prm.precision), dev)
-    nnz = 6 * nF - 3 * nB
+    nnz = 6 * nF  # fixed 6 slots per row (boundary rows padded with explicit zeros)
     rowptr = torch.empty(nF + 1, dtype=I32, device=dev)
     col = torch.empty(max(nnz, 1), dtype=I32, device=dev)
     val = torch.empty(max(nnz, 1), dtype=F64, device=dev)

@@ -218,12 +218,22 @@ def test_condense_parity(make, L, kind, precision, tol):
     kap = None if pb["kappa"] is None else dev(pb["kappa"])
     sysm = P.condense(dev(X), dev(T), gc, kap, gp)
     G = full_csr(sysm, oc["nF"])
-    # pattern: columns ascending, diagonal separate, nnz = 6 nI + 3 nB off-diagonals
-    assert sysm["nnz"] == A.nnz - oc["nF"]
+    # pattern: 6 slots per row; the oracle's off-diagonals ascending, then (boundary rows) 3
+    # explicit zeros in the row's own column
+    nF = oc["nF"]
+    assert sysm["nnz"] == 6 * nF and np.array_equal(host(sysm["rowptr"]), 6 * np.arange(nF + 1))
     Ad = (A - sp.diags(A.diagonal())).tocsr()
     Ad.eliminate_zeros()
     Ad.sort_indices()
-    assert np.array_equal(host(sysm["rowptr"]), Ad.indptr) and np.array_equal(host(sysm["col"]), Ad.indices)
+    gcol, gval = host(sysm["col"]).reshape(nF, 6), host(sysm["val"]).reshape(nF, 6)
+    cnt = np.diff(Ad.indptr)
+    assert set(np.unique(cnt)) <= {3, 6} and (cnt == 3).sum() == oc["nB"]
+    want = np.repeat(np.arange(nF)[:, None], 6, axis=1)
+    for k in range(6):
+        m = cnt > k
+        want[m, k] = Ad.indices[Ad.indptr[:-1][m] + k]
+    assert np.array_equal(gcol, want)
+    assert np.all(gval[cnt == 3, 3:] == 0.0)
     D = abs(G - A).tocsr()
     rowmax = np.asarray(abs(A).max(axis=1).todense()).ravel()
     assert (np.asarray(D.max(axis=1).todense()).ravel() / rowmax).max() <= tol
