@@ -102,13 +102,29 @@ def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort
     return ms, wall / steps * 1e3, kern, out
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    committed rocprofv3 summary, or None when the kernel's source changed since then."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        t = json.load(open(os.path.join(here, "profiles", "traffic_kuhn_L6.json")))
+        k = t["kernels"][kernel]
+        src = os.path.join(here, "paper_2509_11133_amd", "csrc", k["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["source_sha256"][k["source"]]:
+            return None
+        return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(kern, steps):
     name, k = max(kern.items(), key=lambda kv: kv[1]["ms"])
     if k["bytes"] <= 0:  # fall back to the heaviest kernel with a byte count
         name, k = max(((n, v) for n, v in kern.items() if v["bytes"] > 0), key=lambda kv: kv[1]["ms"])
     gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
     return name, dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=name,
+                      frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(name), kernel=name,
                       launches_per_step=k["launches"] // max(steps, 1),
                       avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 5),
                       algorithmic_bytes_per_step=k["bytes"] / max(steps, 1))
@@ -179,7 +195,19 @@ def main():
     ap.add_argument("--cpu-levels", type=int, default=5)
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (per-kernel HIP events)")
     ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device-to-device 3 times (the reference kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 3}))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build measures one GPU only: the hot path runs on a single MI355X; "
