@@ -118,6 +118,22 @@ def measured_traffic(kernel):
         return None
 
 
+def pipeline_traffic(kern, steps):
+    """Measured HBM bytes per step of the whole pipeline: each kernel's launches per step x
+    its measured bytes per launch.  None unless every kernel with >= 1 % of the step time has a
+    current measurement (the small rest is left out, so the figure is a lower bound)."""
+    total_ms = sum(v["ms"] for v in kern.values())
+    tot = 0.0
+    for name, v in kern.items():
+        b = measured_traffic(name)
+        if b is None:
+            if v["ms"] >= 0.01 * total_ms:
+                return None
+            continue
+        tot += b * v["launches"] / max(steps, 1)
+    return tot
+
+
 def roofline(kern, steps):
     name, k = max(kern.items(), key=lambda kv: kv[1]["ms"])
     if k["bytes"] <= 0:  # fall back to the heaviest kernel with a byte count
@@ -278,6 +294,9 @@ def main():
     if mixed["kern"]:
         name, rl = roofline(mixed["kern"], args.steps)
         line["roofline"] = rl
+        pt = pipeline_traffic(mixed["kern"], args.steps)
+        line["achieved_hbm_frac"] = None if pt is None else round(pt / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+        line["measured_bytes_per_step"] = None if pt is None else round(pt)
         line["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
                                        for k, v in sorted(mixed["kern"].items(), key=lambda kv: -kv[1]["ms"])}
         line["fp64"]["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
