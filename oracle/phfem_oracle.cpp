@@ -8,7 +8,8 @@
 // library; the two only agree on data layout (0-based int32 indices, SoA arrays: the k-th
 // column of an n x m MATLAB array is the k-th contiguous block of length n).
 //
-// Arithmetic: FP64 throughout, long double for the 4x4 inverses and the brute-force dense
+// Arithmetic: FP64 throughout, long double for the 4x4 inverses (A(T)^-1 through the exact
+// split of its constant mode, see element_inverse) and the brute-force dense
 // solve.  Every function names the passage of the paper it follows.
 //
 // Readings of the paper taken here (the paper is silent, ambiguous or garbled there):
@@ -407,6 +408,29 @@ int load_tet(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int64_
   return ORC_OK;
 }
 
+// A(T)^-1 by the exact split of the constant mode.  Section 4.2's K(T) has zero row sums and
+// M(T) = (c|T|/20)(1 + delta_ij), so A(T) 1 = (c|T|/4) 1: with the projector P1 = 1 1'/4,
+// A = A_perp + (c|T|/4) P1, where A_perp = kappa K + (c|T|/20)(I - P1) annihilates 1 and acts
+// on its complement.  Hence A^-1 = A_perp^+ + 1 1'/(c|T|), and A_perp^+ = (A_perp + a P1)^-1
+// - P1/a for any a > 0; a = trace(A_perp)/3 makes that matrix as well conditioned as A_perp
+// on the complement.  Inverting A itself loses digits as |K|/(c|T|) ~ h^-2 grows (about 1e-12
+// relative after six 12-subtet refinements of the unit cube, even in long double).
+long double element_inverse(const long double K[4][4], long double kappa, long double c, long double vol,
+                            long double Ainv[4][4]) {
+  const long double m = c * vol / 20.0L;
+  long double As[4][4], Asi[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) As[i][j] = kappa * K[i][j] + m * ((i == j ? 1.0L : 0.0L) - 0.25L);
+  const long double a = (As[0][0] + As[1][1] + As[2][2] + As[3][3]) / 3.0L;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) As[i][j] += 0.25L * a;
+  const long double det = invert4(As, Asi);
+  if (det == 0) return 0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Ainv[i][j] = Asi[i][j] - 0.25L / a + 1.0L / (c * vol);
+  return det;
+}
+
 // Element Schur complement (Algorithm 1, eq. schur): S(T) = C A^-1 C', r(T) = C A^-1 B.
 struct Elem {
   long double A[4][4], Ainv[4][4], K[4][4], C[4][4], B[4];
@@ -425,7 +449,8 @@ int element(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const i
   long double kap = kappa ? kappa[t] : P.kappa_const;
   local_AC(L, kap, P, sig, E.A, E.K, E.C);
   local_load(L, P, E.B);
-  if (val(invert4(E.A, E.Ainv)) == 0) return fail(ORC_ESINGULAR, "singular element matrix");
+  if (element_inverse(E.K, kap, (long double)P.c, L.vol, E.Ainv) == 0)
+    return fail(ORC_ESINGULAR, "singular element matrix");
   long double AiCt[4][4], AiB[4];
   for (int i = 0; i < 4; ++i) {
     for (int l = 0; l < 4; ++l) {

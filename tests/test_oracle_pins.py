@@ -314,6 +314,53 @@ def test_element_schur_split_identity():
         assert np.linalg.eigvalsh(So).min() > 0
 
 
+def test_element_blocks_fine_tet_exact():
+    """Element blocks of tets as small as six refinement levels give (|K| / (c|T|) ~ 1e7) against
+    50-digit arithmetic of the definitions (A(T) = kappa K(T) + c M(T), C(T), S = C A^-1 C',
+    r = C A^-1 B): the oracle must stay at FP64 accuracy there (a direct inverse of A loses
+    about 1e-12)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    X0, T0 = M.kuhn_cube()
+    rng = np.random.default_rng(4)
+    local = [(0, 1, 2), (0, 2, 3), (0, 3, 1), (3, 2, 1)]
+    for t0 in range(6):
+        # a Kuhn tet shrunk by 2^-6 (exact) and moved into the cube, vertices in tet order
+        base = np.round(rng.random(3) * 64) / 64 * 0.9
+        Xs = (X0[:, T0[:, t0]] / 64 + base[:, None]).copy()
+        Ts = np.arange(4, dtype=np.int32).reshape(4, 1)
+        kap, cc = 0.3 + rng.random(), 0.5 + rng.random()
+        p = O.params(c=cc, kappa=kap, f=(O.FUN_SIN3, (2.0,)))
+        L = O.local(Xs, Ts, None, None, p)
+        x = [[mp.mpf(float(Xs[e, i])) for e in range(3)] for i in range(4)]
+        P4 = mp.matrix([[1] * 4] + [[x[i][e] for i in range(4)] for e in range(3)])
+        vol = abs(mp.det(P4)) / 6
+        Pi = P4 ** -1
+        A, C, B = mp.matrix(4, 4), mp.matrix(4, 4), mp.matrix(4, 1)
+        for i in range(4):
+            for j in range(4):
+                A[i, j] = mp.mpf(kap) * vol * sum(Pi[i, 1 + e] * Pi[j, 1 + e] for e in range(3)) + \
+                    mp.mpf(cc) * vol / 20 * (2 if i == j else 1)
+        fc = []
+        for k, (a, b, c3) in enumerate(local):
+            u = [x[c3][e] - x[a][e] for e in range(3)]
+            w = [x[b][e] - x[a][e] for e in range(3)]
+            n = [u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]]
+            area = mp.sqrt(sum(v * v for v in n)) / 2
+            for v in (a, b, c3):
+                C[k, v] = area / 3
+            ct = [(x[a][e] + x[b][e] + x[c3][e]) / 3 for e in range(3)]
+            fc.append(2 * mp.sin(mp.pi * ct[0]) * mp.sin(mp.pi * ct[1]) * mp.sin(mp.pi * ct[2]))
+        for i in range(4):  # face-centroid rule: vertex i lies on the faces other than opp(i)
+            B[i, 0] = vol / 12 * sum(fc[k] for k in range(4) if i in local[k])
+        Ai = A ** -1
+        S, r = C * Ai * C.T, C * Ai * B
+        Se = np.array([[float(S[k, l]) for l in range(4)] for k in range(4)])
+        re = np.array([float(r[k, 0]) for k in range(4)])
+        assert np.abs(L["S"][:, 0].reshape(4, 4) - Se).max() <= 1e-15 * np.abs(Se).max()
+        assert np.abs(L["r"][:, 0] - re).max() <= 1e-14 * np.abs(re).max()
+
+
 def test_assembly_structure():
     """nnz = 7 nI + 4 nB; symmetric (to rounding); each off-diagonal equals the single S(T) entry of the
     one tet holding both faces (bit for bit)."""
