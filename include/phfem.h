@@ -250,9 +250,14 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
 /* Solve S+ lambda = r+ (Jacobi-PCG; the paper solves it with a sparse direct solver,
  * Listing 8) and recover U(T) = A(T)^-1 (B(T) + C(T)' lambda(T)) (Algorithm 1, last loop).
  *  mode FP64_PCG: PCG on the FP64 system to ||r|| <= tol ||r+||.
- *  mode FP32_PCG_FP64_IR: iterative refinement; residual b_D - C U(lambda) recomputed per
- *    tet in FP64 from the geometry (not from the stored system), corrections by FP32 PCG
- *    on an FP32 copy of the system to relative tolerance inner_tol.
+ *  mode FP32_PCG_FP64_IR: iterative refinement without restarts: one FP32 PCG recurrence on
+ *    an FP32 copy of the system, whose residual is replaced by the true residual
+ *    b_D - C U(lambda), recomputed per tet in FP64 from the geometry (not from the stored
+ *    system), each time the FP32 residual has fallen by the factor inner_tol (in (0, 1);
+ *    anything else means 0.7, measured best: rarer replacements let the FP32 recurrence
+ *    drift from the true residual) since the last replacement; the FP32 iterate is then added to
+ *    the FP64 solution and the search direction kept.  Stops when the true residual meets
+ *    tol.  stats.ir_steps counts the replacements.
  * Outputs: lambda[nF], U[4][nE] (float64).  Synchronizes (residual checks every few
  * iterations).  Errors: EINVAL, EDEGEN, ENOCONV (max_iter reached; outputs and stats hold
  * the last iterate), EWORKSPACE. */

@@ -170,6 +170,43 @@ __global__ __launch_bounds__(ST) void k_add_f32(int64_t n, const float* __restri
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) x[i] += (double)d[i];
 }
 
+// residual replacement of the FP32 recurrence: r32 = (float) r64, z = r32 / diag; with
+// init also p = z, x32 = 0.  Partial r.z and r.r as k_pcg_update leaves them.
+template <bool INIT>
+__global__ __launch_bounds__(ST) void k_replace(int64_t n, const double* __restrict__ r64,
+                                                const float* __restrict__ diag, float* __restrict__ r,
+                                                float* __restrict__ z, float* __restrict__ p, float* __restrict__ x32,
+                                                double* __restrict__ part_rz, double* __restrict__ part_rr) {
+  __shared__ double lds[ST / 64];
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    const float ri = (float)r64[i];
+    const float zi = ri / diag[i];
+    r[i] = ri;
+    z[i] = zi;
+    if (INIT) {
+      p[i] = zi;
+      x32[i] = 0.0f;
+    }
+    arz += (double)ri * (double)zi;
+    arr += (double)ri * (double)ri;
+  }
+  double s1 = block_sum(arz, lds);
+  double s2 = block_sum(arr, lds);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = s1;
+    part_rr[blockIdx.x] = s2;
+  }
+}
+
+// x += x32, x32 = 0
+__global__ __launch_bounds__(ST) void k_flush_x(int64_t n, float* __restrict__ x32, double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    x[i] += (double)x32[i];
+    x32[i] = 0.0f;
+  }
+}
+
 __global__ __launch_bounds__(ST) void k_fill0(int64_t n, double* __restrict__ x) {
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) x[i] = 0.0;
 }
@@ -343,41 +380,81 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
     PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nnz), ST, 0, s, (int64_t)nnz, val, w.val32);
     PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, diag, w.diag32);
   }
-  PH_LAUNCH("fill0", k_fill0, pcg_grid(nF), ST, 0, s, nF, x);
+  // Iterative refinement without restarts: one FP32 PCG recurrence on the FP32 system whose
+  // residual is replaced by the true FP64 residual b_D - C U(x) (matrix-free, per tet, from
+  // the geometry) whenever the recurrence residual has dropped by REPLACE since the last
+  // replacement; the accumulated FP32 iterate is then folded into the FP64 solution.  The
+  // search direction is kept, so the Krylov space is not rebuilt as restarted refinement
+  // would; convergence is declared on the true FP64 residual only.
+  const double REPLACE = inner_tol;
+  const unsigned G = pcg_grid(nF);
+  PcgWS& pw = w.pcg;
+  float *r32 = (float*)pw.r, *z = (float*)pw.z, *p = (float*)pw.p, *q = (float*)pw.q;
+  PH_LAUNCH("fill0", k_fill0, G, ST, 0, s, nF, x);
+  rc = residual(m, x, U, w.r64, w.flags, s);
+  if (rc) return rc;
+  rc = check_flags(w.flags, s);
+  if (rc) return rc;
   double r0 = 0;
-  int total_it = 0, steps = 0;
-  for (;;) {
-    rc = residual(m, x, U, w.r64, w.flags, s);
-    if (rc) return rc;
-    double rn = 0;
-    rc = norm2(nF, w.r64, w.pcg, &rn, s);
-    if (rc) return rc;
-    if (steps == 0) {
-      rc = check_flags(w.flags, s);
-      if (rc) return rc;
-      r0 = rn;
-    }
-    loc.rel_res = r0 > 0 ? rn / r0 : 0.0;
-    loc.rhs_norm = r0;
-    if (!(loc.rel_res > tol) || r0 == 0) break;
-    if (total_it >= maxit || steps >= 60) {
-      loc.iters = total_it;
-      loc.ir_steps = steps;
-      *st = loc;
-      return err(PHFEM_ENOCONV, "iterative refinement stopped above tolerance");
-    }
-    PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, (const double*)w.r64, w.b32);
-    int it = 0;
-    double rel = 0;
-    rc = pcg<float>(nF, rowptr, col, w.val32, w.diag32, w.b32, w.x32, inner_tol, maxit - total_it, w.pcg, &it, &rel,
-                    s);
-    if (rc) return rc;
-    total_it += it;
-    PH_LAUNCH("add_f32", k_add_f32, pcg_grid(nF), ST, 0, s, nF, (const float*)w.x32, x);
-    ++steps;
+  rc = norm2(nF, w.r64, pw, &r0, s);
+  if (rc) return rc;
+  loc.rhs_norm = r0;
+  if (r0 == 0) {
+    *st = loc;
+    return PHFEM_OK;
   }
-  loc.iters = total_it;
+  PH_LAUNCH("replace", k_replace<true>, G, ST, 0, s, nF, (const double*)w.r64, (const float*)w.diag32, r32, z, p,
+            w.x32, pw.part_rz, pw.part_rr);
+  PH_LAUNCH("pcg_scalars", k_scalars, 1, ST, 0, s, (int)G, (const double*)pw.part_rz, (const double*)pw.part_rr,
+            pw.scal, 0);
+  double ref = r0, rel = 1.0;
+  int slot = 0, it = 0, steps = 0;
+  bool replace = false, done = false;
+  while (!done) {
+    if (it >= maxit) {
+      loc.iters = it;
+      loc.ir_steps = steps;
+      loc.rel_res = rel;
+      *st = loc;
+      return err(PHFEM_ENOCONV, "mixed refinement reached max_iter above tolerance");
+    }
+    PH_LAUNCH_B("spmv_dot", (double)nF * (4 + 3 * 4) + 6.0 * nF * (4 + 4), k_spmv_dot<float>, G, ST, 0, s, nF, rowptr,
+                col, (const float*)w.val32, (const float*)w.diag32, (const float*)p, q, pw.part_pq);
+    PH_LAUNCH_B("pcg_update", 8.0 * 4 * nF, k_pcg_update<float>, G, ST, 0, s, nF, (int)G, (const double*)pw.part_pq,
+                (const double*)pw.scal, slot, w.x32, r32, (const float*)p, (const float*)q, (const float*)w.diag32, z,
+                pw.part_rz, pw.part_rr);
+    if (replace) {
+      PH_LAUNCH("flush_x", k_flush_x, G, ST, 0, s, nF, w.x32, x);
+      rc = residual(m, x, U, w.r64, w.flags, s);
+      if (rc) return rc;
+      double rn = 0;
+      rc = norm2(nF, w.r64, pw, &rn, s);
+      if (rc) return rc;
+      ++steps;
+      rel = rn / r0;
+      if (!(rel > tol)) {
+        done = true;  // x and U are the converged FP64 solution
+      } else {
+        PH_LAUNCH("replace", k_replace<false>, G, ST, 0, s, nF, (const double*)w.r64, (const float*)w.diag32, r32,
+                  z, p, w.x32, pw.part_rz, pw.part_rr);
+        ref = rn;
+      }
+      replace = false;
+    }
+    PH_LAUNCH_B("pcg_dir", 3.0 * 4 * nF, k_pcg_dir<float>, G, ST, 0, s, nF, (int)G, (const double*)pw.part_rz,
+                (const double*)pw.part_rr, pw.scal, slot, (const float*)z, p);
+    slot ^= 1;
+    ++it;
+    if (!done && it % CHECK == 0) {
+      double rr = 0;
+      rc = read_scalar(pw.scal + 2, &rr, s);
+      if (rc) return rc;
+      if (!(std::sqrt(rr) > REPLACE * ref) || !(rr == rr)) replace = true;
+    }
+  }
+  loc.iters = it;
   loc.ir_steps = steps;
+  loc.rel_res = rel;
   *st = loc;
   return PHFEM_OK;
 }
@@ -427,7 +504,7 @@ extern "C" int phfem_solve(int64_t nC, const double* coord, int64_t nE, const in
   MeshOp m{nC, nE, nF, coord, tetra, tet2face, sigma, kappa, to_dev(*p), nullptr, w.bD};
   rc = launch_face_init(nF, nC, coord, faces, face2tet, m.P, nullptr, nullptr, w.bD, s);
   if (rc) return rc;
-  if (!(inner_tol > 0)) inner_tol = 1e-4;
+  if (!(inner_tol > 0 && inner_tol < 1)) inner_tol = 0.7;
   return face_solve(m, rowptr, col, val, diag, rhs, mode, tol, inner_tol, max_iter, w, lambda, U, stats, s);
 }
 
@@ -468,7 +545,7 @@ extern "C" int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int
   rc = launch_recover(nC, coord, nE, tetra, tet2face, sigma, kappa, P, nullptr, dJdU, Pv, radj, w.flags, s);
   if (rc) return rc;
   MeshOp m{nC, nE, nF, coord, tetra, tet2face, sigma, kappa, P, dJdU, nullptr};
-  if (!(inner_tol > 0)) inner_tol = 1e-4;
+  if (!(inner_tol > 0 && inner_tol < 1)) inner_tol = 0.7;
   rc = face_solve(m, rowptr, col, val, diag, radj, mode, tol, inner_tol, max_iter, w, Q, Pv, stats, s);
   if (rc) return rc;  // Pv = A^-1 (dJdU + C'Q) on exit
   if (dJ_dcoord) PH_HIP(hipMemsetAsync(dJ_dcoord, 0, sizeof(double) * 3 * nC, s));

@@ -165,7 +165,7 @@ def condense(coord, tetra, conn, kappa, prm):
     return dict(rowptr=rowptr, col=col[:nnz], val=val[:nnz], diag=diag, rhs=rhs, nnz=nnz)
 
 
-def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=1e-4, max_iter=200000,
+def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.7, max_iter=200000,
           allow_noconv=False):
     """Face solve + recovery (a8-a9).  Returns (lambda, U, stats)."""
     dev = coord.device
@@ -184,7 +184,7 @@ def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, 
     return lam, U, stats
 
 
-def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=1e-4,
+def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.7,
          max_iter=200000, want_coord=True):
     """Adjoint gradient (a10): (dJ/dlog kappa [nE], dJ/dX [3, nC], stats)."""
     dev = coord.device

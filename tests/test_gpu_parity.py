@@ -263,7 +263,7 @@ def test_solve_parity(make, L, kind, mode, precision):
     kap = None if pb["kappa"] is None else dev(pb["kappa"])
     Xd, Td = dev(X), dev(T)
     sysm = P.condense(Xd, Td, gc, kap, gp)
-    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=1e-5)
+    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=0.7)
     assert st["rel_res"] <= 1e-11, st
     assert np.abs(host(U) - oU).max() <= 1e-10 * np.abs(oU).max(), st
     assert np.abs(host(lam) - olam).max() <= 1e-9 * np.abs(olam).max(), st
@@ -294,8 +294,8 @@ def test_grad_parity(mode, precision):
     Xd, Td, kap = dev(X), dev(T), dev(pb["kappa"])
     gc = P.connect(Td, X.shape[1])
     sysm = P.condense(Xd, Td, gc, kap, gp)
-    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=1e-5)
-    dlogk, dX, st2 = P.grad(Xd, Td, gc, sysm, kap, gp, U, lam, U - dev(Ut), mode=mode, tol=1e-13, inner_tol=1e-5)
+    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=0.7)
+    dlogk, dX, st2 = P.grad(Xd, Td, gc, sysm, kap, gp, U, lam, U - dev(Ut), mode=mode, tol=1e-13, inner_tol=0.7)
     assert np.abs(host(dlogk) - og["dlogk"]).max() <= 1e-6 * np.abs(og["dlogk"]).max()
     assert np.abs(host(dX) - og["dX"]).max() <= 1e-6 * np.abs(og["dX"]).max()
 
