@@ -41,10 +41,13 @@ class Params(C.Structure):
         ("ud_kind", C.c_int32),
         ("ud_par", C.c_double * 4),
         ("quad", C.c_int32),
+        ("g_kind", C.c_int32),
+        ("g_par", C.c_double * 4),
     ]
 
 
-def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE_CENTROID) -> Params:
+def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE_CENTROID, g=(FUN_ZERO, ())) -> Params:
+    """g: on Neumann faces the flux kappa grad(u_g) . nu of u_g = fun(g) (nu outward)."""
     p = Params()
     p.c = c
     p.kappa_const = kappa
@@ -55,6 +58,9 @@ def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE
     for i, v in enumerate(ud[1]):
         p.ud_par[i] = v
     p.quad = quad
+    p.g_kind = g[0]
+    for i, v in enumerate(g[1]):
+        p.g_par[i] = v
     return p
 
 
@@ -166,24 +172,34 @@ def local(coord, tet, sigma, kappa, prm):
     return out
 
 
-def condense(coord, tet, conn, kappa, prm):
-    """Full CSR of S+ (diagonal included) as scipy.sparse.csr_matrix, and rhs."""
+def _u8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def condense(coord, tet, conn, kappa, prm, neumann=None):
+    """CSR of S+ (diagonal included) as scipy.sparse.csr_matrix, and rhs.  With `neumann`
+    (nF flags, 1 = face on Gamma_N) the system is the paper's reduced one over the other faces
+    (RFaces, face order) and (A, rhs, rfaces) is returned, rfaces[f] = row of face f or -1."""
     coord, tet = _f64(coord), _i32(tet)
     nC, nE = coord.shape[1], tet.shape[1]
     nF = conn["nF"]
     kappa = None if kappa is None else _f64(kappa)
+    nm = _u8(neumann)
     rowptr = np.zeros(nF + 1, np.int32)
     col = np.zeros(7 * nF, np.int32)
     val = np.zeros(7 * nF)
     rhs = np.zeros(nF)
-    n = I64()
+    rfaces = np.zeros(nF, np.int32)
+    n, L = I64(), I64()
     _chk(lib().orc_condense(I64(nC), _p(coord), I64(nE), _p(tet), I64(nF), _p(_i32(conn["tet2face"])),
                             _p(np.ascontiguousarray(conn["sigma"], np.int8)), _p(_i32(conn["face2tet"])),
-                            _p(_i32(conn["faces"])), _p(kappa), C.byref(prm), _p(rowptr), _p(col), _p(val),
-                            _p(rhs), C.byref(n)))
-    nnz = n.value
-    A = sp.csr_matrix((val[:nnz].copy(), col[:nnz].copy(), rowptr.copy()), shape=(nF, nF))
-    return A, rhs
+                            _p(_i32(conn["faces"])), _p(kappa), C.byref(prm), _p(nm), _p(rowptr), _p(col), _p(val),
+                            _p(rhs), _p(rfaces), C.byref(n), C.byref(L)))
+    nnz, L = n.value, L.value
+    A = sp.csr_matrix((val[:nnz].copy(), col[:nnz].copy(), rowptr[:L + 1].copy()), shape=(L, L))
+    if neumann is None:
+        return A, rhs[:L]
+    return A, rhs[:L].copy(), rfaces
 
 
 def pcg(A, b, tol=1e-13, maxit=100000):
@@ -198,18 +214,19 @@ def pcg(A, b, tol=1e-13, maxit=100000):
     return x, it.value, rr.value
 
 
-def recover(coord, tet, conn, kappa, prm, lam):
+def recover(coord, tet, conn, kappa, prm, lam, neumann=None):
+    """U(T) = A^-1 (B + LN + C' lambda) with lambda [nF] (entries on Gamma_N are not read)."""
     coord, tet = _f64(coord), _i32(tet)
     nC, nE = coord.shape[1], tet.shape[1]
     kappa = None if kappa is None else _f64(kappa)
     U = np.zeros((4, nE))
     _chk(lib().orc_recover(I64(nC), _p(coord), I64(nE), _p(tet), _p(_i32(conn["tet2face"])),
                            _p(np.ascontiguousarray(conn["sigma"], np.int8)), _p(kappa), C.byref(prm),
-                           _p(None if lam is None else _f64(lam)), _p(U)))
+                           _p(_u8(neumann)), _p(None if lam is None else _f64(lam)), _p(U)))
     return U
 
 
-def dense_solve(coord, tet, conn, kappa, prm):
+def dense_solve(coord, tet, conn, kappa, prm, neumann=None):
     coord, tet = _f64(coord), _i32(tet)
     nC, nE = coord.shape[1], tet.shape[1]
     nF = conn["nF"]
@@ -218,7 +235,8 @@ def dense_solve(coord, tet, conn, kappa, prm):
     lam = np.zeros(nF)
     _chk(lib().orc_dense_solve(I64(nC), _p(coord), I64(nE), _p(tet), I64(nF), _p(_i32(conn["tet2face"])),
                                _p(np.ascontiguousarray(conn["sigma"], np.int8)), _p(_i32(conn["face2tet"])),
-                               _p(_i32(conn["faces"])), _p(kappa), C.byref(prm), _p(U), _p(lam)))
+                               _p(_i32(conn["faces"])), _p(kappa), C.byref(prm), _p(_u8(neumann)), _p(U),
+                               _p(lam)))
     return U, lam
 
 
@@ -240,7 +258,7 @@ def adjoint(coord, tet, conn, kappa, prm, U, lam, gbar, tol=1e-13, maxit=100000)
     return dict(dlogk=dlogk, dX=dX, Q=Q, P=P, iters=it.value)
 
 
-def errors(coord, tet, conn, kappa, prm, U, lam, u_kind, u_par, h, nq=6):
+def errors(coord, tet, conn, kappa, prm, U, lam, u_kind, u_par, h, nq=6, neumann=None):
     coord, tet = _f64(coord), _i32(tet)
     nC, nE = coord.shape[1], tet.shape[1]
     kappa = None if kappa is None else _f64(kappa)
@@ -248,8 +266,9 @@ def errors(coord, tet, conn, kappa, prm, U, lam, u_kind, u_par, h, nq=6):
     par[: len(u_par)] = u_par
     out = np.zeros(3)
     _chk(lib().orc_errors(I64(nC), _p(coord), I64(nE), _p(tet), _p(_i32(conn["tet2face"])),
-                          _p(np.ascontiguousarray(conn["sigma"], np.int8)), _p(kappa), C.byref(prm), _p(_f64(U)),
-                          _p(_f64(lam)), C.c_int32(u_kind), _p(par), C.c_double(h), C.c_int32(nq), _p(out)))
+                          _p(np.ascontiguousarray(conn["sigma"], np.int8)), _p(kappa), C.byref(prm),
+                          _p(_u8(neumann)), _p(_f64(U)), _p(_f64(lam)), C.c_int32(u_kind), _p(par), C.c_double(h),
+                          C.c_int32(nq), _p(out)))
     return dict(grad2=out[0], l22=out[1], lam_h2=out[2])
 
 
@@ -268,10 +287,29 @@ def connect(nC, tet):
     return d
 
 
-def solve(coord, tet, kappa, prm, tol=1e-13, maxit=100000):
-    """Connect, condense, PCG, recover.  Returns (conn, A, rhs, lam, U, iters)."""
+def solve(coord, tet, kappa, prm, tol=1e-13, maxit=100000, neumann_faces=None):
+    """Connect, condense, PCG, recover.  Returns (conn, A, rhs, lam, U, iters).  neumann_faces:
+    optional boundary face list [3][n] (node triples, any orientation) on Gamma_N; lam [nF]
+    then holds the solved multipliers on the other faces and 0 on Gamma_N."""
     conn = connect(coord.shape[1], tet)
-    A, rhs = condense(coord, tet, conn, kappa, prm)
-    lam, it, _ = pcg(A, rhs, tol, maxit)
-    U = recover(coord, tet, conn, kappa, prm, lam)
+    nm = None if neumann_faces is None else neumann_flags(conn, neumann_faces)
+    if nm is None:
+        A, rhs = condense(coord, tet, conn, kappa, prm)
+        lam, it, _ = pcg(A, rhs, tol, maxit)
+    else:
+        A, rhs, rf = condense(coord, tet, conn, kappa, prm, nm)
+        lr, it, _ = pcg(A, rhs, tol, maxit)
+        lam = np.zeros(conn["nF"])
+        lam[rf >= 0] = lr[rf[rf >= 0]]
+    U = recover(coord, tet, conn, kappa, prm, lam, nm)
     return conn, A, rhs, lam, U, it
+
+
+def neumann_flags(conn, tris):
+    """nF flags (uint8): 1 for the faces whose node sets appear in tris [3][n]."""
+    F = np.asarray(conn["faces"])
+    key = {tuple(sorted(F[:, f])): f for f in range(F.shape[1])}
+    nm = np.zeros(F.shape[1], np.uint8)
+    for j in range(np.asarray(tris).shape[1]):
+        nm[key[tuple(sorted(np.asarray(tris)[:, j]))]] = 1
+    return nm

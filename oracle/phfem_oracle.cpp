@@ -269,6 +269,10 @@ struct Params {
   int32_t ud_kind;
   double ud_par[4];
   int32_t quad;  // 0: face-centroid rule of StiffMassPH, 1: P1 interpolation b = M f(x_i)
+  // Neumann data on Gamma_N: g = kappa_T grad(u_g) . nu with u_g = fun(g_kind, g_par) and nu
+  // the outward unit normal (the paper's example prescribes the flux of its exact solution)
+  int32_t g_kind;
+  double g_par[4];
 };
 
 // ---------------------------------------------------------------------------------------
@@ -433,14 +437,47 @@ long double element_inverse(const long double K[4][4], long double kappa, long d
 
 // Element Schur complement (Algorithm 1, eq. schur): S(T) = C A^-1 C', r(T) = C A^-1 B.
 struct Elem {
+  bool neu[4];  // local face on Gamma_N
   long double A[4][4], Ainv[4][4], K[4][4], C[4][4], B[4];
   long double S[4][4], r[4];
   long double vol;
   long double area[4];
 };
 
+// Outward unit normal of the tet on its local face k (away from the opposite vertex).
+void outward_normal(const Local<long double>& L, int k, long double nu[3]) {
+  const long double* x1 = L.x[FACE_V[k][0]];
+  const long double* x2 = L.x[FACE_V[k][1]];
+  const long double* x3 = L.x[FACE_V[k][2]];
+  long double a[3], b[3];
+  for (int d = 0; d < 3; ++d) {
+    a[d] = x2[d] - x1[d];
+    b[d] = x3[d] - x1[d];
+  }
+  long double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+  const int opp = 6 - FACE_V[k][0] - FACE_V[k][1] - FACE_V[k][2];
+  long double s = 0;
+  for (int d = 0; d < 3; ++d) s += n[d] * (L.x[opp][d] - x1[d]);
+  const long double nl = sqrtl(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int d = 0; d < 3; ++d) nu[d] = (s > 0 ? -n[d] : n[d]) / nl;
+}
+
+// g at the centroid of local face k: kappa grad(u_g) . nu (outward)
+long double neumann_g(const Local<long double>& L, int k, long double kappa, const Params& P) {
+  long double c[3], nu[3], gu[3];
+  for (int d = 0; d < 3; ++d)
+    c[d] = (L.x[FACE_V[k][0]][d] + L.x[FACE_V[k][1]][d] + L.x[FACE_V[k][2]][d]) / 3.0L;
+  outward_normal(L, k, nu);
+  fun_grad(P.g_kind, P.g_par, c[0], c[1], c[2], gu);
+  return kappa * (gu[0] * nu[0] + gu[1] * nu[1] + gu[2] * nu[2]);
+}
+
+// tet2face / neumann (nF flags, 1 = Neumann face) may be null: then no Neumann face.  A
+// Neumann face adds LN_j = |F| g(Ct_F) phi_j(Ct_F) = |F| g(Ct_F) / 3 for its three vertices
+// to the load (Section 4.3, Multiplier's LN).
 int element(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int8_t* sigma, const double* kappa,
-            const Params& P, int64_t t, Elem& E) {
+            const Params& P, int64_t t, Elem& E, const int32_t* tet2face = nullptr,
+            const uint8_t* neumann = nullptr) {
   Local<long double> L;
   int rc = load_tet(nC, X, nE, tet, t, L);
   if (rc) return rc;
@@ -449,6 +486,12 @@ int element(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const i
   long double kap = kappa ? kappa[t] : P.kappa_const;
   local_AC(L, kap, P, sig, E.A, E.K, E.C);
   local_load(L, P, E.B);
+  for (int k = 0; k < 4; ++k) {
+    E.neu[k] = neumann && tet2face && neumann[tet2face[k * nE + t]];
+    if (!E.neu[k]) continue;
+    const long double g = neumann_g(L, k, kap, P);
+    for (int m = 0; m < 3; ++m) E.B[FACE_V[k][m]] += L.area[k] * g / 3.0L;
+  }
   if (element_inverse(E.K, kap, (long double)P.c, L.vol, E.Ainv) == 0)
     return fail(ORC_ESINGULAR, "singular element matrix");
   long double AiCt[4][4], AiB[4];
@@ -621,32 +664,41 @@ int pcg(const CSR& A, const std::vector<double>& b, double tol, int maxit, std::
   return ORC_OK;
 }
 
+// The face system over the faces not on Gamma_N (the paper's RFaces: Neumann rows and columns
+// removed, Section 4.4), numbered in face order; rfaces[f] = its row, or -1 on Gamma_N.
+// neumann may be null (every boundary face Dirichlet).
 int build_csr(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int64_t nF, const int32_t* tet2face,
               const int8_t* sigma, const int32_t* face2tet, const int32_t* faces, const double* kappa, const Params& P,
-              CSR& A, std::vector<double>& rhs) {
-  std::vector<std::map<int, double>> rows(nF);
-  rhs.assign(nF, 0.0);
+              const uint8_t* neumann, CSR& A, std::vector<double>& rhs, std::vector<int>& rfaces) {
+  rfaces.assign(nF, -1);
+  int64_t L = 0;
+  for (int64_t f = 0; f < nF; ++f)
+    if (!(neumann && neumann[f])) rfaces[f] = (int)L++;
+  std::vector<std::map<int, double>> rows(L);
+  rhs.assign(L, 0.0);
   for (int64_t f = 0; f < nF; ++f) {
-    if (face2tet[nF + f] < 0) {
+    if (face2tet[nF + f] < 0 && rfaces[f] >= 0) {
       int tri[3] = {faces[f], faces[nF + f], faces[2 * nF + f]};
-      rhs[f] = (double)face_bD(nC, X, tri, P);
+      rhs[rfaces[f]] = (double)face_bD(nC, X, tri, P);
     }
   }
   for (int64_t t = 0; t < nE; ++t) {  // tets in order: owners before neighbours
     Elem E;
-    int rc = element(nC, X, nE, tet, sigma, kappa, P, t, E);
+    int rc = element(nC, X, nE, tet, sigma, kappa, P, t, E, tet2face, neumann);
     if (rc) return rc;
     int F[4];
-    for (int k = 0; k < 4; ++k) F[k] = tet2face[k * nE + t];
+    for (int k = 0; k < 4; ++k) F[k] = rfaces[tet2face[k * nE + t]];
     for (int k = 0; k < 4; ++k) {
-      for (int l = 0; l < 4; ++l) rows[F[k]][F[l]] += (double)E.S[k][l];
+      if (F[k] < 0) continue;
+      for (int l = 0; l < 4; ++l)
+        if (F[l] >= 0) rows[F[k]][F[l]] += (double)E.S[k][l];
       rhs[F[k]] -= (double)E.r[k];
     }
   }
-  A.rowptr.assign(nF + 1, 0);
+  A.rowptr.assign(L + 1, 0);
   A.col.clear();
   A.val.clear();
-  for (int64_t f = 0; f < nF; ++f) {
+  for (int64_t f = 0; f < L; ++f) {
     for (auto& kv : rows[f]) {
       A.col.push_back(kv.first);
       A.val.push_back(kv.second);
@@ -657,17 +709,20 @@ int build_csr(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int64
 }
 
 // U(T) = A(T)^-1 (B(T) + C(T)' Lambda(T))   (Algorithm 1, recovery step)
+// On Gamma_N the multiplier is not an unknown: its faces contribute LN through B instead.
 int recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* tet2face, const int8_t* sigma,
-            const double* kappa, const Params& P, const double* lambda, const double* Bsrc, double* U) {
+            const double* kappa, const Params& P, const double* lambda, const double* Bsrc, double* U,
+            const uint8_t* neumann = nullptr) {
   for (int64_t t = 0; t < nE; ++t) {
     Elem E;
-    int rc = element(nC, X, nE, tet, sigma, kappa, P, t, E);
+    int rc = element(nC, X, nE, tet, sigma, kappa, P, t, E, tet2face, neumann);
     if (rc) return rc;
     long double rhsT[4];
     for (int i = 0; i < 4; ++i) {
       long double s = Bsrc ? (long double)Bsrc[i * nE + t] : E.B[i];
       if (lambda)
-        for (int k = 0; k < 4; ++k) s += E.C[k][i] * lambda[tet2face[k * nE + t]];
+        for (int k = 0; k < 4; ++k)
+          if (!E.neu[k]) s += E.C[k][i] * lambda[tet2face[k * nE + t]];
       rhsT[i] = s;
     }
     for (int i = 0; i < 4; ++i) {
@@ -926,20 +981,25 @@ int orc_local(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const
 // Capacities: col/val 7 nF.  nnz_out = number of stored entries.
 int orc_condense(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int64_t nF, const int32_t* tet2face,
                  const int8_t* sigma, const int32_t* face2tet, const int32_t* faces, const double* kappa,
-                 const Params* P, int32_t* rowptr, int32_t* col, double* val, double* rhs, int64_t* nnz_out) {
+                 const Params* P, const uint8_t* neumann, int32_t* rowptr, int32_t* col, double* val, double* rhs,
+                 int32_t* rfaces, int64_t* nnz_out, int64_t* L_out) {
   int rc = check_mesh(nC, nE, tet);
   if (rc) return rc;
   rc = check_params(P);
   if (rc) return rc;
   CSR A;
   std::vector<double> b;
-  rc = build_csr(nC, X, nE, tet, nF, tet2face, sigma, face2tet, faces, kappa, *P, A, b);
+  std::vector<int> rf;
+  rc = build_csr(nC, X, nE, tet, nF, tet2face, sigma, face2tet, faces, kappa, *P, neumann, A, b, rf);
   if (rc) return rc;
-  std::memcpy(rowptr, A.rowptr.data(), sizeof(int32_t) * (nF + 1));
+  const int64_t L = (int64_t)b.size();
+  std::memcpy(rowptr, A.rowptr.data(), sizeof(int32_t) * (L + 1));
   std::memcpy(col, A.col.data(), sizeof(int32_t) * A.col.size());
   std::memcpy(val, A.val.data(), sizeof(double) * A.val.size());
-  std::memcpy(rhs, b.data(), sizeof(double) * nF);
+  std::memcpy(rhs, b.data(), sizeof(double) * L);
+  if (rfaces) std::memcpy(rfaces, rf.data(), sizeof(int32_t) * nF);
   *nnz_out = (int64_t)A.col.size();
+  if (L_out) *L_out = L;
   return ORC_OK;
 }
 
@@ -962,20 +1022,22 @@ int orc_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const double* 
 
 // Recovery U(T) = A(T)^-1 (B(T) + C(T)' Lambda(T)).  U: [4][nE].
 int orc_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* tet2face,
-                const int8_t* sigma, const double* kappa, const Params* P, const double* lambda, double* U) {
+                const int8_t* sigma, const double* kappa, const Params* P, const uint8_t* neumann,
+                const double* lambda, double* U) {
   int rc = check_mesh(nC, nE, tet);
   if (rc) return rc;
   rc = check_params(P);
   if (rc) return rc;
-  return recover(nC, X, nE, tet, tet2face, sigma, kappa, *P, lambda, nullptr, U);
+  return recover(nC, X, nE, tet, tet2face, sigma, kappa, *P, lambda, nullptr, U, neumann);
 }
 
 // Brute force: the full (N+L) block system of eq. (VectorForm)
-//   [K+M  -C'; -C  0] [U; Lambda] = [b; -b_D]
+//   [K+M  -C'; -C  0] [U; Lambda] = [b + LN; -b_D]
 // assembled dense and solved by LU with partial pivoting in long double.  Tiny meshes only.
+// Faces on Gamma_N carry no multiplier: their rows are lambda_F = 0 and couple to nothing.
 int orc_dense_solve(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int64_t nF, const int32_t* tet2face,
                     const int8_t* sigma, const int32_t* face2tet, const int32_t* faces, const double* kappa,
-                    const Params* P, double* U, double* lambda) {
+                    const Params* P, const uint8_t* neumann, double* U, double* lambda) {
   int rc = check_mesh(nC, nE, tet);
   if (rc) return rc;
   rc = check_params(P);
@@ -985,12 +1047,13 @@ int orc_dense_solve(int64_t nC, const double* X, int64_t nE, const int32_t* tet,
   std::vector<long double> M(n * n, 0.0L), rhs(n, 0.0L);
   for (int64_t t = 0; t < nE; ++t) {
     Elem E;
-    rc = element(nC, X, nE, tet, sigma, kappa, *P, t, E);
+    rc = element(nC, X, nE, tet, sigma, kappa, *P, t, E, tet2face, neumann);
     if (rc) return rc;
     for (int i = 0; i < 4; ++i) {
       for (int j = 0; j < 4; ++j) M[(4 * t + i) * n + 4 * t + j] += E.A[i][j];
       rhs[4 * t + i] += E.B[i];
       for (int k = 0; k < 4; ++k) {
+        if (E.neu[k]) continue;
         int64_t f = tet2face[k * nE + t];
         M[(4 * t + i) * n + N + f] -= E.C[k][i];
         M[(N + f) * n + 4 * t + i] -= E.C[k][i];
@@ -998,7 +1061,9 @@ int orc_dense_solve(int64_t nC, const double* X, int64_t nE, const int32_t* tet,
     }
   }
   for (int64_t f = 0; f < nF; ++f)
-    if (face2tet[nF + f] < 0) {
+    if (neumann && neumann[f]) M[(N + f) * n + N + f] = 1.0L;
+  for (int64_t f = 0; f < nF; ++f)
+    if (face2tet[nF + f] < 0 && !(neumann && neumann[f])) {
       int tri[3] = {faces[f], faces[nF + f], faces[2 * nF + f]};
       rhs[N + f] = -face_bD(nC, X, tri, *P);
     }
@@ -1048,7 +1113,8 @@ int orc_adjoint(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int
   if (rc) return rc;
   CSR A;
   std::vector<double> b;
-  rc = build_csr(nC, X, nE, tet, nF, tet2face, sigma, face2tet, faces, kappa, *Pm, A, b);
+  std::vector<int> rf;
+  rc = build_csr(nC, X, nE, tet, nF, tet2face, sigma, face2tet, faces, kappa, *Pm, nullptr, A, b, rf);
   if (rc) return rc;
   // adjoint right-hand side -C A^-1 gbar
   std::vector<double> w(4 * nE), radj(nF, 0.0);
@@ -1124,12 +1190,13 @@ int orc_adjoint(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int
 }
 
 // Error norms against an exact solution u (kind/params): out[0] = sum_T ||grad(u-u_h)||^2,
-// out[1] = sum_T ||u-u_h||^2, out[2] = sum_T h sum_{F in dT} ||kappa grad u . nu_F - lambda_F||^2_F
-// (nu_F: outward normal of the face's owner; all boundary faces carry multipliers).
+// out[1] = sum_T ||u-u_h||^2, out[2] = sum_T h sum_{F in dT \ Gamma_N} ||kappa grad u . nu_F - lambda_F||^2_F
+// (nu_F: outward normal of the face's owner; the h-norm of eq. (eMnorm) without the root).
+// With out[0..2], ||u - u_h||_Y = sqrt(out[0] + out[1] / h^2) and ||kappa - kappa_h||_h = sqrt(out[2]).
 // Quadrature: collapsed Gauss-Legendre product rules with nq points per direction.
 int orc_errors(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* tet2face,
-               const int8_t* sigma, const double* kappa, const Params* P, const double* U, const double* lambda,
-               int32_t u_kind, const double* u_par, double h, int32_t nq, double* out) {
+               const int8_t* sigma, const double* kappa, const Params* P, const uint8_t* neumann, const double* U,
+               const double* lambda, int32_t u_kind, const double* u_par, double h, int32_t nq, double* out) {
   int rc = check_mesh(nC, nE, tet);
   if (rc) return rc;
   std::vector<std::array<long double, 4>> qt;
@@ -1165,6 +1232,7 @@ int orc_errors(int64_t nC, const double* X, int64_t nE, const int32_t* tet, cons
       e_l2 += w * (u - uh) * (u - uh);
     }
     for (int k = 0; k < 4; ++k) {
+      if (neumann && neumann[tet2face[k * nE + t]]) continue;  // the h-norm runs over dT \ Gamma_N
       const long double* x1 = L.x[FACE_V[k][0]];
       const long double* x2 = L.x[FACE_V[k][1]];
       const long double* x3 = L.x[FACE_V[k][2]];

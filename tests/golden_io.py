@@ -43,3 +43,8 @@ def faces_listing1():
 def counts_tables():
     s, _ = _sections("counts_tables.txt")
     return s[None].astype(np.int64)
+
+
+def table4_errors():
+    """rows: level, Y-error, Y-order, h-error, h-order (Table 4)"""
+    return np.loadtxt(os.path.join(GOLDEN, "table4_errors.txt"))

@@ -6,6 +6,8 @@ inputs written here in pure Python.
 """
 import itertools
 
+import os
+
 import numpy as np
 import pytest
 
@@ -359,6 +361,97 @@ def test_element_blocks_fine_tet_exact():
         re = np.array([float(r[k, 0]) for k in range(4)])
         assert np.abs(L["S"][:, 0].reshape(4, 4) - Se).max() <= 1e-15 * np.abs(Se).max()
         assert np.abs(L["r"][:, 0] - re).max() <= 1e-14 * np.abs(re).max()
+
+
+def _paper_levels(L):
+    X, T, Db, Nb = M.paper_cube()
+    for _ in range(L):
+        X, T, Db, Nb = O.refine(X, T, Db, Nb)
+    return X, T, Db, Nb
+
+
+def _owner_normals(X, T, conn):
+    """outward unit normal of every face seen from its owner tet"""
+    f2t = np.asarray(conn["face2tet"])
+    local = [(0, 1, 2), (0, 2, 3), (0, 3, 1), (3, 2, 1)]
+    nu = np.zeros((3, conn["nF"]))
+    for f in range(conn["nF"]):
+        t, k = divmod(int(f2t[0, f]), 4)
+        a, b, c = (X[:, T[v, t]] for v in local[k])
+        n = np.cross(b - a, c - a)
+        d = X[:, T[6 - sum(local[k]), t]] - a
+        nu[:, f] = (-n if n @ d > 0 else n) / np.linalg.norm(n)
+    return nu
+
+
+@pytest.mark.parametrize("lev", [0, 1, 2])
+def test_neumann_linear_exact(lev):
+    """Mixed Dirichlet/Neumann faces of Listing 1 (Db, Nb), u = a + b.x, P1 load: the discrete
+    solution is exact -- U = nodal values, lambda_F = kappa grad u . nu_F on the faces left in
+    the system -- and the reduced system has Table 2's size L = nF - |Nb|."""
+    X, T, Db, Nb = _paper_levels(lev)
+    a = (0.3, 0.5, -0.2, 0.7)
+    kap, cc = 0.8, 1.3
+    p = O.params(c=cc, kappa=kap, f=(O.FUN_LINEAR, tuple(cc * v for v in a)), ud=(O.FUN_LINEAR, a),
+                 g=(O.FUN_LINEAR, a), quad=O.QUAD_P1_INTERP)
+    conn, A, rhs, lam, U, it = O.solve(X, T, None, p, tol=1e-14, neumann_faces=Nb)
+    assert A.shape[0] == conn["nF"] - Nb.shape[1]
+    u = a[0] + a[1] * X[0] + a[2] * X[1] + a[3] * X[2]
+    assert np.abs(U - u[T]).max() <= 1e-12
+    nm = O.neumann_flags(conn, Nb)
+    flux = kap * (np.array(a[1:]) @ _owner_normals(X, T, conn))
+    assert np.abs(lam - flux)[nm == 0].max() <= 1e-10 * np.abs(flux).max()  # lambda: solve-limited
+
+
+def test_neumann_table2_sizes():
+    """The reduced face system has Table 2's L rows and the primal space Table 2's N = 4 nE."""
+    tab = np.loadtxt(os.path.join(G.GOLDEN, "counts_tables.txt"))
+    X, T, Db, Nb = M.paper_cube()
+    for lev in (1, 2, 3):
+        X, T, Db, Nb = O.refine(X, T, Db, Nb)
+        conn = O.connect(X.shape[1], T)
+        nm = O.neumann_flags(conn, Nb)
+        p = O.params(c=1.0, f=(O.FUN_CONST, (1.0,)))
+        A, rhs, rf = O.condense(X, T, conn, None, p, nm)
+        row = tab[tab[:, 0] == lev][0]
+        assert 4 * T.shape[1] == row[5] and A.shape[0] == row[6] and (rf >= 0).sum() == row[6]
+
+
+@pytest.mark.parametrize("lev", [0, 1])
+def test_neumann_dense_matches_schur(lev):
+    """Brute force of the full block system with Gamma_N faces removed and LN in the load
+    equals the condensed solve (paper's example data)."""
+    X, T, Db, Nb = _paper_levels(lev)
+    p = O.params(c=1.0, f=(O.FUN_X2Y2Z2_LOAD, (1.0, 1.0)), ud=(O.FUN_X2Y2Z2, (1.0,)), g=(O.FUN_X2Y2Z2, (1.0,)))
+    conn, A, rhs, lam, U, it = O.solve(X, T, None, p, tol=1e-14, neumann_faces=Nb)
+    nm = O.neumann_flags(conn, Nb)
+    Ud, ld = O.dense_solve(X, T, conn, None, p, nm)
+    assert np.abs(U - Ud).max() <= 1e-11 * np.abs(Ud).max()
+    assert np.abs(lam - ld)[nm == 0].max() <= 1e-10 * np.abs(ld).max()
+
+
+def test_table4_convergence_orders():
+    """The paper's example: errors in the Y-norm and the h-norm converge with the orders
+    printed in Table 4 (about 1).  The printed values themselves are not pinned: the norm
+    quadrature and h are unstated (here: collapsed Gauss rules, h = largest edge)."""
+    tab = G.table4_errors()
+    X, T, Db, Nb = M.paper_cube()
+    p = O.params(c=1.0, f=(O.FUN_X2Y2Z2_LOAD, (1.0, 1.0)), ud=(O.FUN_X2Y2Z2, (1.0,)), g=(O.FUN_X2Y2Z2, (1.0,)))
+    ey, el, hs = [], [], []
+    for lev in (1, 2, 3):
+        X, T, Db, Nb = O.refine(X, T, Db, Nb)
+        conn, A, rhs, lam, U, it = O.solve(X, T, None, p, tol=1e-13, neumann_faces=Nb)
+        nm = O.neumann_flags(conn, Nb)
+        h = max(np.linalg.norm(X[:, T[a]] - X[:, T[b]], axis=0).max()
+                for a, b in [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)])
+        er = O.errors(X, T, conn, None, p, U, lam, O.FUN_X2Y2Z2, (1.0,), h, nq=6, neumann=nm)
+        ey.append(np.sqrt(er["grad2"] + er["l22"] / h ** 2))
+        el.append(np.sqrt(er["lam_h2"]))
+        hs.append(h)
+    for i in (1, 2):
+        oy = np.log(ey[i - 1] / ey[i]) / np.log(hs[i - 1] / hs[i])
+        ol = np.log(el[i - 1] / el[i]) / np.log(hs[i - 1] / hs[i])
+        assert abs(oy - tab[i, 2]) <= 0.15 and abs(ol - tab[i, 4]) <= 0.15, (i, oy, ol)
 
 
 def test_assembly_structure():
