@@ -70,8 +70,17 @@ enum {
 enum { PHFEM_QUAD_FACE_CENTROID = 0, PHFEM_QUAD_P1_INTERP = 1 };
 enum { PHFEM_FP64 = 0, PHFEM_MIXED = 1 };
 
-/* Problem -div(kappa grad u) + c u = f, u = u_D on the boundary (model problem of
- * Section 4 with a per-tet kappa; the paper has kappa = c = 1).  All boundary faces are Dirichlet faces.
+/* Problem -div(kappa grad u) + c u = f (model problem of Section 4 with a per-tet kappa;
+ * the paper has kappa = c = 1), u = u_D on Dirichlet faces, kappa grad u . nu = g on the
+ * Neumann faces flagged in `neumann` (NULL: every boundary face is a Dirichlet face).
+ *  g: the flux kappa_T grad(u_g) . nu of the data function u_g = fun(g_kind, g_par), nu the
+ *        outward unit normal (the paper's example prescribes the flux of its exact solution);
+ *        taken at the face centroid, LN = |F| g(Ct_F) / 3 on the face's vertices.
+ *  neumann: device array of nF flags (1 = Neumann face; only boundary faces may be flagged),
+ *        caller-owned, read by condense and solve.  A Neumann face leaves the multiplier
+ *        space as in the paper: the face system keeps its row as lambda_F = g(Ct_F) (diagonal
+ *        1, no coupling: its column is zero in every other row), which is the paper's system
+ *        over the other faces (RFaces) with LN in the load, without renumbering.
  *  quad: PHFEM_QUAD_FACE_CENTROID = the paper's load rule (f at the 4 face centroids,
  *        weight |T|/4, StiffMassPH); PHFEM_QUAD_P1_INTERP = b(T) = M(T) f(x_i).
  *  precision: PHFEM_FP64, or PHFEM_MIXED = FP32 local-matrix and element-Schur arithmetic
@@ -85,6 +94,9 @@ typedef struct {
   double ud_par[4];
   int32_t quad;
   int32_t precision;
+  int32_t g_kind;
+  double g_par[4];
+  const uint8_t* neumann;
 } phfem_params;
 
 /* ---------------------------------------------------------------- connect (a1-a3) ---- */
@@ -210,6 +222,8 @@ int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const int32_t* t
                    const double* kappa, const phfem_params* p, double* vol, double* K, double* d, double* B,
                    double* S, double* r, phfem_stream_t stream);
 
+/* (phfem_assemble ignores params.neumann: its B(T) is the load without LN.) */
+
 /* ---------------------------------------------------------------- condense (a5-a7) --- */
 size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision);
 
@@ -277,7 +291,8 @@ size_t phfem_grad_workspace(int64_t nE, int64_t nF, int32_t mode);
  *   dJ/dlog kappa_T = -kappa_T P_T' K_T U_T,
  *   dJ/dX = -d/dX [P'A U - lambda'C P - P'B - Q'C U + Q'b_D]  (P, U, lambda, Q fixed).
  * Outputs: dJ_dlogkappa[nE] (may be NULL), dJ_dcoord[3][nC] (may be NULL; zeroed and
- * accumulated with atomics).  Synchronizes.  Errors as phfem_solve. */
+ * accumulated with atomics).  Synchronizes.  Errors as phfem_solve; EINVAL when
+ * params.neumann is set (the gradient covers Dirichlet boundaries only). */
 int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF, const int32_t* faces,
                const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet, const int32_t* nbr,
                const double* kappa, const phfem_params* p, const int32_t* rowptr, const int32_t* col,

@@ -47,6 +47,9 @@ class Params(C.Structure):
         ("ud_par", C.c_double * 4),
         ("quad", C.c_int32),
         ("precision", C.c_int32),
+        ("g_kind", C.c_int32),
+        ("g_par", C.c_double * 4),
+        ("neumann", C.c_void_p),
     ]
 
 
@@ -57,7 +60,9 @@ class SolveStats(C.Structure):
         return dict(iters=self.iters, ir_steps=self.ir_steps, rel_res=self.rel_res, rhs_norm=self.rhs_norm)
 
 
-def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE_CENTROID, precision=FP64):
+def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE_CENTROID, precision=FP64,
+           g=(FUN_ZERO, ()), neumann=None):
+    """neumann: device uint8 tensor of nF flags (kept alive by the caller) or None."""
     p = Params()
     p.c, p.kappa_const = c, kappa
     p.f_kind = f[0]
@@ -67,6 +72,11 @@ def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE
     for i, v in enumerate(ud[1]):
         p.ud_par[i] = v
     p.quad, p.precision = quad, precision
+    p.g_kind = g[0]
+    for i, v in enumerate(g[1]):
+        p.g_par[i] = v
+    p.neumann = None if neumann is None else neumann.data_ptr()
+    p._neumann_ref = neumann  # keeps the flags alive with the params
     return p
 
 

@@ -109,6 +109,9 @@ struct DevParams {
   int uk;
   double up[4];
   int quad;
+  int gk;
+  double gp[4];
+  const uint8_t* nm;  // Neumann flags per face, or null
 };
 
 inline DevParams to_dev(const phfem_params& p) {
@@ -120,8 +123,11 @@ inline DevParams to_dev(const phfem_params& p) {
   for (int i = 0; i < 4; ++i) {
     d.fp[i] = p.f_par[i];
     d.up[i] = p.ud_par[i];
+    d.gp[i] = p.g_par[i];
   }
   d.quad = p.quad;
+  d.gk = p.g_kind;
+  d.nm = p.neumann;
   return d;
 }
 

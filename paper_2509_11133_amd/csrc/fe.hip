@@ -210,6 +210,22 @@ __device__ __forceinline__ void gather_x(int64_t nC, const double* __restrict__ 
     for (int e = 0; e < 3; ++e) x[i][e] = X[e * nC + v[i]];
 }
 
+// Neumann flux at the centroid of local face k: kappa grad(u_g) . nu, nu the outward unit
+// normal = -grad(lambda_opp(k)) / |grad(lambda_opp(k))| (the barycentric coordinate of the
+// opposite vertex grows inward).  LN adds |F_k| g / 3 to the three vertices of face k, which
+// is d_k g / 3 with d_k = |F_k| on a boundary face (sigma = +1).
+template <class R>
+__device__ __forceinline__ double neumann_flux(const Elem<R>& E, const double x[4][3], int k, double kap,
+                                               const DevParams& P) {
+  const int a = fv(k, 0), b = fv(k, 1), c = fv(k, 2), o = opp(k);
+  const double g0 = (double)E.g[o][0], g1 = (double)E.g[o][1], g2 = (double)E.g[o][2];
+  const double gl = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+  double gu[3];
+  fun_grad(P.gk, P.gp, (x[a][0] + x[b][0] + x[c][0]) / 3.0, (x[a][1] + x[b][1] + x[c][1]) / 3.0,
+           (x[a][2] + x[b][2] + x[c][2]) / 3.0, gu);
+  return -kap * (gu[0] * g0 + gu[1] * g1 + gu[2] * g2) / gl;
+}
+
 // ---------------------------------------------------------------- assemble (inspection)
 template <class R>
 __global__ __launch_bounds__(FT) void k_assemble(int64_t nC, const double* __restrict__ X, int64_t nE,
@@ -267,7 +283,7 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
   if (diag) diag[f] = 0.0;
   if (!rhs) return;
   double b = 0.0;
-  if (!interior && P.uk != PHFEM_FUN_ZERO) {
+  if (!interior && P.uk != PHFEM_FUN_ZERO && !(P.nm && P.nm[f])) {
     double x[3][3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -337,6 +353,20 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __re
     E.init(x, kap, P.c, sig);
     R B[4], r[4], su[10];
     load_vec<R>(x, E.vol, P, B);
+    bool neu[4] = {false, false, false, false};
+    double gN[4] = {0, 0, 0, 0};
+    if (P.nm) {  // Neumann faces: LN in the load; their rows become lambda_F = g
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        neu[k] = (uint32_t)F[k] < (uint64_t)nF && P.nm[F[k]];
+        if (!neu[k]) continue;
+        gN[k] = neumann_flux(E, x, k, kap, P);
+        const R ln = E.d[k] * (R)gN[k] * (R)(1.0 / 3.0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i != opp(k)) B[i] += ln;
+      }
+    }
     E.CAinv(B, r);
     E.Supper(su);
 #pragma unroll
@@ -345,14 +375,14 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __re
         SlotRec<R> rec;
         uint2 w[W];
       } u;
-      u.rec.d = su[uidx(k, k)];
-      u.rec.r = r[k];
+      u.rec.d = neu[k] ? (R)1 : su[uidx(k, k)];
+      u.rec.r = neu[k] ? (R)(-gN[k]) : r[k];
       int n = 0;
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
         if (l == k) continue;
-        u.rec.o[n] = su[uidx(k, l)];
-        u.rec.c[n] = F[l];
+        u.rec.o[n] = neu[k] ? (R)0 : su[uidx(k, l)];
+        u.rec.c[n] = neu[l] ? (int32_t)((uint32_t)F[l] | 0x80000000u) : F[l];  // a Neumann column: no coupling
         ++n;
       }
 #pragma unroll
@@ -387,7 +417,7 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
     int cf[6];
     double cv[6];
     double dg = 0.0, rh = 0.0;
-    if (!interior && P.uk != PHFEM_FUN_ZERO) {  // b_D = |F| u_D(centroid) on a boundary face
+    if (!interior && P.uk != PHFEM_FUN_ZERO && !(P.nm && P.nm[f])) {  // b_D = |F| u_D(centroid), Dirichlet
       double xx[3][3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
@@ -427,6 +457,14 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
         cf[i] = INT_MAX;  // sorts last; written as column F with value 0
         cv[i] = 0.0;
       }
+    }
+    if (P.nm) {  // columns of Neumann faces carry no coupling
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+        if (cf[i] != INT_MAX && (cf[i] & 0x80000000)) {
+          cf[i] &= 0x7fffffff;
+          cv[i] = 0.0;
+        }
     }
     const int base = 6 * (int)(f - f0);
 #pragma unroll
@@ -482,10 +520,21 @@ __global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __rest
   } else {
     load_vec<double>(x, E.vol, P, B);
   }
-  double mu[4] = {0, 0, 0, 0};
+  double mu[4] = {0, 0, 0, 0}, gN[4] = {0, 0, 0, 0};
+  bool neu[4] = {false, false, false, false};
+  if (P.nm && !gsrc) {  // Neumann faces: LN = C_k' g in place of C_k' lambda_F
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      neu[k] = P.nm[F[k]];
+      if (neu[k]) gN[k] = neumann_flux(E, x, k, kap, P);
+    }
+  }
   if (lambda) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) mu[k] = E.d[k] * lambda[F[k]];
+    for (int k = 0; k < 4; ++k) mu[k] = E.d[k] * (neu[k] ? gN[k] : lambda[F[k]]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mu[k] = neu[k] ? E.d[k] * gN[k] : 0.0;
   }
   const double s = ((B[0] + B[1]) + (B[2] + B[3]) + ((mu[0] + mu[1]) + (mu[2] + mu[3]))) * E.icv;
   double y[4], u[4];
@@ -500,7 +549,8 @@ __global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __rest
   if (res) {
     const double su = (u[0] + u[1]) + (u[2] + u[3]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) atomicAdd(&res[F[k]], -E.d[k] * (su - u[opp(k)]) / 3.0);
+    for (int k = 0; k < 4; ++k)  // a Neumann row is lambda_F = g
+      atomicAdd(&res[F[k]], neu[k] ? gN[k] - (lambda ? lambda[F[k]] : 0.0) : -E.d[k] * (su - u[opp(k)]) / 3.0);
   }
 }
 

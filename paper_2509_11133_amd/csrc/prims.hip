@@ -28,7 +28,8 @@ int check_params(const phfem_params* p) {
   if (!(p->c > 0)) return err(PHFEM_ESINGULAR, "reaction coefficient c must be > 0 (kappa K + c M singular)");
   if (p->quad != PHFEM_QUAD_FACE_CENTROID && p->quad != PHFEM_QUAD_P1_INTERP) return err(PHFEM_EINVAL, "bad quad");
   if (p->precision != PHFEM_FP64 && p->precision != PHFEM_MIXED) return err(PHFEM_EINVAL, "bad precision");
-  if (p->f_kind < 0 || p->f_kind > PHFEM_FUN_X2Y2Z2_LOAD || p->ud_kind < 0 || p->ud_kind > PHFEM_FUN_X2Y2Z2_LOAD)
+  if (p->f_kind < 0 || p->f_kind > PHFEM_FUN_X2Y2Z2_LOAD || p->ud_kind < 0 || p->ud_kind > PHFEM_FUN_X2Y2Z2_LOAD ||
+      p->g_kind < 0 || p->g_kind > PHFEM_FUN_X2Y2Z2_LOAD)
     return err(PHFEM_EINVAL, "bad function kind");
   return PHFEM_OK;
 }

@@ -531,6 +531,7 @@ extern "C" int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int
                      max_iter);
   if (rc) return rc;
   if (!nbr || !U || !lambda || !dJdU || !stats) return err(PHFEM_EINVAL, "null nbr/U/lambda/dJdU/stats");
+  if (p->neumann) return err(PHFEM_EINVAL, "the gradient covers Dirichlet boundaries only (params.neumann must be NULL)");
   if (!work || work_bytes < phfem_grad_workspace(nE, nF, mode)) return err(PHFEM_EWORKSPACE, "grad workspace too small");
   Arena a(work, work_bytes);
   double* radj = a.take<double>(nF);

@@ -65,6 +65,24 @@ def refine(coord, tetra, conn, db=None, nb=None):
     return Xo, To, dbo, nbo
 
 
+def neumann_flags(conn, tris):
+    """Device uint8 flags [nF] (1 = Neumann face) for the boundary triangles tris [3][n]
+    (node triples in any order, e.g. a refined Nb list).  Matched on the host against the
+    boundary faces only (a vanishing fraction of the faces); every triangle must be one."""
+    dev = conn["faces"].device
+    f2t = conn["face2tet"][1]
+    bnd = torch.nonzero(f2t < 0).flatten()
+    key = {tuple(sorted(t)): int(f) for f, t in zip(bnd.tolist(), conn["faces"][:, bnd].t().tolist())}
+    tris = tris.cpu().numpy() if hasattr(tris, "cpu") else np.asarray(tris)
+    nm = np.zeros(conn["nF"], np.uint8)
+    for j in range(tris.shape[1]):
+        k = tuple(sorted(int(v) for v in tris[:, j]))
+        if k not in key:
+            raise B.PhfemError(B.EINVAL, f"Neumann triangle {k} is not a boundary face")
+        nm[key[k]] = 1
+    return torch.tensor(nm, device=dev)
+
+
 def refine_connected(coord, tetra, conn, status=None):
     """One refinement level that also returns the refined mesh's full connectivity (same
     numbering as connect() on it), derived from `conn` (full connectivity of the coarse

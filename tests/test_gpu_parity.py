@@ -414,3 +414,107 @@ def test_refine_connected_matches_sort_connect_L5():
     for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma", "face2tet",
               "nbr"):
         assert torch.equal(conn[k], ref[k]), k
+
+
+# ------------------------------------------------------------------ mixed Dirichlet/Neumann (paper's example)
+def paper_levels(L):
+    X, T, Db, Nb = M.paper_cube()
+    for _ in range(L):
+        X, T, Db, Nb = O.refine(X, T, Db, Nb)
+    return X, T, Db, Nb
+
+
+EXAMPLE = dict(c=1.0, f=(O.FUN_X2Y2Z2_LOAD, (1.0, 1.0)), ud=(O.FUN_X2Y2Z2, (1.0,)), g=(O.FUN_X2Y2Z2, (1.0,)))
+
+
+def owner_flux(X, T, conn, kap, gpar):
+    """kappa grad(x^2 y^2 z^2 * p0) . nu (owner outward) at every face centroid"""
+    f2t = np.asarray(conn["face2tet"])
+    F = np.asarray(conn["faces"])
+    local = [(0, 1, 2), (0, 2, 3), (0, 3, 1), (3, 2, 1)]
+    out = np.zeros(F.shape[1])
+    for f in range(F.shape[1]):
+        t, k = divmod(int(f2t[0, f]), 4)
+        a, b, c = (X[:, T[v, t]] for v in local[k])
+        n = np.cross(b - a, c - a)
+        n = (-n if n @ (X[:, T[6 - sum(local[k]), t]] - a) > 0 else n) / np.linalg.norm(n)
+        x, y, z = (a + b + c) / 3
+        gu = 2 * gpar * np.array([x * y * y * z * z, x * x * y * z * z, x * x * y * y * z])
+        out[f] = kap * gu @ n
+    return out
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_neumann_condense_parity(L, precision, tol):
+    """Listing 1's cube with its Db / Nb faces and the paper's example data: the rows of the
+    faces left in the system equal the oracle's reduced system (RFaces) with LN in the load;
+    Neumann rows are lambda_F = g(Ct_F) and their columns are zero."""
+    X, T, Db, Nb = paper_levels(L)
+    oc = O.connect(X.shape[1], T)
+    nm = O.neumann_flags(oc, Nb)
+    op = O.params(**EXAMPLE)
+    A, rhs, rf = O.condense(X, T, oc, None, op, nm)
+    gc = P.connect(dev(T), X.shape[1])
+    nmd = P.neumann_flags(gc, dev(Nb))
+    assert np.array_equal(host(nmd), nm)
+    gp = P.params(**EXAMPLE, precision=precision, neumann=nmd)
+    sysm = P.condense(dev(X), dev(T), gc, None, gp)
+    G = full_csr(sysm, oc["nF"])
+    free = np.flatnonzero(nm == 0)
+    Gf = G[free][:, free]
+    D = abs(Gf - A).tocsr()
+    rowmax = np.asarray(abs(A).max(axis=1).todense()).ravel()
+    assert (np.asarray(D.max(axis=1).todense()).ravel() / rowmax).max() <= tol
+    r = host(sysm["rhs"])
+    assert np.abs(r[free] - rhs).max() <= tol * np.abs(rhs).max()
+    neu = np.flatnonzero(nm)
+    assert np.all(G[free][:, neu].toarray() == 0) and np.all(G[neu][:, free].toarray() == 0)
+    assert np.abs(G[neu][:, neu].toarray() - np.eye(len(neu))).max() == 0
+    g = owner_flux(X, T, oc, 1.0, 1.0)
+    assert np.abs(r[neu] - g[neu]).max() <= 1e-12 * np.abs(g).max() + (tol if precision else 0) * np.abs(g).max()
+
+
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
+def test_neumann_solve_parity(mode, precision):
+    """u_h of the paper's example with mixed boundaries against the oracle (1e-10), lambda on
+    the faces left in the system (1e-9), lambda = g on the Neumann faces."""
+    X, T, Db, Nb = paper_levels(3)
+    op = O.params(**EXAMPLE)
+    oc, A, rhs, lam, U, it = O.solve(X, T, None, op, tol=1e-14, neumann_faces=Nb)
+    nm = O.neumann_flags(oc, Nb)
+    gc = P.connect(dev(T), X.shape[1])
+    gp = P.params(**EXAMPLE, precision=precision, neumann=P.neumann_flags(gc, dev(Nb)))
+    sysm = P.condense(dev(X), dev(T), gc, None, gp)
+    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=mode, tol=1e-13)
+    assert np.abs(host(gU) - U).max() <= 1e-10 * np.abs(U).max()
+    gl = host(glam)
+    assert np.abs(gl - lam)[nm == 0].max() <= 1e-9 * np.abs(lam).max()
+    g = owner_flux(X, T, oc, 1.0, 1.0)
+    assert np.abs(gl - g)[nm == 1].max() <= 1e-9 * np.abs(g).max()
+
+
+def test_neumann_linear_exact_gpu():
+    """Linear exact solution with Listing 1's Db / Nb and the P1 load: U = nodal values."""
+    X, T, Db, Nb = paper_levels(2)
+    a = (0.3, 0.5, -0.2, 0.7)
+    kap, cc = 0.8, 1.3
+    par = dict(c=cc, kappa=kap, f=(O.FUN_LINEAR, tuple(cc * v for v in a)), ud=(O.FUN_LINEAR, a),
+               g=(O.FUN_LINEAR, a), quad=1)
+    gc = P.connect(dev(T), X.shape[1])
+    gp = P.params(**par, neumann=P.neumann_flags(gc, dev(Nb)))
+    sysm = P.condense(dev(X), dev(T), gc, None, gp)
+    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=0, tol=1e-14)
+    u = a[0] + a[1] * X[0] + a[2] * X[1] + a[3] * X[2]
+    assert np.abs(host(gU) - u[T]).max() <= 1e-12
+
+
+def test_neumann_grad_rejected():
+    X, T, Db, Nb = paper_levels(1)
+    gc = P.connect(dev(T), X.shape[1])
+    gp = P.params(**EXAMPLE, neumann=P.neumann_flags(gc, dev(Nb)))
+    sysm = P.condense(dev(X), dev(T), gc, None, gp)
+    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=0, tol=1e-12)
+    from paper_2509_11133_amd import _binding as B
+    with pytest.raises(B.PhfemError):
+        P.grad(dev(X), dev(T), gc, sysm, None, gp, gU, glam, gU)
