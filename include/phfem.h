@@ -300,6 +300,27 @@ int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra
                int32_t mode, double tol, double inner_tol, int32_t max_iter, void* work, size_t work_bytes,
                double* dJ_dlogkappa, double* dJ_dcoord, phfem_solve_stats* stats, phfem_stream_t stream);
 
+/* ---------------------------------------------------------------- error norms ------- */
+size_t phfem_errors_workspace(int64_t nE);
+
+/* A-priori error norms of a solution (U, lambda) of phfem_solve against an exact solution
+ * u = (u_kind, u_par[4] in host memory) (Section 5: the mesh-dependent norm ||.||_Y and the h-norm of the
+ * multiplier, eq. (eMnorm); the quantities of Table 4), with u_h linear on each tet:
+ *   out[0] = sum_T ||grad(u - u_h)||^2_T,   out[1] = sum_T ||u - u_h||^2_T,
+ *   out[2] = sum_T h sum_{F in dT \ Gamma_N} ||kappa_T grad u . nu_F - lambda_F||^2_F,
+ * nu_F the outward normal of the face's owner tet (lambda's orientation), Gamma_N the faces
+ * flagged in params.neumann (if set).  ||u - u_h||_Y = sqrt(out[0] + out[1] / h^2),
+ * ||kappa grad u - lambda||_h = sqrt(out[2]).  h > 0 is the caller's mesh size.
+ * Quadrature: collapsed Gauss-Legendre products with nq in [1, 12] points per direction (exact
+ * to degree 2 nq - 3 on tets and 2 nq - 2 on faces).  Inputs on the device as for
+ * phfem_solve (nF faces); out[3] is HOST memory, written only on success.  The sums are
+ * reduced in a fixed order (deterministic).  Synchronizes.  Errors: EINVAL (also for a vertex
+ * or face id out of range, found on the device), EWORKSPACE. */
+int phfem_errors(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF, const int32_t* tet2face,
+                 const int8_t* sigma, const double* kappa, const phfem_params* p, const double* U,
+                 const double* lambda, int32_t u_kind, const double* u_par, double h, int32_t nq, void* work,
+                 size_t work_bytes, double* out, phfem_stream_t stream);
+
 /* ---------------------------------------------------------------- profiling --------- */
 /* When enabled, every kernel launch of the library is bracketed by HIP events on its
  * stream.  phfem_profile_query synchronizes those events and returns, for the kernel

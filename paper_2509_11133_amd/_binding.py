@@ -27,7 +27,8 @@ EXPORTS = [
     "phfem_assemble", "phfem_condense_workspace", "phfem_condense", "phfem_solve_workspace", "phfem_solve",
     "phfem_grad_workspace", "phfem_grad", "phfem_profile_enable", "phfem_profile_reset", "phfem_profile_query",
     "phfem_profile_names", "phfem_refine_connected_workspace", "phfem_refine_connected", "phfem_refined_sizes",
-    "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels",
+    "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels", "phfem_errors_workspace",
+    "phfem_errors",
 ]
 
 
@@ -95,7 +96,7 @@ def lib():
         L.phfem_last_error.restype = C.c_char_p
         for n in ("phfem_connect_workspace", "phfem_condense_workspace", "phfem_solve_workspace",
                   "phfem_grad_workspace", "phfem_refine_connected_workspace",
-                  "phfem_refine_connected_levels_workspace"):
+                  "phfem_refine_connected_levels_workspace", "phfem_errors_workspace"):
             getattr(L, n).restype = SZ
         L.phfem_connect_workspace.argtypes = [I64, I64, I32]
         L.phfem_condense_workspace.argtypes = [I64, I64, I64, I32]
@@ -115,6 +116,8 @@ def lib():
                                   + [VP] * 3 + [VP])
         L.phfem_grad.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 7 + [VP] * 4 + [VP] * 3
                                  + [I32, DBL, DBL, I32, VP, SZ] + [VP] * 3 + [VP])
+        L.phfem_errors_workspace.argtypes = [I64]
+        L.phfem_errors.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, SZ, VP, VP]
         L.phfem_profile_enable.argtypes = [I32]
         L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
         L.phfem_profile_names.argtypes = [C.c_char_p, SZ]
@@ -219,6 +222,16 @@ def phfem_grad(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, nbr, 
                           _p(kappa), C.addressof(prm), _p(rowptr), _p(col), _p(val), _p(diag), _p(U), _p(lam),
                           _p(dJdU), mode, tol, inner_tol, max_iter, _p(work), work.numel(), _p(dlogk), _p(dX),
                           C.addressof(stats), _stream()))
+
+
+def phfem_errors(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, prm, U, lam, u_kind, u_par, h, nq, work):
+    """(sum ||grad(u-u_h)||^2, sum ||u-u_h||^2, sum h ||kappa grad u.nu - lambda||^2) as floats."""
+    par = (C.c_double * 4)(*([float(v) for v in u_par] + [0.0] * (4 - len(u_par))))
+    out = (C.c_double * 3)()
+    _chk(lib().phfem_errors(nC, _p(coord), nE, _p(tetra), nF, _p(tet2face), _p(sigma), _p(kappa), C.addressof(prm),
+                            _p(U), _p(lam), u_kind, C.addressof(par), h, nq, _p(work), work.numel(),
+                            C.addressof(out), _stream()))
+    return out[0], out[1], out[2]
 
 
 def phfem_profile_enable(on):

@@ -217,6 +217,17 @@ def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG
     return dlogk, dX, st.as_dict()
 
 
+def errors(coord, tetra, conn, kappa, prm, U, lam, u_kind, u_par, h, nq=8):
+    """Error norms of (U, lambda) against the exact solution u (Section 5, Table 4's norms):
+    dict(grad2, l22, lam_h2, Y, h_norm) with Y = sqrt(grad2 + l22 / h^2), h_norm = sqrt(lam_h2).
+    Neumann faces (prm.neumann) are left out of the multiplier norm."""
+    nC, nE = coord.shape[1], tetra.shape[1]
+    work = B.workspace(B.lib().phfem_errors_workspace(nE), coord.device)
+    g2, l2, lh = B.phfem_errors(nC, coord, nE, tetra, conn["nF"], conn["tet2face"], conn["sigma"], kappa, prm, U, lam,
+                                u_kind, u_par, h, nq, work)
+    return dict(grad2=g2, l22=l2, lam_h2=lh, Y=(g2 + l2 / h ** 2) ** 0.5, h_norm=lh ** 0.5)
+
+
 def refine_levels(coord, tetra, levels, db=None):
     """Pipeline of the paper's uniform refinement: [connect edges -> refine] per level."""
     for _ in range(levels):

@@ -41,6 +41,7 @@ def test_workspace_queries():
     assert L.phfem_grad_workspace(100, 200, 0) > L.phfem_solve_workspace(100, 200, 0)
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 2) > L.phfem_refine_connected_workspace(72, 114)
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 0) == 0
+    assert L.phfem_errors_workspace(0) == 0 and L.phfem_errors_workspace(1000) >= 3 * 8 * 4
     # Kuhn cube: 6 tets, 19 edges, 18 faces -> Table-1-style counts by the recurrences
     assert B.phfem_refined_sizes(8, 6, 19, 18, 2) == (8 + 19 + 6 + 2 * 19 + 3 * 18 + 6 * 6 + 72, 864,
                                                    2 * (2 * 19 + 3 * 18 + 36) + 3 * (4 * 18 + 96) + 6 * 72,
@@ -68,3 +69,8 @@ def test_validation_errors_on_host():
     assert rc == B.EINVAL  # bad mode
     rc = L.phfem_refine(8, 16, 6, 16, 0, *([16] * 3), None, None, None, 0, None, 0, None, 16, 16, None, None, None)
     assert rc == B.EINVAL
+    par, out = (C.c_double * 4)(), (C.c_double * 3)()
+    for nq, h in ((0, 0.5), (13, 0.5), (4, 0.0)):  # rule size / mesh size checked before any GPU work
+        rc = L.phfem_errors(8, 16, 6, 16, 18, 16, 16, None, C.addressof(p), 16, 16, 4, C.addressof(par), h, nq, 16,
+                            1 << 20, C.addressof(out), None)
+        assert rc == B.EINVAL
