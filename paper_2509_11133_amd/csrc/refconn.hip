@@ -44,6 +44,24 @@ static_assert(ch(7, 0) == 9 && ch(7, 3) == 10 && ch(8, 1) == 7 && ch(11, 0) == 9
 __host__ __device__ constexpr int posv(int v, int j) {
   return ch(v, 1) == 4 + j ? 1 : (ch(v, 2) == 4 + j ? 2 : (ch(v, 3) == 4 + j ? 3 : 0));
 }
+// runtime forms of posv and eidx (one shift of a packed constant instead of a chain of
+// compares): posv_r(v, j) for corner child v < 4, eidx_r(i, j) for local vertices i != j
+__host__ __device__ constexpr uint64_t posv_pack() {
+  uint64_t r = 0;
+  for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < 6; ++j) r |= (uint64_t)posv(v, j) << (2 * (6 * v + j));
+  return r;
+}
+__device__ __forceinline__ int posv_r(int v, int j) { return (int)((posv_pack() >> (2 * (6 * v + j))) & 3ull); }
+__host__ __device__ constexpr uint64_t eidx_pack() {
+  uint64_t r = 0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) r |= (uint64_t)(i == j ? 15 : eidx(i, j)) << (4 * (4 * i + j));
+  return r;
+}
+__device__ __forceinline__ int eidx_r(int i, int j) { return (int)((eidx_pack() >> (4 * (4 * i + j))) & 15ull); }
+static_assert(((posv_pack() >> (2 * (6 * 1 + 3))) & 3) == (uint64_t)posv(1, 3), "posv pack");
+
 // local face of corner child v that lies on coarse face k (15 if none)
 __host__ __device__ constexpr int cornerface(int v, int k) { return (int)((0x12f1f2021f0f210ull >> (4 * (4 * v + k))) & 15ull); }
 static_assert(cornerface(0, 0) == 0 && cornerface(0, 2) == 2 && cornerface(1, 2) == 1 && cornerface(2, 1) == 2 &&
@@ -100,6 +118,20 @@ static_assert(fkind(0, 3) == 0 && fpartner(0, 3) == 4 * 4 + 0, "cut triangle at 
 static_assert(fkind(8, 0) == 2 && fcoarse(8, 0) == 0 && fkind(11, 0) == 2 && fcoarse(11, 0) == 3, "middles");
 static_assert(fkind(1, 1) == 1 && fcoarse(1, 1) == 2 && fkind(2, 2) == 1 && fcoarse(2, 2) == 1, "corners");
 static_assert(first3(0, false) == 4 && first3(3, false) == 5, "first (M, C)");
+
+// Element i of an array addressed as its (wave-uniform) base plus an unsigned 32-bit byte
+// offset: the hardware adds the offset to a scalar base, so no 64-bit address arithmetic is
+// spent per access.  Valid while i * sizeof(T) < 2^32 (every array indexed this way holds
+// at most 16 nE' bytes < 2^32 by the entry point's size limits; two-dimensional outputs
+// take a per-row base).
+template <class T>
+__device__ __forceinline__ T ldu(const T* p, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stu(T* p, uint32_t i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + i * (uint32_t)sizeof(T)) = v;
+}
 
 constexpr int RCT = 256;
 
@@ -172,9 +204,11 @@ __global__ __launch_bounds__(RCT) void k_rc_prep(int64_t nE, int64_t nEd, const 
   }
 }
 
-__device__ __forceinline__ int64_t rowof(int64_t nE, int64_t tt, int c) { return c == 0 ? tt : nE + 11 * tt + (c - 1); }
+// Row arithmetic is 32-bit: the entry point guarantees 6 nE' < 2^31, so rows, 6 row + j and
+// 4 row + k all fit in int32.
+__device__ __forceinline__ int rowof(int nE, int tt, int c) { return c == 0 ? tt : nE + 11 * tt + (c - 1); }
 template <int C>
-__device__ __forceinline__ int64_t rowc(int64_t nE, int64_t tt) { return C == 0 ? tt : nE + 11 * tt + (C - 1); }
+__device__ __forceinline__ int rowc(int nE, int tt) { return C == 0 ? tt : nE + 11 * tt + (C - 1); }
 // order of the rows of one tet's children: child 0 first, then 1..11
 __host__ __device__ constexpr int rord(int c) { return c == 0 ? -1 : c; }
 __device__ __forceinline__ int loc4v(const int4& v, int x) { return v.x == x ? 0 : (v.y == x ? 1 : (v.z == x ? 2 : 3)); }
@@ -183,7 +217,9 @@ __device__ __forceinline__ int loc4v(const int4& v, int x) { return v.x == x ? 0
 // so the child index is uniform across a wave and every rule above resolves at compile time
 // (one specialised code path per child, selected by a scalar branch).  A workgroup's rows
 // are rows [t0, t0 + RCW) and [nE + 11 t0, nE + 11 (t0 + RCW)): per-row outputs are staged
-// in LDS and written out as two contiguous ranges.
+// in LDS and written out as two contiguous ranges.  The lookups below are branch-free
+// (clamped indices, selects), so a lane issues all loads of one stage back to back instead
+// of waiting for each in turn.
 constexpr int RCW = 64;
 constexpr int RCB = 12 * RCW;
 constexpr int RCS = 13;  // LDS stride of one tet's 12 child slots (odd: no bank conflicts)
@@ -199,24 +235,27 @@ __device__ __forceinline__ void sfor(F&& f) {
 
 // coarse tet data of one lane
 struct CT {
-  int64_t t;
+  int t;
   int n[4], f[4], nb[4], e[6];
 };
-__device__ __forceinline__ void load_ct(const RCArgs& A, int64_t t, CT& T) {
-  const int4 a = A.T4[t], b = A.F4[t], c = A.N4[t], d = A.E8[2 * t], e = A.E8[2 * t + 1];
+__device__ __forceinline__ void load_ct(const RCArgs& A, int t, CT& T) {
+  const uint32_t u = (uint32_t)t;
+  const int4 a = ldu(A.T4, u), b = ldu(A.F4, u), c = ldu(A.N4, u), d = ldu(A.E8, 2 * u), e = ldu(A.E8, 2 * u + 1);
   T.t = t;
   T.n[0] = a.x, T.n[1] = a.y, T.n[2] = a.z, T.n[3] = a.w;
   T.f[0] = b.x, T.f[1] = b.y, T.f[2] = b.z, T.f[3] = b.w;
   T.nb[0] = c.x, T.nb[1] = c.y, T.nb[2] = c.z, T.nb[3] = c.w;
   T.e[0] = d.x, T.e[1] = d.y, T.e[2] = d.z, T.e[3] = d.w, T.e[4] = e.x, T.e[5] = e.y;
 }
+// the neighbour across coarse face k, or the tet itself (a valid address) on the boundary
+__device__ __forceinline__ int nb_or_self(const CT& T, int k) { return T.nb[k] >= 0 ? T.nb[k] : T.t; }
 
 // first occurrence (row, local edge) of local edge J of child C
 template <int C, int J>
-__device__ __forceinline__ void efirst(const RCArgs& A, const CT& T, int64_t& er, int& ej) {
+__device__ __forceinline__ void efirst(const RCArgs& A, const CT& T, int& er, int& ej) {
   constexpr int s0 = ch(C, ev0(J)), s1 = ch(C, ev1(J));
   constexpr int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
-  const int64_t nE = A.nE;
+  const int nE = (int)A.nE;
   if constexpr (hi == 10) {  // (M_j, C): inside t
     er = rowc<first3(lo - 4, false)>(nE, T.t);
     ej = first3(lo - 4, true);
@@ -224,40 +263,31 @@ __device__ __forceinline__ void efirst(const RCArgs& A, const CT& T, int64_t& er
     constexpr int j = hi - 4;
     const int e = T.e[j], v = T.n[lo];
     const int na = T.n[ev0(j)], nb = T.n[ev1(j)];
-    const int lon = na < nb ? na : nb;
-    const int mi = A.minI[2 * e + (v == lon ? 0 : 1)];
-    if (mi != INT_MAX && (mi >> 2) < nE) {
-      er = mi >> 2;  // child 0 of that tet, local edge j of (I, m_j)
-      ej = mi & 3;
-      return;
-    }
-    const int p0 = A.efp[e];
+    const bool vlo = v == (na < nb ? na : nb);
+    const int mi = ldu(A.minI, (uint32_t)(2 * e + (vlo ? 0 : 1)));
+    const int p0 = ldu(A.efp, (uint32_t)e);
+    // child 0 of the lowest tet whose vertex I is v (local edge j of (I, m_j)), else the
+    // corner child of v in the first tet of e
     const int flip = p0 & 1, p = p0 >> 1;
     const int t0 = p / 6, j0 = p - 6 * t0;
-    const int vl = ((v == lon) != (flip != 0)) ? ev0(j0) : ev1(j0);
+    const int vl = (vlo != (flip != 0)) ? ev0(j0) : ev1(j0);
     const bool ok = p0 >= 0 && t0 < nE;  // unset only for inconsistent input
-    er = ok ? rowof(nE, t0, vl) : rowc<C>(nE, T.t);
-    ej = ok ? posv(vl, j0) - 1 : J;
+    const bool use_mi = mi != INT_MAX && (mi >> 2) < nE;
+    er = use_mi ? (mi >> 2) : (ok ? rowof(nE, t0, vl) : rowc<C>(nE, T.t));
+    ej = use_mi ? (mi & 3) : (ok ? posv_r(vl, j0) - 1 : J);
   } else {  // (M_i, M_j) on a coarse face: corner child of the shared vertex, here or in the neighbour
     constexpr int i = lo - 4, j = hi - 4;
     constexpr int v = common_v(i, j), a = other_end(i, v), b = other_end(j, v);
     constexpr int k = face_with(v, a, b);
     constexpr int jr = eidx(posv(v, i), posv(v, j));
-    int64_t rr = rowc<v>(nE, T.t);
-    int jj = jr;
-    const int tn = T.nb[k];
-    if (tn >= 0) {
-      const int4 nn = A.T4[tn];
-      const int v2 = loc4v(nn, T.n[v]), a2 = loc4v(nn, T.n[a]), b2 = loc4v(nn, T.n[b]);
-      const int le2 = eidx(posv(v2, eidx(v2, a2)), posv(v2, eidx(v2, b2)));
-      const int64_t r2 = rowof(nE, tn, v2);
-      if (6 * r2 + le2 < 6 * rr + jr) {
-        rr = r2;
-        jj = le2;
-      }
-    }
-    er = rr;
-    ej = jj;
+    const int rr = rowc<v>(nE, T.t);
+    const int4 nn = ldu(A.T4, (uint32_t)(nb_or_self(T, k)));
+    const int v2 = loc4v(nn, T.n[v]), a2 = loc4v(nn, T.n[a]), b2 = loc4v(nn, T.n[b]);
+    const int le2 = eidx_r(posv_r(v2, eidx_r(v2, a2)), posv_r(v2, eidx_r(v2, b2)));
+    const int r2 = rowof(nE, nb_or_self(T, k), v2);
+    const bool there = T.nb[k] >= 0 && 6 * r2 + le2 < 6 * rr + jr;
+    er = there ? r2 : rr;
+    ej = there ? le2 : jr;
   }
 }
 
@@ -271,44 +301,39 @@ __device__ __forceinline__ bool efirst_here(const RCArgs& A, const CT& T) {
   } else if constexpr (lo >= 4 && common_v(lo - 4, hi - 4) != C) {
     return false;  // an octahedron child never holds the first (M, M) occurrence
   } else {
-    int64_t er;
-    int ej;
+    int er, ej;
     efirst<C, J>(A, T, er, ej);
-    return er == rowc<C>(A.nE, T.t) && ej == J;
+    return er == rowc<C>((int)A.nE, T.t) && ej == J;
   }
 }
 
 // other occurrence (row, local face) of local face K of child C; row -1 on the boundary
 template <int C, int K>
-__device__ __forceinline__ void fother(const RCArgs& A, const CT& T, int64_t& fr, int& fk) {
+__device__ __forceinline__ void fother(const RCArgs& A, const CT& T, int& fr, int& fk) {
   constexpr int kind = fkind(C, K);
-  const int64_t nE = A.nE;
+  const int nE = (int)A.nE;
   if constexpr (kind == 0) {
     constexpr int p = fpartner(C, K);
     fr = rowc<(p >> 2)>(nE, T.t);
     fk = p & 3;
   } else {
     constexpr int k = fcoarse(C, K);
-    const int tn = T.nb[k];
-    if (tn < 0) {
-      fr = -1;
-      fk = 0;
-      return;
-    }
-    const int k2 = loc4v(A.F4[tn], T.f[k]);
+    const int tn = nb_or_self(T, k);
+    const int k2 = loc4v(ldu(A.F4, (uint32_t)tn), T.f[k]);
     if constexpr (kind == 2) {
       fr = rowof(nE, tn, 8 + k2);
       fk = 0;
     } else {
-      const int v2 = loc4v(A.T4[tn], T.n[C]);  // corner child C holds vertex V_C
+      const int v2 = loc4v(ldu(A.T4, (uint32_t)tn), T.n[C]);  // corner child C holds vertex V_C
       fr = rowof(nE, tn, v2);
       fk = cornerface(v2, k2);
     }
+    if (T.nb[k] < 0) fr = -1, fk = 0;
   }
 }
 
 template <int C, int K>
-__device__ __forceinline__ bool fown(const RCArgs& A, const CT& T, int64_t r, int64_t& fr, int& fk) {
+__device__ __forceinline__ bool fown(const RCArgs& A, const CT& T, int r, int& fr, int& fk) {
   fother<C, K>(A, T, fr, fk);
   if constexpr (fkind(C, K) == 0)
     return rord(fpartner(C, K) >> 2) > rord(C);
@@ -322,29 +347,29 @@ __device__ __forceinline__ int sym_node(const RCArgs& A, const CT& T) {
     return T.n[S];
   } else if constexpr (S < 10) {
     const int e = T.e[S - 4];
-    return (int)(A.nC + A.eft[e] + e + 1);
+    return (int)A.nC + ldu(A.eft, (uint32_t)e) + e + 1;
   } else {
-    return (int)(A.nC + T.t + A.pre[T.t]);
+    return (int)A.nC + T.t + ldu(A.pre, (uint32_t)T.t);
   }
 }
 
 // the rows of a workgroup: LDS slot l * RCS + c of (lane l, child c) <-> global row
 struct RCBlock {
-  int64_t t0;
+  int t0;
   int nb;  // tets in this workgroup
 };
 __device__ __forceinline__ RCBlock rc_block(const RCArgs& A) {
   RCBlock B;
-  B.t0 = (int64_t)blockIdx.x * RCW;
-  const int64_t rest = A.nE - B.t0;
-  B.nb = rest < RCW ? (int)rest : RCW;
+  B.t0 = (int)blockIdx.x * RCW;
+  const int rest = (int)A.nE - B.t0;
+  B.nb = rest < RCW ? rest : RCW;
   return B;
 }
 // flush slot of thread i: row and LDS slot, or false
-__device__ __forceinline__ bool rc_flush_slot(const RCArgs& A, const RCBlock& B, int i, int64_t& row, int& slot) {
+__device__ __forceinline__ bool rc_flush_slot(const RCArgs& A, const RCBlock& B, int i, int& row, int& slot) {
   if (i < 11 * B.nb) {  // children 1..11, rows nE + 11 t0 + i
     const int l = i / 11;
-    row = A.nE + 11 * B.t0 + i;
+    row = (int)A.nE + 11 * B.t0 + i;
     slot = l * RCS + 1 + (i - 11 * l);
     return true;
   }
@@ -371,7 +396,7 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
     sfor<12>([&](auto Cc) {
       constexpr int C = decltype(Cc)::value;
       if (c != C) return;
-      const int64_t r = rowc<C>(A.nE, T.t);
+      const int r = rowc<C>((int)A.nE, T.t);
       int me = 0, mf = 0;
       sfor<6>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
@@ -379,8 +404,7 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
       });
       sfor<4>([&](auto Kc) {
         constexpr int K = decltype(Kc)::value;
-        int64_t fr;
-        int fk;
+        int fr, fk;
         if (fown<C, K>(A, T, r, fr, fk)) mf |= 1 << K;
       });
       sE[lane * RCS + C] = (uint32_t)me;
@@ -389,8 +413,7 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
   }
   __syncthreads();
   // rows in flush order: threads 0 .. 11 RCW - 1 the other rows, the last RCW the child-0 rows
-  int64_t row;
-  int slot;
+  int row, slot;
   const bool has = rc_flush_slot(A, B, threadIdx.x, row, slot);
   const uint32_t me = has ? sE[slot] : 0u, mf = has ? sF[slot] : 0u;
   const bool first = threadIdx.x >= 11 * RCW;
@@ -400,8 +423,8 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
   const uint32_t p1 = block_excl_scan<RCB / 64>(first ? pk : 0u, lw, agg1);
   if (has) {
     const uint32_t p = first ? p1 : p2;
-    A.recE[row] = ((p & 0xffffu) << 6) | me;
-    A.recF[row] = ((p >> 16) << 4) | mf;
+    stu(A.recE, (uint32_t)row, ((p & 0xffffu) << 6) | me);
+    stu(A.recF, (uint32_t)row, ((p >> 16) << 4) | mf);
   }
   if (threadIdx.x == 0) {
     const int64_t b = blockIdx.x, n = A.ntiles;
@@ -413,21 +436,24 @@ __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
 }
 
 // absolute prefix of a row's record: its workgroup range's offset + the in-range prefix
-__device__ __forceinline__ int64_t row_tile(int64_t nE, int64_t row) {
-  return (row < nE ? row : (row - nE) / 11) / RCW;
+__device__ __forceinline__ int row_tile(int nE, int row) {
+  return (row < nE ? row : (int)((uint32_t)(row - nE) / 11u)) / RCW;
 }
-__device__ __forceinline__ uint32_t pre_e(const RCArgs& A, int64_t row, uint32_t rec) {
-  return A.tpre[(row < A.nE ? 0 : 1) * A.ntiles + row_tile(A.nE, row)] + (rec >> 6);
+__device__ __forceinline__ uint32_t pre_e(const RCArgs& A, int row, uint32_t rec) {
+  const int nE = (int)A.nE;
+  return ldu(A.tpre, (uint32_t)((row < nE ? 0 : 1) * (int)A.ntiles + row_tile(nE, row))) + (rec >> 6);
 }
-__device__ __forceinline__ uint32_t pre_f(const RCArgs& A, int64_t row, uint32_t rec) {
-  return A.tpre[(row < A.nE ? 2 : 3) * A.ntiles + row_tile(A.nE, row)] + (rec >> 4);
+__device__ __forceinline__ uint32_t pre_f(const RCArgs& A, int row, uint32_t rec) {
+  const int nE = (int)A.nE;
+  return ldu(A.tpre, (uint32_t)((row < nE ? 2 : 3) * (int)A.ntiles + row_tile(nE, row))) + (rec >> 4);
 }
 
 // pass 2: ids of the refined edges and faces of every row, and all outputs.  Phase 1 stages
 // the per-row outputs in LDS and writes them as two contiguous row ranges; phase 2 reuses
 // the LDS for the records of the edges and faces first seen in the workgroup's rows, whose
 // ids form one contiguous range per row range, and writes those out contiguously too.
-constexpr int RCO = 16;  // staged words per row: pre, 6 edges, 4 faces, 4 neighbours, 4 packed signs
+constexpr int RCO = 20;  // staged words per row: pre, 6 edges, 4 faces, 4 neighbours, 4 packed signs,
+                         // and (not written out) the node ids of the row's 4 vertices
 constexpr int RCL = RCO * RCW * RCS;  // LDS words
 // phase-2 capacities (entities per row range): child-0 rows exactly (<= 6 edges, 4 faces
 // each), the other rows about 1.2 edges and 2 faces per row; overflow goes out directly
@@ -437,98 +463,117 @@ static_assert(CF2 >= 2 * 11 * RCW + 64, "room for the typical face count of a wo
 constexpr int OE1 = 0, OF1 = OE1 + 3 * CE1, OE2 = OF1 + 5 * CF1, OF2 = OE2 + 3 * CE2;  // SoA blocks
 
 struct RCRange {  // one row range's first-seen edges and faces: [e0, e0 + ne), [f0, f0 + nf)
-  int64_t e0, f0;
+  int e0, f0;      // < nEd' < 2^26, < nF' < 2^28
   int ne, nf;
 };
 
-__global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
+__global__ __launch_bounds__(RCB) __attribute__((amdgpu_waves_per_eu(6))) void k_rc_pass2(RCArgs A) {
   __shared__ int32_t sW[RCL];
   __shared__ RCRange sR[2];
   const RCBlock B = rc_block(A);
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t nE = A.nE, nEd2 = A.nEd2, nF2 = A.nF2;
+  const int nE = (int)A.nE;
+  const int64_t nEd2 = A.nEd2, nF2 = A.nF2;
   if (threadIdx.x < 2) {  // ranges from the prefix records (exact for consistent input)
     const bool r2 = threadIdx.x == 1;
-    const int64_t lo = r2 ? nE + 11 * B.t0 : B.t0;
-    const int64_t hi = r2 ? nE + 11 * (B.t0 + B.nb) : B.t0 + B.nb;  // row after the range
+    const int lo = r2 ? nE + 11 * B.t0 : B.t0;
+    const int hi = r2 ? nE + 11 * (B.t0 + B.nb) : B.t0 + B.nb;  // row after the range
     const bool last = r2 && hi == A.nE2;
-    const int64_t e0 = pre_e(A, lo, A.recE[lo]), f0 = pre_f(A, lo, A.recF[lo]);
-    const int64_t e1 = last ? nEd2 : (int64_t)pre_e(A, hi, A.recE[hi]);
-    const int64_t f1 = last ? nF2 : (int64_t)pre_f(A, hi, A.recF[hi]);
+    const int64_t e0 = pre_e(A, lo, ldu(A.recE, (uint32_t)lo)), f0 = pre_f(A, lo, ldu(A.recF, (uint32_t)lo));
+    const int64_t e1 = last ? nEd2 : (int64_t)pre_e(A, hi, ldu(A.recE, (uint32_t)hi));
+    const int64_t f1 = last ? nF2 : (int64_t)pre_f(A, hi, ldu(A.recF, (uint32_t)hi));
     RCRange R;
-    R.e0 = e0;
-    R.f0 = f0;
+    R.e0 = (int)e0;
+    R.f0 = (int)f0;
     R.ne = (int)(e1 > e0 ? e1 - e0 : 0);
     R.nf = (int)(f1 > f0 ? f1 - f0 : 0);
     sR[threadIdx.x] = R;
   }
-  CT T;
-  int32_t fnb[4] = {-1, -1, -1, -1};  // f2t slot of the other side, per owned local face
+  // kept in registers from phase 1 to phase 2: this row's masks and the f2t slot across each
+  // owned face (its edge and face ids and vertex node ids are read back from LDS)
+  int me = 0, mf = 0, r = 0;
+  int fnb[4];
   if (lane < B.nb) {
+    CT T;
     load_ct(A, B.t0 + lane, T);
     sfor<12>([&](auto Cc) {
       constexpr int C = decltype(Cc)::value;
       if (c != C) return;
-      const int64_t r = rowc<C>(nE, T.t);
-      int32_t* w = sW + lane * RCS + C;
-      const uint32_t oe = A.recE[r], of = A.recF[r];
-      const int me = oe & 63, mf = of & 15;
-      const uint32_t pe = pre_e(A, r, oe), pf = pre_f(A, r, of);
-      w[0] = (int32_t)pe;
+      r = rowc<C>(nE, T.t);
+      // stage 1: this row's records, every first occurrence / other side, the vertex ids
+      const uint32_t oe = ldu(A.recE, (uint32_t)r), of = ldu(A.recF, (uint32_t)r);
+      int er[6], ej[6], fr[4], fk[4];
       sfor<6>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
-        int32_t id;
-        if ((me >> J) & 1) {
-          id = (int32_t)(pe + __popc(me & ((1 << J) - 1)));
-        } else {
-          int64_t er;
-          int ej;
-          efirst<C, J>(A, T, er, ej);
-          const uint32_t o = A.recE[er];
-          id = (int32_t)(pre_e(A, er, o) + __popc((o & 63) & ((1u << ej) - 1)));
-        }
-        w[(1 + J) * RCW * RCS] = id;
+        efirst<C, J>(A, T, er[J], ej[J]);
+      });
+      sfor<4>([&](auto Kc) {
+        constexpr int K = decltype(Kc)::value;
+        fother<C, K>(A, T, fr[K], fk[K]);
+      });
+      int32_t* w = sW + lane * RCS + C;
+      sfor<4>([&](auto Pc) {
+        constexpr int Q = decltype(Pc)::value;
+        w[(16 + Q) * RCW * RCS] = sym_node<ch(C, Q)>(A, T);
+      });
+      // stage 2: the records of those rows (a first-seen edge's row is this row)
+      uint32_t oE[6], oF[4];
+      sfor<6>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        oE[J] = ldu(A.recE, (uint32_t)(er[J]));
+      });
+      sfor<4>([&](auto Kc) {
+        constexpr int K = decltype(Kc)::value;
+        oF[K] = ldu(A.recF, (uint32_t)(fr[K] >= 0 ? fr[K] : r));
+      });
+      // stage 3: ids = workgroup offset + in-workgroup prefix + rank inside the row
+      me = (int)(oe & 63);
+      mf = (int)(of & 15);
+      const uint32_t pf = pre_f(A, r, of);
+      w[0] = (int32_t)pre_e(A, r, oe);
+      sfor<6>([&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        w[(1 + J) * RCW * RCS] = (int)(pre_e(A, er[J], oE[J]) + __popc((oE[J] & 63) & ((1u << ej[J]) - 1)));
       });
       uint32_t sg = 0;
       sfor<4>([&](auto Kc) {
         constexpr int K = decltype(Kc)::value;
-        int64_t fr;
-        int fk;
-        fother<C, K>(A, T, fr, fk);
         const bool own = (mf >> K) & 1;
-        int32_t id;
-        if (own) {
-          id = (int32_t)(pf + __popc(mf & ((1 << K) - 1)));
-          fnb[K] = fr < 0 ? -1 : (int32_t)(4 * fr + fk);
-        } else if (fr >= 0) {
-          const uint32_t o = A.recF[fr];
-          id = (int32_t)(pre_f(A, fr, o) + __popc((o & 15) & ((1u << fk) - 1)));
-        } else {
-          id = -1;  // inconsistent input only
-        }
-        w[(7 + K) * RCW * RCS] = id;
-        w[(11 + K) * RCW * RCS] = fr < 0 ? -1 : (int32_t)fr;
+        const int idn = (int)(pre_f(A, fr[K], oF[K]) + __popc((oF[K] & 15) & ((1u << fk[K]) - 1)));
+        fnb[K] = fr[K] < 0 ? -1 : 4 * fr[K] + fk[K];
+        w[(7 + K) * RCW * RCS] = own ? (int)(pf + __popc(mf & ((1 << K) - 1))) : (fr[K] >= 0 ? idn : -1);  // -1: bad input
+        w[(11 + K) * RCW * RCS] = fr[K] < 0 ? -1 : fr[K];
         sg |= (own ? 0x01u : 0xffu) << (8 * K);
       });
       w[15 * RCW * RCS] = (int32_t)sg;
     });
   }
   __syncthreads();
-  int64_t row;
-  int slot;
+  int row, slot;
   if (rc_flush_slot(A, B, threadIdx.x, row, slot)) {
     const int64_t n2 = A.nE2;
     const int32_t* v = sW + slot;
-    A.pre2[row] = v[0];
+    const uint32_t u = (uint32_t)row;
+    stu(A.pre2, u, v[0]);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) A.t2e2[j * n2 + row] = v[(1 + j) * RCW * RCS];
+    for (int j = 0; j < 6; ++j) stu(A.t2e2 + j * n2, u, v[(1 + j) * RCW * RCS]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      A.t2f2[k * n2 + row] = v[(7 + k) * RCW * RCS];
-      A.nbr2[k * n2 + row] = v[(11 + k) * RCW * RCS];
-      A.sig2[k * n2 + row] = (int8_t)(((uint32_t)v[15 * RCW * RCS] >> (8 * k)) & 0xffu);
+      stu(A.t2f2 + k * n2, u, v[(7 + k) * RCW * RCS]);
+      stu(A.nbr2 + k * n2, u, v[(11 + k) * RCW * RCS]);
+      stu(A.sig2 + k * n2, u, (int8_t)(((uint32_t)v[15 * RCW * RCS] >> (8 * k)) & 0xffu));
     }
+  }
+  int eid[6], fid[4], nd[4];
+  if (lane < B.nb) {
+    const int32_t* w = sW + lane * RCS + c;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) eid[j] = w[(1 + j) * RCW * RCS];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fid[k] = w[(7 + k) * RCW * RCS];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nd[q] = w[(16 + q) * RCW * RCS];
   }
   __syncthreads();
   // phase 2: records of the edges and faces first seen in these rows
@@ -536,49 +581,44 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
     sfor<12>([&](auto Cc) {
       constexpr int C = decltype(Cc)::value;
       if (c != C) return;
-      const int64_t r = rowc<C>(nE, T.t);
       const RCRange R = sR[C == 0 ? 0 : 1];
       constexpr int oe_ = C == 0 ? OE1 : OE2, ce = C == 0 ? CE1 : CE2;
       constexpr int of_ = C == 0 ? OF1 : OF2, cf = C == 0 ? CF1 : CF2;
-      const uint32_t oe = A.recE[r], of = A.recF[r];
-      const int me = oe & 63, mf = of & 15;
-      const uint32_t pe = pre_e(A, r, oe), pf = pre_f(A, r, of);
       sfor<6>([&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         if (!((me >> J) & 1)) return;
-        const int64_t id = pe + __popc(me & ((1 << J) - 1));
-        const int na = sym_node<ch(C, ev0(J))>(A, T), nb = sym_node<ch(C, ev1(J))>(A, T);
+        const int id = eid[J];
+        const int na = nd[ev0(J)], nb = nd[ev1(J)];
         const int lo = na < nb ? na : nb, hi = na < nb ? nb : na;
-        const int64_t li = id - R.e0;
+        const int li = id - R.e0;
         if (li >= 0 && li < ce && li < R.ne) {
           sW[oe_ + li] = lo;
           sW[oe_ + ce + li] = hi;
-          sW[oe_ + 2 * ce + li] = (int32_t)r;
-        } else if (id < nEd2) {
-          A.edges2[id] = lo;
-          A.edges2[nEd2 + id] = hi;
-          A.eft2[id] = (int32_t)r;
+          sW[oe_ + 2 * ce + li] = r;
+        } else if (id >= 0 && id < nEd2) {
+          stu(A.edges2, (uint32_t)id, lo);
+          stu(A.edges2 + nEd2, (uint32_t)id, hi);
+          stu(A.eft2, (uint32_t)id, r);
         }
       });
       sfor<4>([&](auto Kc) {
         constexpr int K = decltype(Kc)::value;
         if (!((mf >> K) & 1)) return;
-        const int64_t id = pf + __popc(mf & ((1 << K) - 1));
-        const int n0 = sym_node<ch(C, fv(K, 0))>(A, T), n1 = sym_node<ch(C, fv(K, 1))>(A, T),
-                  n2 = sym_node<ch(C, fv(K, 2))>(A, T);
-        const int64_t li = id - R.f0;
+        const int id = fid[K];
+        const int n0 = nd[fv(K, 0)], n1 = nd[fv(K, 1)], n2 = nd[fv(K, 2)];
+        const int li = id - R.f0;
         if (li >= 0 && li < cf && li < R.nf) {
-          sW[of_ + li] = (int32_t)(4 * r + K);
+          sW[of_ + li] = 4 * r + K;
           sW[of_ + cf + li] = fnb[K];
           sW[of_ + 2 * cf + li] = n0;
           sW[of_ + 3 * cf + li] = n1;
           sW[of_ + 4 * cf + li] = n2;
-        } else if (id < nF2) {
-          A.f2t2[id] = (int32_t)(4 * r + K);
-          A.f2t2[nF2 + id] = fnb[K];
-          A.faces2[id] = n0;
-          A.faces2[nF2 + id] = n1;
-          A.faces2[2 * nF2 + id] = n2;
+        } else if (id >= 0 && id < nF2) {
+          stu(A.f2t2, (uint32_t)id, 4 * r + K);
+          stu(A.f2t2 + nF2, (uint32_t)id, fnb[K]);
+          stu(A.faces2, (uint32_t)id, n0);
+          stu(A.faces2 + nF2, (uint32_t)id, n1);
+          stu(A.faces2 + 2 * nF2, (uint32_t)id, n2);
         }
       });
     });
@@ -592,19 +632,20 @@ __global__ __launch_bounds__(RCB) void k_rc_pass2(RCArgs A) {
     int ne = R.ne < ce ? R.ne : ce, nf = R.nf < cf ? R.nf : cf;
     if (R.e0 + ne > nEd2) ne = R.e0 < nEd2 ? (int)(nEd2 - R.e0) : 0;  // inconsistent input only
     if (R.f0 + nf > nF2) nf = R.f0 < nF2 ? (int)(nF2 - R.f0) : 0;
+    int32_t *ed0 = A.edges2 + R.e0, *ed1 = A.edges2 + nEd2 + R.e0, *ef = A.eft2 + R.e0;
     for (int i = threadIdx.x; i < ne; i += RCB) {
-      const int64_t id = R.e0 + i;
-      A.edges2[id] = sW[oe_ + i];
-      A.edges2[nEd2 + id] = sW[oe_ + ce + i];
-      A.eft2[id] = sW[oe_ + 2 * ce + i];
+      stu(ed0, (uint32_t)i, sW[oe_ + i]);
+      stu(ed1, (uint32_t)i, sW[oe_ + ce + i]);
+      stu(ef, (uint32_t)i, sW[oe_ + 2 * ce + i]);
     }
+    int32_t *ft0 = A.f2t2 + R.f0, *ft1 = A.f2t2 + nF2 + R.f0, *fa0 = A.faces2 + R.f0, *fa1 = A.faces2 + nF2 + R.f0,
+            *fa2 = A.faces2 + 2 * nF2 + R.f0;
     for (int i = threadIdx.x; i < nf; i += RCB) {
-      const int64_t id = R.f0 + i;
-      A.f2t2[id] = sW[of_ + i];
-      A.f2t2[nF2 + id] = sW[of_ + cf + i];
-      A.faces2[id] = sW[of_ + 2 * cf + i];
-      A.faces2[nF2 + id] = sW[of_ + 3 * cf + i];
-      A.faces2[2 * nF2 + id] = sW[of_ + 4 * cf + i];
+      stu(ft0, (uint32_t)i, sW[of_ + i]);
+      stu(ft1, (uint32_t)i, sW[of_ + cf + i]);
+      stu(fa0, (uint32_t)i, sW[of_ + 2 * cf + i]);
+      stu(fa1, (uint32_t)i, sW[of_ + 3 * cf + i]);
+      stu(fa2, (uint32_t)i, sW[of_ + 4 * cf + i]);
     }
   }
 }
