@@ -217,6 +217,42 @@ def solve_block(torch, P, B, M, Ls):
     return out
 
 
+def reassembly_block(torch, P, B, M, X0d, T0d, L, reps=5, nk=4):
+    """Pattern reuse and batched coefficients on the final mesh (mixed precision): a full
+    condense (pattern + values), values-only re-assembly of one lognormal kappa field, and a
+    values-only batch of nk fields; ms per call (HIP events, mean of reps) and tets/s per field."""
+    X, T, conn = P.refine_connected_levels(X0d, T0d, L)
+    nE = T.shape[1]
+    K = torch.tensor(M.lognormal_kappa_fields(nE, nk, 1.0), device=X.device)
+    prm = P.params(c=1.0, kappa=1.0, f=(B.FUN_SIN3, (M.SIN3_AMPLITUDE,)), precision=B.MIXED)
+    first = P.condense(X, T, conn, K[0].contiguous(), prm)
+    pat = (first["rowptr"], first["col"])
+    k1 = K[:1].contiguous()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        del out
+        return e0.elapsed_time(e1) / reps
+
+    full = timed(lambda: P.condense(X, T, conn, K[0].contiguous(), prm))
+    vals = timed(lambda: P.condense_batch(X, T, conn, k1, prm, pattern=pat))
+    batch = timed(lambda: P.condense_batch(X, T, conn, K, prm, pattern=pat))
+    out = {"workload": f"Kuhn cube, {L} levels ({nE} tets), mixed precision, lognormal kappa (sigma 1)",
+           "condense_ms": round(full, 4), "values_only_ms": round(vals, 4), f"batch{nk}_values_only_ms": round(batch, 4),
+           "condense_tets_per_s": round(nE / (full * 1e-3), 1),
+           "values_only_tets_per_s": round(nE / (vals * 1e-3), 1),
+           f"batch{nk}_tets_per_s_per_field": round(nk * nE / (batch * 1e-3), 1)}
+    log("reassembly", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +265,7 @@ def main():
     ap.add_argument("--cpu-levels", type=int, default=5)
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (per-kernel HIP events)")
     ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
+    ap.add_argument("--no-reassembly", action="store_true", help="skip the pattern-reuse / batched-kappa timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -319,6 +356,9 @@ def main():
                                        for k, v in sorted(mixed["kern"].items(), key=lambda kv: -kv[1]["ms"])}
         line["fp64"]["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
                                                for k, v in sorted(fp64["kern"].items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_reassembly:
+        line["reassembly"] = reassembly_block(torch, P, B, M, X0d, T0d, L)
+        torch.cuda.empty_cache()
     if not args.no_solve:
         line["solve"] = solve_block(torch, P, B, M, args.solve_levels)
     if not args.no_cpu:

@@ -249,6 +249,27 @@ int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* t
                    size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag, double* rhs,
                    phfem_stream_t stream);
 
+/* Re-assembly with a reused pattern and batched coefficient fields (for optimisation loops
+ * that change kappa on a fixed mesh; the pattern of S+ depends on the connectivity alone,
+ * the assembly step of Algorithm 1, Listing 8).  The face systems of nk >= 1 fields
+ * kappa[nk][nE] (kappa may be NULL only for nk = 1: params.kappa_const) in one call:
+ *   val[nk][6 nF], diag[nk][nF], rhs[nk][nF] (float64, the layout of phfem_condense per field).
+ * rowptr[nF+1] and col[6 nF] are written when both are given and left untouched when both are
+ * NULL (values-only re-assembly: the pattern phfem_condense wrote for the same connectivity
+ * stays valid; it saves the 28 B/face of col and row pointers).  The coordinate copy is built
+ * once per call and the fields are condensed in turn (measured faster than one fused pass,
+ * whose per-field registers cost occupancy); field j's arrays equal phfem_condense's with
+ * kappa + j nE, bit for bit.  Workspace: phfem_condense_batch_workspace (one field's slot
+ * records, independent of nk).
+ * Errors: EINVAL (also for only one of rowptr / col), ESINGULAR, EWORKSPACE.  Does not
+ * synchronize. */
+size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision, int32_t nk);
+int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                         const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
+                         int32_t nk, const double* kappa, const phfem_params* p, void* work, size_t work_bytes,
+                         int32_t* rowptr, int32_t* col, double* val, double* diag, double* rhs,
+                         phfem_stream_t stream);
+
 /* ---------------------------------------------------------------- solve (a8-a9) ------ */
 enum { PHFEM_SOLVE_FP64_PCG = 0, PHFEM_SOLVE_FP32_PCG_FP64_IR = 1 };
 

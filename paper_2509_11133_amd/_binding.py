@@ -28,7 +28,7 @@ EXPORTS = [
     "phfem_grad_workspace", "phfem_grad", "phfem_profile_enable", "phfem_profile_reset", "phfem_profile_query",
     "phfem_profile_names", "phfem_refine_connected_workspace", "phfem_refine_connected", "phfem_refined_sizes",
     "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels", "phfem_errors_workspace",
-    "phfem_errors",
+    "phfem_errors", "phfem_condense_batch_workspace", "phfem_condense_batch",
 ]
 
 
@@ -96,7 +96,8 @@ def lib():
         L.phfem_last_error.restype = C.c_char_p
         for n in ("phfem_connect_workspace", "phfem_condense_workspace", "phfem_solve_workspace",
                   "phfem_grad_workspace", "phfem_refine_connected_workspace",
-                  "phfem_refine_connected_levels_workspace", "phfem_errors_workspace"):
+                  "phfem_refine_connected_levels_workspace", "phfem_errors_workspace",
+                  "phfem_condense_batch_workspace"):
             getattr(L, n).restype = SZ
         L.phfem_connect_workspace.argtypes = [I64, I64, I32]
         L.phfem_condense_workspace.argtypes = [I64, I64, I64, I32]
@@ -117,6 +118,8 @@ def lib():
         L.phfem_grad.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 7 + [VP] * 4 + [VP] * 3
                                  + [I32, DBL, DBL, I32, VP, SZ] + [VP] * 3 + [VP])
         L.phfem_errors_workspace.argtypes = [I64]
+        L.phfem_condense_batch_workspace.argtypes = [I64, I64, I64, I32, I32]
+        L.phfem_condense_batch.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [I32, VP, VP, VP, SZ] + [VP] * 5 + [VP]
         L.phfem_errors.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, SZ, VP, VP]
         L.phfem_profile_enable.argtypes = [I32]
         L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
@@ -204,6 +207,13 @@ def phfem_condense(nC, coord, nE, tetra, nF, faces, tet2face, sigma, nbr, face2t
     _chk(lib().phfem_condense(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(nbr),
                               _p(face2tet), _p(kappa), C.addressof(prm), _p(work), work.numel(), _p(rowptr), _p(col),
                               _p(val), _p(diag), _p(rhs), _stream()))
+
+
+def phfem_condense_batch(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, nk, kappa, prm, work, rowptr,
+                         col, val, diag, rhs):
+    _chk(lib().phfem_condense_batch(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma),
+                                    _p(face2tet), nk, _p(kappa), C.addressof(prm), _p(work), work.numel(), _p(rowptr),
+                                    _p(col), _p(val), _p(diag), _p(rhs), _stream()))
 
 
 def phfem_solve(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, kappa, prm, rowptr, col, val, diag, rhs,

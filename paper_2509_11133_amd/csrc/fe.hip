@@ -328,6 +328,52 @@ struct SlotRec {  // row k of one tet's element Schur block S(T) and (C A^-1 B)_
 };
 static_assert(sizeof(SlotRec<float>) == 32 && sizeof(SlotRec<double>) == 56, "packed slot records");
 
+// the four slot records of one tet for one coefficient value, into the thread's LDS slots
+template <class R>
+__device__ __forceinline__ void elem_records(const double (&x)[4][3], const int (&sig)[4], const int (&F)[4],
+                                             double kap, const DevParams& P, int64_t nF, uint2* lrec) {
+  constexpr int W = sizeof(SlotRec<R>) / 8;
+  Elem<R> E;
+  E.init(x, kap, P.c, sig);
+  R B[4], r[4], su[10];
+  load_vec<R>(x, E.vol, P, B);
+  bool neu[4] = {false, false, false, false};
+  double gN[4] = {0, 0, 0, 0};
+  if (P.nm) {  // Neumann faces: LN in the load; their rows become lambda_F = g
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      neu[k] = (uint32_t)F[k] < (uint64_t)nF && P.nm[F[k]];
+      if (!neu[k]) continue;
+      gN[k] = neumann_flux(E, x, k, kap, P);
+      const R ln = E.d[k] * (R)gN[k] * (R)(1.0 / 3.0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i != opp(k)) B[i] += ln;
+    }
+  }
+  E.CAinv(B, r);
+  E.Supper(su);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    union {
+      SlotRec<R> rec;
+      uint2 w[W];
+    } u;
+    u.rec.d = neu[k] ? (R)1 : su[uidx(k, k)];
+    u.rec.r = neu[k] ? (R)(-gN[k]) : r[k];
+    int n = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (l == k) continue;
+      u.rec.o[n] = neu[k] ? (R)0 : su[uidx(k, l)];
+      u.rec.c[n] = neu[l] ? (int32_t)((uint32_t)F[l] | 0x80000000u) : F[l];  // a Neumann column: no coupling
+      ++n;
+    }
+#pragma unroll
+    for (int m = 0; m < W; ++m) lrec[k * W + m] = u.w[m];
+  }
+}
+
 template <class R>
 __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __restrict__ XA, int64_t nE,
                                                  const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
@@ -348,46 +394,7 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __re
     }
     double x[4][3];
     gather_xa(XA, v, x);
-    const double kap = kappa ? kappa[t] : P.kc;
-    Elem<R> E;
-    E.init(x, kap, P.c, sig);
-    R B[4], r[4], su[10];
-    load_vec<R>(x, E.vol, P, B);
-    bool neu[4] = {false, false, false, false};
-    double gN[4] = {0, 0, 0, 0};
-    if (P.nm) {  // Neumann faces: LN in the load; their rows become lambda_F = g
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        neu[k] = (uint32_t)F[k] < (uint64_t)nF && P.nm[F[k]];
-        if (!neu[k]) continue;
-        gN[k] = neumann_flux(E, x, k, kap, P);
-        const R ln = E.d[k] * (R)gN[k] * (R)(1.0 / 3.0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i != opp(k)) B[i] += ln;
-      }
-    }
-    E.CAinv(B, r);
-    E.Supper(su);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      union {
-        SlotRec<R> rec;
-        uint2 w[W];
-      } u;
-      u.rec.d = neu[k] ? (R)1 : su[uidx(k, k)];
-      u.rec.r = neu[k] ? (R)(-gN[k]) : r[k];
-      int n = 0;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        if (l == k) continue;
-        u.rec.o[n] = neu[k] ? (R)0 : su[uidx(k, l)];
-        u.rec.c[n] = neu[l] ? (int32_t)((uint32_t)F[l] | 0x80000000u) : F[l];  // a Neumann column: no coupling
-        ++n;
-      }
-#pragma unroll
-      for (int m = 0; m < W; ++m) lrec[(4 * threadIdx.x + k) * W + m] = u.w[m];
-    }
+    elem_records<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, lrec + 4 * threadIdx.x * W);
   }
   __syncthreads();
   const int64_t nb = nE - t0 < FT ? nE - t0 : FT;
@@ -395,10 +402,79 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __re
   for (int i = threadIdx.x; i < 4 * nb * W; i += FT) out[i] = lrec[i];
 }
 
-// Every face row has 6 off-diagonal slots (rowptr[F] = 6 F): an interior face fills them
-// with the 6 faces its two tets share it with, ascending; a boundary face (about 2 nF^(2/3)
-// of nF) has 3, ascending, followed by 3 explicit zeros in column F.  A workgroup's rows
-// are one contiguous range: assembled in LDS, written out with coalesced stores.
+// One face's row from its owner's slot q0 and its neighbour's slot q1 (-1 on the boundary):
+// the 6 (column, value) pairs unsorted (boundary: 3 pads INT_MAX / 0), diagonal, and the rhs
+// b_D - r_owner - r_neighbour.
+template <class R>
+__device__ __forceinline__ void face_row(const SlotRec<R>* __restrict__ recs, int q0, int q1, double bD,
+                                         const DevParams& P, int (&cf)[6], double (&cv)[6], double& dg,
+                                         double& rh) {
+  const SlotRec<R> a = recs[q0];  // owner's slot: row k of its element block
+  dg = (double)a.d;
+  rh = bD - (double)a.r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cf[i] = a.c[i];
+    cv[i] = (double)a.o[i];
+  }
+  if (q1 >= 0) {
+    const SlotRec<R> bq = recs[q1];  // neighbour's slot
+    dg += (double)bq.d;
+    rh -= (double)bq.r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cf[3 + i] = bq.c[i];
+      cv[3 + i] = (double)bq.o[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 3; i < 6; ++i) {
+      cf[i] = INT_MAX;  // sorts last; written as column F with value 0
+      cv[i] = 0.0;
+    }
+  }
+  if (P.nm) {  // columns of Neumann faces carry no coupling
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (cf[i] != INT_MAX && (cf[i] & 0x80000000)) {
+        cf[i] &= 0x7fffffff;
+        cv[i] = 0.0;
+      }
+  }
+}
+
+// b_D = |F| u_D(centroid) of a Dirichlet boundary face (0 elsewhere)
+__device__ __forceinline__ double face_bD(int64_t nF, int64_t nC, const double* __restrict__ X,
+                                          const int32_t* __restrict__ faces, const DevParams& P, int64_t f, int q1) {
+  if (q1 >= 0 || P.uk == PHFEM_FUN_ZERO || (P.nm && P.nm[f])) return 0.0;
+  double xx[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    int vv = faces[m * nF + f];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) xx[m][e] = X[e * nC + vv];
+  }
+  double u0 = xx[2][0] - xx[0][0], u1 = xx[2][1] - xx[0][1], u2 = xx[2][2] - xx[0][2];
+  double s0 = xx[1][0] - xx[0][0], s1 = xx[1][1] - xx[0][1], s2 = xx[1][2] - xx[0][2];
+  double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
+  double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+  return area * fun_at<double>(P.uk, P.up, (xx[0][0] + xx[1][0] + xx[2][0]) / 3.0,
+                               (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
+}
+
+// rank of each of the 6 columns (ties by position; pads last)
+__device__ __forceinline__ void col_ranks(const int (&cf)[6], int (&rk)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    int rank = 0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) rank += (cf[m] < cf[i] || (cf[m] == cf[i] && m < i)) ? 1 : 0;
+    rk[i] = rank;
+  }
+}
+
+// rowptr and col are written only when given (null: the pattern an earlier call wrote for the
+// same connectivity is reused).
 template <class R>
 __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const double* __restrict__ X,
                                                   const int32_t* __restrict__ faces,
@@ -411,79 +487,34 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
   const int64_t f0 = (int64_t)blockIdx.x * FT;
   const int64_t f = f0 + threadIdx.x;
   const int nb = nF - f0 < FT ? (int)(nF - f0) : FT;
+  const int base = 6 * (int)(f - f0);
   if (f < nF) {
     const int q0 = face2tet[f], q1 = face2tet[nF + f];
-    const bool interior = q1 >= 0;
-    int cf[6];
-    double cv[6];
-    double dg = 0.0, rh = 0.0;
-    if (!interior && P.uk != PHFEM_FUN_ZERO && !(P.nm && P.nm[f])) {  // b_D = |F| u_D(centroid), Dirichlet
-      double xx[3][3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        int vv = faces[m * nF + f];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) xx[m][e] = X[e * nC + vv];
-      }
-      double u0 = xx[2][0] - xx[0][0], u1 = xx[2][1] - xx[0][1], u2 = xx[2][2] - xx[0][2];
-      double s0 = xx[1][0] - xx[0][0], s1 = xx[1][1] - xx[0][1], s2 = xx[1][2] - xx[0][2];
-      double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
-      double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-      rh = area * fun_at<double>(P.uk, P.up, (xx[0][0] + xx[1][0] + xx[2][0]) / 3.0,
-                                 (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
-    }
-    {
-      const SlotRec<R> a = recs[q0];  // owner's slot: row k of its element block
-      dg = (double)a.d;
-      rh -= (double)a.r;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        cf[i] = a.c[i];
-        cv[i] = (double)a.o[i];
-      }
-    }
-    if (interior) {
-      const SlotRec<R> bq = recs[q1];  // neighbour's slot
-      dg += (double)bq.d;
-      rh -= (double)bq.r;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        cf[3 + i] = bq.c[i];
-        cv[3 + i] = (double)bq.o[i];
-      }
-    } else {
-#pragma unroll
-      for (int i = 3; i < 6; ++i) {
-        cf[i] = INT_MAX;  // sorts last; written as column F with value 0
-        cv[i] = 0.0;
-      }
-    }
-    if (P.nm) {  // columns of Neumann faces carry no coupling
-#pragma unroll
-      for (int i = 0; i < 6; ++i)
-        if (cf[i] != INT_MAX && (cf[i] & 0x80000000)) {
-          cf[i] &= 0x7fffffff;
-          cv[i] = 0.0;
-        }
-    }
-    const int base = 6 * (int)(f - f0);
+    const double bD = face_bD(nF, nC, X, faces, P, f, q1);
+    int cf[6], rk[6];
+    double cv[6], dg, rh;
+    face_row<R>(recs, q0, q1, bD, P, cf, cv, dg, rh);
+    col_ranks(cf, rk);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      int rank = 0;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) rank += (cf[j] < cf[i] || (cf[j] == cf[i] && j < i)) ? 1 : 0;
-      lcol[base + rank] = cf[i] == INT_MAX ? (int32_t)f : cf[i];
-      lval[base + rank] = cv[i];
+      lcol[base + rk[i]] = cf[i] == INT_MAX ? (int32_t)f : cf[i];
+      lval[base + rk[i]] = cv[i];
     }
     diag[f] = dg;
     rhs[f] = rh;
-    rowptr[f] = (int32_t)(6 * f);
-    if (f == nF - 1) rowptr[nF] = (int32_t)(6 * nF);
+    if (rowptr) {
+      rowptr[f] = (int32_t)(6 * f);
+      if (f == nF - 1) rowptr[nF] = (int32_t)(6 * nF);
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 6 * nb; i += FT) {
-    col[6 * f0 + i] = lcol[i];
-    val[6 * f0 + i] = lval[i];
+  if (col) {
+    for (int i = threadIdx.x; i < 6 * nb; i += FT) {
+      col[6 * f0 + i] = lcol[i];
+      val[6 * f0 + i] = lval[i];
+    }
+  } else {
+    for (int i = threadIdx.x; i < 6 * nb; i += FT) val[6 * f0 + i] = lval[i];
   }
 }
 
@@ -738,8 +769,11 @@ extern "C" int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const
   return PHFEM_OK;
 }
 
-extern "C" size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision) {
-  Arena a;
+extern "C" size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision,
+                                                 int32_t nk) {
+  (void)nF;
+  if (nk < 1) return 0;
+  Arena a;  // the AoS coordinates and one field's slot records (the fields run in turn)
   a.take<double4>(nC);
   if (precision == PHFEM_MIXED)
     a.take<SlotRec<float>>(4 * nE);
@@ -748,44 +782,72 @@ extern "C" size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, i
   return a.size();
 }
 
-extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
-                              const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* nbr,
-                              const int32_t* face2tet, const double* kappa, const phfem_params* p, void* work,
-                              size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag,
-                              double* rhs, phfem_stream_t stream_) {
+extern "C" size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision) {
+  return phfem_condense_batch_workspace(nC, nE, nF, precision, 1);
+}
+
+extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                                    const int32_t* faces, const int32_t* tet2face, const int8_t* sigma,
+                                    const int32_t* face2tet, int32_t nk, const double* kappa, const phfem_params* p,
+                                    void* work, size_t work_bytes, int32_t* rowptr, int32_t* col, double* val,
+                                    double* diag, double* rhs, phfem_stream_t stream_) {
   clear_error();
   hipStream_t s = (hipStream_t)stream_;
   int rc = check_params(p);
   if (rc) return rc;
-  (void)nbr;
-  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !face2tet || !rowptr ||
-      !col || !val || !diag || !rhs)
+  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !face2tet || !val ||
+      !diag || !rhs)
     return err(PHFEM_EINVAL, "bad condense arguments");
+  if (nk < 1 || (nk > 1 && !kappa)) return err(PHFEM_EINVAL, "nk >= 1 coefficient fields (kappa required for nk > 1)");
+  if ((rowptr == nullptr) != (col == nullptr)) return err(PHFEM_EINVAL, "rowptr and col: both or neither");
   if (6 * nF >= (int64_t(1) << 31)) return err(PHFEM_EINVAL, "face system exceeds int32 indexing");
-  if (!work || work_bytes < phfem_condense_workspace(nC, nE, nF, p->precision))
+  if (!work || work_bytes < phfem_condense_batch_workspace(nC, nE, nF, p->precision, nk))
     return err(PHFEM_EWORKSPACE, "condense workspace too small");
   Arena a(work, work_bytes);
   const bool mixed = p->precision == PHFEM_MIXED;
   double4* XA = a.take<double4>(nC);
   void* recs = mixed ? (void*)a.take<SlotRec<float>>(4 * nE) : (void*)a.take<SlotRec<double>>(4 * nE);
   DevParams P = to_dev(*p);
-  // algorithmic bytes: tets, faces, sigma (+ kappa) once per tet, coordinates once per node,
-  // four records per tet written once and read once, face2tet once, every off-diagonal slot
-  // (col + val), diagonal, rhs and row pointer written once
+  // algorithmic bytes per field: tets, faces, sigma (+ kappa) once per tet, four records per
+  // tet written once and read once, face2tet once, every off-diagonal value, diagonal and rhs
+  // written once, the pattern (col + row pointer) once when written; coordinates once per call
   const double rb = 4.0 * (double)(mixed ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>));
   const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
-  const double fb = rb * nE + 8.0 * nF + 12.0 * (6.0 * nF) + 20.0 * nF;
+  const double fbv = rb * nE + 8.0 * nF + (8.0 * 6.0 + 16.0) * nF, fbp = 4.0 * 7.0 * nF;
+  const unsigned ge = grid_for(nE, FT), gf = grid_for(nF, FT);
   PH_LAUNCH_B("coords_aos", 56.0 * nC, k_coords_aos, grid_for(nC, FT), FT, 0, s, nC, coord, XA);
-  if (mixed) {
-    PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
-                sigma, kappa, P, nF, (SlotRec<float>*)recs);
-    PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
-                face2tet, P, (const SlotRec<float>*)recs, rowptr, col, val, diag, rhs);
-  } else {
-    PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
-                sigma, kappa, P, nF, (SlotRec<double>*)recs);
-    PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, grid_for(nF, FT), FT, 0, s, nF, nC, coord, faces,
-                face2tet, P, (const SlotRec<double>*)recs, rowptr, col, val, diag, rhs);
+  for (int j = 0; j < nk; ++j) {
+    // field j; the pattern (when asked for) with the first field only
+    const double* kj = kappa ? kappa + j * nE : nullptr;
+    int32_t* rp = j == 0 ? rowptr : nullptr;
+    int32_t* cl = j == 0 ? col : nullptr;
+    double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
+    const double fb = fbv + (cl ? fbp : 0.0);
+    if (mixed) {
+      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, ge, FT, 0, s, nC, XA, nE, tetra, tet2face, sigma, kj, P, nF,
+                  (SlotRec<float>*)recs);
+      PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
+                  (const SlotRec<float>*)recs, rp, cl, vj, dj, rj);
+    } else {
+      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, ge, FT, 0, s, nC, XA, nE, tetra, tet2face, sigma, kj, P,
+                  nF, (SlotRec<double>*)recs);
+      PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
+                  (const SlotRec<double>*)recs, rp, cl, vj, dj, rj);
+    }
   }
   return PHFEM_OK;
+}
+
+extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                              const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* nbr,
+                              const int32_t* face2tet, const double* kappa, const phfem_params* p, void* work,
+                              size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag,
+                              double* rhs, phfem_stream_t stream) {
+  (void)nbr;
+  if (!rowptr || !col) {
+    clear_error();
+    return err(PHFEM_EINVAL, "bad condense arguments");
+  }
+  return phfem_condense_batch(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, 1, kappa, p, work,
+                              work_bytes, rowptr, col, val, diag, rhs, stream);
 }

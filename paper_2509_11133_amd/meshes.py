@@ -108,4 +108,9 @@ def lognormal_kappa(nE, sigma=1.0, seed=KAPPA_SEED):
     return np.exp(sigma * rng.standard_normal(nE))
 
 
+def lognormal_kappa_fields(nE, nk, sigma=1.0, seed=KAPPA_SEED):
+    """nk independent lognormal fields [nk, nE] (field j seeded with seed + j)."""
+    return np.stack([lognormal_kappa(nE, sigma, seed + j) for j in range(nk)])
+
+
 SIN3_AMPLITUDE = 3.0 * np.pi ** 2 + 1.0  # f = (3 pi^2 kappa + c) sin sin sin for kappa = c = 1

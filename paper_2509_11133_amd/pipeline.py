@@ -183,6 +183,45 @@ def condense(coord, tetra, conn, kappa, prm):
     return dict(rowptr=rowptr, col=col[:nnz], val=val[:nnz], diag=diag, rhs=rhs, nnz=nnz)
 
 
+def condense_batch(coord, tetra, conn, kappas, prm, pattern=None):
+    """Face systems of several kappa fields kappas [nk, nE] on one mesh in one call (NEXT
+    item: pattern reuse and batched coefficients).  pattern = (rowptr, col) of an earlier
+    condense on the same connectivity: only values are written; None: the pattern is built too.
+    Returns a list of nk systems (dicts as condense returns; they share rowptr and col)."""
+    dev = coord.device
+    nC, nE, nF = coord.shape[1], tetra.shape[1], conn["nF"]
+    kappas = kappas.contiguous()
+    nk = kappas.shape[0]
+    work = B.workspace(B.lib().phfem_condense_batch_workspace(nC, nE, nF, prm.precision, nk), dev)
+    nnz = 6 * nF
+    if pattern is None:
+        rowptr = torch.empty(nF + 1, dtype=I32, device=dev)
+        col = torch.empty(nnz, dtype=I32, device=dev)
+        rp, cl = rowptr, col
+    else:
+        rowptr, col = pattern
+        rp = cl = None
+    val = torch.empty((nk, nnz), dtype=F64, device=dev)
+    diag = torch.empty((nk, nF), dtype=F64, device=dev)
+    rhs = torch.empty((nk, nF), dtype=F64, device=dev)
+    B.phfem_condense_batch(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"],
+                           conn["face2tet"], nk, kappas, prm, work, rp, cl, val, diag, rhs)
+    return [dict(rowptr=rowptr, col=col, val=val[j], diag=diag[j], rhs=rhs[j], nnz=nnz) for j in range(nk)]
+
+
+def condense_reuse(coord, tetra, conn, kappa, prm):
+    """condense with the pattern kept in conn["pattern"]: the first call builds it, later calls
+    on the same connectivity write values only (the pattern depends on the connectivity alone)."""
+    if "pattern" not in conn:
+        sysm = condense(coord, tetra, conn, kappa, prm)
+        conn["pattern"] = (sysm["rowptr"], sysm["col"])
+        return sysm
+    nE = tetra.shape[1]
+    k = (torch.full((1, nE), prm.kappa_const, dtype=F64, device=coord.device) if kappa is None
+         else kappa.reshape(1, nE))
+    return condense_batch(coord, tetra, conn, k, prm, pattern=conn["pattern"])[0]
+
+
 def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.7, max_iter=200000,
           allow_noconv=False):
     """Face solve + recovery (a8-a9).  Returns (lambda, U, stats)."""
@@ -239,13 +278,14 @@ def refine_levels(coord, tetra, levels, db=None):
 class PrimalHybridSolve(torch.autograd.Function):
     """U = solution of the primal hybrid system for per-tet log-diffusivity and vertex
     coordinates; backward = one adjoint face solve + per-tet VJP kernels (phfem_grad).
-    Mesh connectivity (from connect) and params are fixed inputs."""
+    Mesh connectivity (from connect) and params are fixed inputs; the face-system pattern is
+    built by the first call and reused (values-only re-assembly) by later ones."""
 
     @staticmethod
     def forward(ctx, log_kappa, coord, tetra, conn, prm, mode, tol):
         kappa = torch.exp(log_kappa.detach()).contiguous()
         X = coord.detach().contiguous()
-        sysm = condense(X, tetra, conn, kappa, prm)
+        sysm = condense_reuse(X, tetra, conn, kappa, prm)
         lam, U, st = solve(X, tetra, conn, sysm, kappa, prm, mode=mode, tol=tol)
         ctx.save_for_backward(X, kappa, U, lam)
         ctx.tetra, ctx.conn, ctx.prm, ctx.mode, ctx.tol, ctx.sysm = tetra, conn, prm, mode, tol, sysm

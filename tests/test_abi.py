@@ -42,6 +42,9 @@ def test_workspace_queries():
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 2) > L.phfem_refine_connected_workspace(72, 114)
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 0) == 0
     assert L.phfem_errors_workspace(0) == 0 and L.phfem_errors_workspace(1000) >= 3 * 8 * 4
+    assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 1) == L.phfem_condense_workspace(20, 50, 100, 1)
+    assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 3) == L.phfem_condense_workspace(20, 50, 100, 1)
+    assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 0) == 0
     # Kuhn cube: 6 tets, 19 edges, 18 faces -> Table-1-style counts by the recurrences
     assert B.phfem_refined_sizes(8, 6, 19, 18, 2) == (8 + 19 + 6 + 2 * 19 + 3 * 18 + 6 * 6 + 72, 864,
                                                    2 * (2 * 19 + 3 * 18 + 36) + 3 * (4 * 18 + 96) + 6 * 72,
