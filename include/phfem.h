@@ -284,6 +284,9 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
 
 /* Solve S+ lambda = r+ (Jacobi-PCG; the paper solves it with a sparse direct solver,
  * Listing 8) and recover U(T) = A(T)^-1 (B(T) + C(T)' lambda(T)) (Algorithm 1, last loop).
+ * (rowptr, col, val, diag, rhs) as phfem_condense writes them: 6 slots per row, rowptr[F] =
+ * 6 F, column ids in [0, nF) -- checked on the device once per call (EINVAL otherwise); col
+ * 8-byte and val 16-byte aligned (vector loads of a row's slots).
  *  mode FP64_PCG: PCG on the FP64 system to ||r|| <= tol ||r+||.
  *  mode FP32_PCG_FP64_IR: iterative refinement without restarts: one FP32 PCG recurrence on
  *    an FP32 copy of the system, whose residual is replaced by the true residual

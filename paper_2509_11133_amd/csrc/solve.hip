@@ -48,22 +48,59 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return block_sum(v, lds);
 }
 
+// The face system's fixed 6-slot rows (rowptr[i] = 6 i, as phfem_condense writes them):
+// y = (D + offdiag) x and the partial dots x.y.  A row's 6 column ids and values are read as
+// three 8-byte (int2) and three 16- or 8-byte (double2 / float2) vector loads; the products
+// are summed in slot order, as a plain CSR loop would.
 template <class T>
-__global__ __launch_bounds__(ST) void k_spmv_dot(int64_t n, const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                 const T* __restrict__ diag, const T* __restrict__ x,
-                                                 T* __restrict__ y, double* __restrict__ part) {
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
+template <class T>
+__global__ __launch_bounds__(ST) void k_spmv_dot(int64_t n, const int32_t* __restrict__ col,
+                                                 const T* __restrict__ val, const T* __restrict__ diag,
+                                                 const T* __restrict__ x, T* __restrict__ y,
+                                                 double* __restrict__ part) {
+  using V2 = typename Vec2<T>::type;
   __shared__ double lds[ST / 64];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
-    T s = diag[i] * x[i];
-    const int q1 = rowptr[i + 1];
-    for (int q = rowptr[i]; q < q1; ++q) s += val[q] * x[col[q]];
+    const int2* c2 = reinterpret_cast<const int2*>(col + 6 * i);
+    const V2* v2 = reinterpret_cast<const V2*>(val + 6 * i);
+    const int2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
+    const V2 v01 = v2[0], v23 = v2[1], v45 = v2[2];
+    const T xi = x[i];
+    T s = diag[i] * xi;
+    s += v01.x * x[c01.x];
+    s += v01.y * x[c01.y];
+    s += v23.x * x[c23.x];
+    s += v23.y * x[c23.y];
+    s += v45.x * x[c45.x];
+    s += v45.y * x[c45.y];
     y[i] = s;
-    acc += (double)x[i] * (double)s;
+    acc += (double)xi * (double)s;
   }
   double b = block_sum(acc, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+// the pattern check run once per solve: rowptr[i] = 6 i and every column id in [0, nF)
+__global__ __launch_bounds__(ST) void k_check_pattern(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, int* __restrict__ flags) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i <= n; i += (int64_t)gridDim.x * ST) {
+    bad = bad || (int64_t)rowptr[i] != 6 * i;
+    if (i < n)
+      for (int q = 0; q < 6; ++q) bad = bad || (uint32_t)col[6 * i + q] >= (uint64_t)n;
+  }
+  if (bad) atomicOr(flags + 1, 1);
 }
 
 template <class T>
@@ -270,9 +307,9 @@ static int norm2(int64_t n, const double* v, PcgWS& w, double* out, hipStream_t 
   return rc;
 }
 
-// PCG on (rowptr, col, val, diag) from x0 = 0; stops at ||r|| <= tol ||b|| or maxit.
+// PCG on the 6-slot system (col, val, diag) from x0 = 0; stops at ||r|| <= tol ||b|| or maxit.
 template <class T>
-static int pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* diag, const T* b, T* x,
+static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const T* b, T* x,
                double tol, int maxit, PcgWS& w, int* iters, double* relres, hipStream_t s) {
   const unsigned G = pcg_grid(n);
   T *r = (T*)w.r, *z = (T*)w.z, *p = (T*)w.p, *q = (T*)w.q;
@@ -289,7 +326,8 @@ static int pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const T* va
   int slot = 0, it = 0;
   double rel = 1.0;
   while (it < maxit) {
-    PH_LAUNCH_B("spmv_dot", (double)n * (4 + 3 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dot<T>, G, ST, 0, s, n, rowptr, col, val, diag, (const T*)p, q, w.part_pq);
+    PH_LAUNCH_B("spmv_dot", (double)n * (3 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dot<T>, G, ST, 0, s, n,
+                col, val, diag, (const T*)p, q, w.part_pq);
     PH_LAUNCH_B("pcg_update", 8.0 * sizeof(T) * n, k_pcg_update<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
               slot, x, r, (const T*)p, (const T*)q, diag, z, w.part_rz, w.part_rr);
     PH_LAUNCH_B("pcg_dir", 3.0 * sizeof(T) * n, k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz, (const double*)w.part_rr,
@@ -343,13 +381,23 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
                       const double* diag, const double* rhs, int32_t mode, double tol, double inner_tol, int maxit,
                       SolveWS& w, double* x, double* U, phfem_solve_stats* st, hipStream_t s) {
   const int64_t nF = m.nF;
-  PH_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+  PH_HIP(hipMemsetAsync(w.flags, 0, 2 * sizeof(int), s));
   int rc;
+  if ((reinterpret_cast<uintptr_t>(col) & 7) || (reinterpret_cast<uintptr_t>(val) & 15))
+    return err(PHFEM_EINVAL, "col must be 8-byte and val 16-byte aligned");
+  {
+    PH_LAUNCH("check_pattern", k_check_pattern, pcg_grid(nF + 1), ST, 0, s, nF, rowptr, col, w.flags);
+    int hf[2] = {0, 0};
+    PH_HIP(hipMemcpyAsync(hf, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (hf[1]) return err(PHFEM_EINVAL, "face system is not the 6-slot layout of phfem_condense (rowptr[F] = 6 F, "
+                                        "column ids in [0, nF))");
+  }
   phfem_solve_stats loc = {0, 0, 0.0, 0.0};
   if (mode == PHFEM_SOLVE_FP64_PCG) {
     double rel = 0;
     int it = 0;
-    rc = pcg<double>(nF, rowptr, col, val, diag, rhs, x, tol, maxit, w.pcg, &it, &rel, s);
+    rc = pcg<double>(nF, col, val, diag, rhs, x, tol, maxit, w.pcg, &it, &rel, s);
     if (rc) return rc;
     loc.iters = it;
     // true residual in FP64, matrix-free; also writes U
@@ -371,15 +419,9 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
       return err(PHFEM_ENOCONV, "PCG reached max_iter above tolerance");
     return PHFEM_OK;
   }
-  // mixed: FP32 copy of the system (nnz = rowptr[nF] off-diagonals)
-  {
-    int32_t nnz = 0;
-    PH_HIP(hipMemcpyAsync(&nnz, rowptr + nF, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    PH_HIP(hipStreamSynchronize(s));
-    if (nnz < 0 || nnz > 6 * nF) return err(PHFEM_EINVAL, "row pointer inconsistent with nF");
-    PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nnz), ST, 0, s, (int64_t)nnz, val, w.val32);
-    PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, diag, w.diag32);
-  }
+  // mixed: FP32 copy of the system (6 nF off-diagonal slots)
+  PH_LAUNCH("to_f32", k_to_f32, pcg_grid(6 * nF), ST, 0, s, 6 * nF, val, w.val32);
+  PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, diag, w.diag32);
   // Iterative refinement without restarts: one FP32 PCG recurrence on the FP32 system whose
   // residual is replaced by the true FP64 residual b_D - C U(x) (matrix-free, per tet, from
   // the geometry) whenever the recurrence residual has dropped by REPLACE since the last
@@ -418,8 +460,8 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
       *st = loc;
       return err(PHFEM_ENOCONV, "mixed refinement reached max_iter above tolerance");
     }
-    PH_LAUNCH_B("spmv_dot", (double)nF * (4 + 3 * 4) + 6.0 * nF * (4 + 4), k_spmv_dot<float>, G, ST, 0, s, nF, rowptr,
-                col, (const float*)w.val32, (const float*)w.diag32, (const float*)p, q, pw.part_pq);
+    PH_LAUNCH_B("spmv_dot", (double)nF * (3 * 4) + 6.0 * nF * (4 + 4), k_spmv_dot<float>, G, ST, 0, s, nF, col,
+                (const float*)w.val32, (const float*)w.diag32, (const float*)p, q, pw.part_pq);
     PH_LAUNCH_B("pcg_update", 8.0 * 4 * nF, k_pcg_update<float>, G, ST, 0, s, nF, (int)G, (const double*)pw.part_pq,
                 (const double*)pw.scal, slot, w.x32, r32, (const float*)p, (const float*)q, (const float*)w.diag32, z,
                 pw.part_rz, pw.part_rr);

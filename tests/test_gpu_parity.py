@@ -518,3 +518,22 @@ def test_neumann_grad_rejected():
     from paper_2509_11133_amd import _binding as B
     with pytest.raises(B.PhfemError):
         P.grad(dev(X), dev(T), gc, sysm, None, gp, gU, glam, gU)
+
+
+def test_solve_pattern_check():
+    """phfem_solve takes the 6-slot layout condense writes; another row pointer or a column id
+    outside [0, nF) is found by the device-side check and refused before any iteration."""
+    X, T = jittered(1, seed=2)
+    gc = P.connect(dev(T), X.shape[1])
+    gp = P.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
+    sysm = P.condense(dev(X), dev(T), gc, None, gp)
+    from paper_2509_11133_amd import _binding as B
+    bad_rp = dict(sysm, rowptr=sysm["rowptr"].clone())
+    bad_rp["rowptr"][5] += 1
+    bad_col = dict(sysm, col=sysm["col"].clone())
+    bad_col["col"][17] = gc["nF"]
+    for bad in (bad_rp, bad_col):
+        with pytest.raises(B.PhfemError, match="6-slot"):
+            P.solve(dev(X), dev(T), gc, bad, None, gp, mode=0, tol=1e-10)
+    lam, U, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=1, tol=1e-10)
+    assert st["converged"]
