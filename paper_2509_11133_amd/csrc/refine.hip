@@ -24,13 +24,12 @@ __global__ __launch_bounds__(RT) void k_copy_coords(int64_t nC, const double* __
   for (int d = 0; d < 3; ++d) Xo[d * nCo + v] = X[d * nC + v];
 }
 
-__global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restrict__ X, int64_t nE,
-                                               const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
-                                               const int32_t* __restrict__ eft, const int32_t* __restrict__ pre,
-                                               int64_t nCo, double* __restrict__ Xo, int32_t* __restrict__ To,
-                                               uint32_t* __restrict__ bad) {
-  int64_t t = (int64_t)blockIdx.x * RT + threadIdx.x;
-  if (t >= nE) return;
+// one tet: its new coordinates (written directly) and its children (into the LDS rows)
+__device__ __forceinline__ void refine_tet(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                           const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
+                                           const int32_t* __restrict__ eft, const int32_t* __restrict__ pre,
+                                           int64_t nCo, double* __restrict__ Xo, uint32_t* __restrict__ bad, int64_t t,
+                                           int32_t (*sT)[12 * RT], int l) {
   const int64_t nEd = nCo - nC - nE;
   int v[4], e[6], m[6];
   bool ok = true;
@@ -52,8 +51,12 @@ __global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restr
     m[j] = (int)mj;
     e[j] = (ft == t) ? 1 : 0;  // reuse: does the edge first appear in this tet?
   }
-  if (!ok) {  // ids outside the mesh: nothing is written for this tet
+  if (!ok) {  // ids outside the mesh: no coordinates, children rows -1, and the call fails
     if (bad) atomicOr(bad, 1u);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sT[i][c == 0 ? l : RT + 11 * l + c - 1] = -1;
     return;
   }
 #pragma unroll
@@ -71,13 +74,34 @@ __global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restr
                          {L, m[5], m[4], m[2]},    {m[0], m[1], m[2], C},    {m[3], m[0], m[4], C},
                          {m[1], m[3], m[5], C},    {m[5], m[4], m[2], C},    {m[0], m[3], m[1], C},
                          {m[1], m[5], m[2], C},    {m[0], m[2], m[4], C},    {m[5], m[3], m[4], C}};
-  const int64_t nEo = 12 * nE;
-  const int64_t r1 = nE + 11 * t;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    To[i * nEo + t] = ch[0][i];
+    sT[i][l] = ch[0][i];
 #pragma unroll
-    for (int c = 1; c < 12; ++c) To[i * nEo + r1 + (c - 1)] = ch[c][i];
+    for (int c = 1; c < 12; ++c) sT[i][RT + 11 * l + (c - 1)] = ch[c][i];
+  }
+}
+
+// The children of a workgroup's RT tets are rows [t0, t0 + RT) (child 0) and
+// [nE + 11 t0, nE + 11 (t0 + RT)) (children 1..11): staged in LDS and stored as two
+// contiguous ranges per vertex array (full cache lines instead of stride-11 stores).
+__global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restrict__ X, int64_t nE,
+                                               const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
+                                               const int32_t* __restrict__ eft, const int32_t* __restrict__ pre,
+                                               int64_t nCo, double* __restrict__ Xo, int32_t* __restrict__ To,
+                                               uint32_t* __restrict__ bad) {
+  __shared__ int32_t sT[4][12 * RT];
+  const int64_t t0 = (int64_t)blockIdx.x * RT;
+  const int nb = nE - t0 < RT ? (int)(nE - t0) : RT;
+  const int l = threadIdx.x;
+  if (l < nb) refine_tet(nC, X, nE, tet, t2e, eft, pre, nCo, Xo, bad, t0 + l, sT, l);
+  __syncthreads();
+  const int64_t nEo = 12 * nE;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int32_t* o = To + i * nEo;
+    for (int k = l; k < nb; k += RT) o[t0 + k] = sT[i][k];
+    for (int k = l; k < 11 * nb; k += RT) o[nE + 11 * t0 + k] = sT[i][RT + k];
   }
 }
 
