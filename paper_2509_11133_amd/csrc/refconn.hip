@@ -151,7 +151,8 @@ struct RCArgs {
   uint32_t* recF;
   uint32_t* tagg;  // [4][ntiles] per-workgroup totals: edges of the child-0 rows, of the other
   uint32_t* tpre;  // rows, faces of the child-0 rows, of the other rows; tpre = their offsets
-  int64_t ntiles;  // (exclusive scans of [edges | edges], [faces | faces]), then the two totals
+  int64_t ntiles;  // (one exclusive scan over all four; a face offset is tpre[.] - tpre[2 ntiles],
+                   // the edge total), then the grand total
   int32_t* edges2;
   int32_t* t2e2;
   int32_t* eft2;
@@ -444,8 +445,9 @@ __device__ __forceinline__ uint32_t pre_e(const RCArgs& A, int row, uint32_t rec
   return ldu(A.tpre, (uint32_t)((row < nE ? 0 : 1) * (int)A.ntiles + row_tile(nE, row))) + (rec >> 6);
 }
 __device__ __forceinline__ uint32_t pre_f(const RCArgs& A, int row, uint32_t rec) {
-  const int nE = (int)A.nE;
-  return ldu(A.tpre, (uint32_t)((row < nE ? 2 : 3) * (int)A.ntiles + row_tile(nE, row))) + (rec >> 4);
+  const int nE = (int)A.nE, n = (int)A.ntiles;
+  return ldu(A.tpre, (uint32_t)((row < nE ? 2 : 3) * n + row_tile(nE, row))) - ldu(A.tpre, (uint32_t)(2 * n)) +
+         (rec >> 4);
 }
 
 // pass 2: ids of the refined edges and faces of every row, and all outputs.  Phase 1 stages
@@ -663,11 +665,13 @@ __global__ __launch_bounds__(RCT) void k_rc_init(int64_t nEd, int32_t* __restric
 }
 
 // input ids out of range (flag) and refined totals against the recurrences: ORs a code into
-// *status (device), and writes out[3] = {edges, faces, flag} when out != null
-__global__ void k_rc_check(const uint32_t* __restrict__ tot, const uint32_t* __restrict__ flag, int64_t nEd2,
-                           int64_t nF2, int32_t* __restrict__ status, int64_t* __restrict__ out) {
+// *status (device), and writes out[3] = {edges, faces, flag} when out != null.  etot = the
+// edge total, all = edges + faces.
+__global__ void k_rc_check(const uint32_t* __restrict__ etot, const uint32_t* __restrict__ all,
+                           const uint32_t* __restrict__ flag, int64_t nEd2, int64_t nF2, int32_t* __restrict__ status,
+                           int64_t* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int64_t ne = tot[0], nf = tot[1];
+  const int64_t ne = *etot, nf = (int64_t)*all - ne;
   int32_t code = 0;
   if (*flag) code |= 1;
   if (ne != nEd2 || nf != nF2) code |= 2;
@@ -684,7 +688,7 @@ struct RCWS {
   int4 *T4, *F4, *N4, *E8;
   uint32_t *recE, *recF;
   uint32_t* z;  // zeroed by the init kernel: 4 words (input flag z[2]), the scans' status
-  uint64_t *stE, *stF;
+  uint64_t* st;
   uint32_t *tagg, *tpre;
   int64_t ntiles, nz;
   int64_t* chk;  // {edges, faces, flag} read back by the synchronous check
@@ -702,11 +706,10 @@ static void rc_layout(Arena& a, int64_t nE, int64_t nEd, RCWS& w) {
   w.recE = a.take<uint32_t>(n2);
   w.recF = a.take<uint32_t>(n2);
   w.ntiles = (nE + RCW - 1) / RCW;
-  const int64_t sw = scan_status_words(2 * w.ntiles);
-  w.z = a.take<uint32_t>(4 + 4 * sw);
-  w.stE = reinterpret_cast<uint64_t*>(w.z + 4);
-  w.stF = w.stE + sw;
-  w.nz = 4 + 4 * sw;
+  const int64_t sw = scan_status_words(4 * w.ntiles);
+  w.z = a.take<uint32_t>(4 + 2 * sw);
+  w.st = reinterpret_cast<uint64_t*>(w.z + 4);
+  w.nz = 4 + 2 * sw;
   w.tagg = a.take<uint32_t>(4 * w.ntiles);
   w.tpre = a.take<uint32_t>(4 * w.ntiles + 2);
   w.chk = a.take<int64_t>(4);
@@ -796,16 +799,14 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   // one record word per refined row and count
   PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, (unsigned)w.ntiles, RCB, 0, s, A);
   // offsets of the workgroups' row ranges: other rows after all child-0 rows
-  rc = scan_exclusive(w.tagg, w.tpre, 2 * w.ntiles, w.tpre + 4 * w.ntiles, a, s, w.stE);
-  if (rc) return rc;
-  rc = scan_exclusive(w.tagg + 2 * w.ntiles, w.tpre + 2 * w.ntiles, 2 * w.ntiles, w.tpre + 4 * w.ntiles + 1, a, s,
-                      w.stF);
+  rc = scan_exclusive(w.tagg, w.tpre, 4 * w.ntiles, w.tpre + 4 * w.ntiles, a, s, w.st);
   if (rc) return rc;
   // pass 2 writes every refined connectivity array once
   PH_LAUNCH_B("refconn_pass2", 80.0 * nE + 12.0 * nEd + 8.0 * nE2 + (24.0 + 4 + 16 + 1 * 4 + 16) * nE2 + 12.0 * nEd2 +
                                    20.0 * nF2,
               k_rc_pass2, (unsigned)w.ntiles, RCB, 0, s, A);
-  PH_LAUNCH("rc_check", k_rc_check, 1, 64, 0, s, w.tpre + 4 * w.ntiles, w.z + 2, nEd2, nF2, status,
+  PH_LAUNCH("rc_check", k_rc_check, 1, 64, 0, s, (const uint32_t*)w.tpre + 2 * w.ntiles,
+            (const uint32_t*)w.tpre + 4 * w.ntiles, w.z + 2, nEd2, nF2, status,
             status ? nullptr : w.chk);
   if (!status) {  // synchronous check
     int64_t chk[3] = {0, 0, 0};

@@ -16,14 +16,6 @@ constexpr int RT = 256;
 
 __device__ int g_face_flag;
 
-__global__ __launch_bounds__(RT) void k_copy_coords(int64_t nC, const double* __restrict__ X, int64_t nCo,
-                                                    double* __restrict__ Xo) {
-  int64_t v = (int64_t)blockIdx.x * RT + threadIdx.x;
-  if (v >= nC) return;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) Xo[d * nCo + v] = X[d * nC + v];
-}
-
 // one tet: its new coordinates (written directly) and its children (into the LDS rows)
 __device__ __forceinline__ void refine_tet(int64_t nC, const double* __restrict__ X, int64_t nE,
                                            const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
@@ -84,7 +76,8 @@ __device__ __forceinline__ void refine_tet(int64_t nC, const double* __restrict_
 
 // The children of a workgroup's RT tets are rows [t0, t0 + RT) (child 0) and
 // [nE + 11 t0, nE + 11 (t0 + RT)) (children 1..11): staged in LDS and stored as two
-// contiguous ranges per vertex array (full cache lines instead of stride-11 stores).
+// contiguous ranges per vertex array (full cache lines instead of stride-11 stores).  The
+// grid covers max(nE, nC): thread g also copies the old node g's coordinates.
 __global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restrict__ X, int64_t nE,
                                                const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
                                                const int32_t* __restrict__ eft, const int32_t* __restrict__ pre,
@@ -92,8 +85,12 @@ __global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restr
                                                uint32_t* __restrict__ bad) {
   __shared__ int32_t sT[4][12 * RT];
   const int64_t t0 = (int64_t)blockIdx.x * RT;
-  const int nb = nE - t0 < RT ? (int)(nE - t0) : RT;
+  const int nb = nE - t0 < RT ? (nE > t0 ? (int)(nE - t0) : 0) : RT;
   const int l = threadIdx.x;
+  if (t0 + l < nC) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Xo[d * nCo + t0 + l] = X[d * nC + t0 + l];
+  }
   if (l < nb) refine_tet(nC, X, nE, tet, t2e, eft, pre, nCo, Xo, bad, t0 + l, sT, l);
   __syncthreads();
   const int64_t nEo = 12 * nE;
@@ -146,10 +143,10 @@ __global__ __launch_bounds__(RT) void k_refine_faces(int64_t n, const int32_t* _
 int launch_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, const int32_t* t2e,
                   const int32_t* eft, const int32_t* pre, int64_t nCo, double* coord_out, int32_t* tetra_out,
                   hipStream_t s, uint32_t* bad) {
-  PH_LAUNCH_B("copy_coords", 48.0 * nC, k_copy_coords, grid_for(nC, RT), RT, 0, s, nC, coord, nCo, coord_out);
   const int64_t nEd = nCo - nC - nE;
-  PH_LAUNCH_B("refine", 44.0 * nE + 4.0 * nEd + 24.0 * nC + 192.0 * nE + 24.0 * (nE + nEd), k_refine, grid_for(nE, RT),
-              RT, 0, s, nC, coord, nE, tetra, t2e, eft, pre, nCo, coord_out, tetra_out, bad);
+  PH_LAUNCH_B("refine", 44.0 * nE + 4.0 * nEd + 24.0 * nC + 192.0 * nE + 24.0 * (nE + nEd) + 48.0 * nC, k_refine,
+              grid_for(std::max(nE, nC), RT), RT, 0, s, nC, coord, nE, tetra, t2e, eft, pre, nCo, coord_out, tetra_out,
+              bad);
   return PHFEM_OK;
 }
 
