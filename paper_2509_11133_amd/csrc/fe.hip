@@ -21,6 +21,7 @@
 namespace ph {
 
 constexpr int FT = 256;
+constexpr int ET64 = 128;
 
 template <class R>
 struct Elem {
@@ -374,14 +375,22 @@ __device__ __forceinline__ void elem_records(const double (&x)[4][3], const int 
   }
 }
 
+// workgroup size of k_elem_rec: FP64 records (56 B) stage 4 x 56 B per thread, so FP64 takes
+// smaller workgroups to keep several resident per CU
 template <class R>
-__global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __restrict__ XA, int64_t nE,
+constexpr int elem_threads() {
+  return sizeof(R) == 8 ? ET64 : FT;
+}
+
+template <class R>
+__global__ __launch_bounds__(elem_threads<R>()) void k_elem_rec(int64_t nC, const double4* __restrict__ XA, int64_t nE,
                                                  const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                                  const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
                                                  DevParams P, int64_t nF, SlotRec<R>* __restrict__ recs) {
   constexpr int W = sizeof(SlotRec<R>) / 8;
-  __shared__ uint2 lrec[4 * FT * W];
-  const int64_t t0 = (int64_t)blockIdx.x * FT;
+  constexpr int NT = elem_threads<R>();
+  __shared__ uint2 lrec[4 * NT * W];
+  const int64_t t0 = (int64_t)blockIdx.x * NT;
   const int64_t t = t0 + threadIdx.x;
   if (t < nE) {
     int v[4], sig[4], F[4];
@@ -397,9 +406,9 @@ __global__ __launch_bounds__(FT) void k_elem_rec(int64_t nC, const double4* __re
     elem_records<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, lrec + 4 * threadIdx.x * W);
   }
   __syncthreads();
-  const int64_t nb = nE - t0 < FT ? nE - t0 : FT;
+  const int64_t nb = nE - t0 < NT ? nE - t0 : NT;
   uint2* out = reinterpret_cast<uint2*>(recs + 4 * t0);
-  for (int i = threadIdx.x; i < 4 * nb * W; i += FT) out[i] = lrec[i];
+  for (int i = threadIdx.x; i < 4 * nb * W; i += NT) out[i] = lrec[i];
 }
 
 // One face's row from its owner's slot q0 and its neighbour's slot q1 (-1 on the boundary):
@@ -814,7 +823,7 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
   const double rb = 4.0 * (double)(mixed ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>));
   const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
   const double fbv = rb * nE + 8.0 * nF + (8.0 * 6.0 + 16.0) * nF, fbp = 4.0 * 7.0 * nF;
-  const unsigned ge = grid_for(nE, FT), gf = grid_for(nF, FT);
+  const unsigned gf = grid_for(nF, FT);
   PH_LAUNCH_B("coords_aos", 56.0 * nC, k_coords_aos, grid_for(nC, FT), FT, 0, s, nC, coord, XA);
   for (int j = 0; j < nk; ++j) {
     // field j; the pattern (when asked for) with the first field only
@@ -824,13 +833,13 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
     double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
     const double fb = fbv + (cl ? fbp : 0.0);
     if (mixed) {
-      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, ge, FT, 0, s, nC, XA, nE, tetra, tet2face, sigma, kj, P, nF,
-                  (SlotRec<float>*)recs);
+      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
+                  sigma, kj, P, nF, (SlotRec<float>*)recs);
       PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
                   (const SlotRec<float>*)recs, rp, cl, vj, dj, rj);
     } else {
-      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, ge, FT, 0, s, nC, XA, nE, tetra, tet2face, sigma, kj, P,
-                  nF, (SlotRec<double>*)recs);
+      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, ET64), ET64, 0, s, nC, XA, nE, tetra,
+                  tet2face, sigma, kj, P, nF, (SlotRec<double>*)recs);
       PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
                   (const SlotRec<double>*)recs, rp, cl, vj, dj, rj);
     }
