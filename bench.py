@@ -253,6 +253,45 @@ def reassembly_block(torch, P, B, M, X0d, T0d, L, reps=5, nk=4):
     return out
 
 
+# The paper's own timings (MATLAB R2025a, vectorized, FP64, on an Intel Core i5-10210U), level
+# 5 of its 5-tet cube (1,244,160 tets): Table 1 (connectivity and refinement) and Table 2
+# (local matrices), in seconds.  Another machine and another program: context, not a target.
+PAPER_L5 = {"cpu": "Intel Core i5-10210U, MATLAB R2025a (vectorized, FP64)", "tets": 1244160,
+            "FacesUp_s": 3.7920, "NumEdges_s": 1.0248, "EdgeNum2Tetra_s": 2.7785, "RedRefine_s": 0.5407,
+            "StiffMassPH_s": 4.2434, "Multiplier_s": 4.5835}
+
+
+def paper_mesh_block(torch, P, B, M, L=5, reps=5):
+    """The paper's 5-tet cube refined to its Table 1/2 level 5 (1,244,160 tets), through the
+    same GPU pipeline as the headline (connect of level 0, refined connectivity per level,
+    condense), FP64 and mixed, beside the paper's level-5 MATLAB timings (context only: the
+    paper's times cover one level's connectivity / refinement and the local matrices)."""
+    dev = torch.device("cuda:0")
+    X0, T0, _, _ = M.paper_cube()
+    X0d, T0d = torch.tensor(X0, device=dev), torch.tensor(T0, device=dev)
+    out = {"workload": f"the paper's 5-tet cube (Section 2.3), {L} levels, sin^3 load, all faces Dirichlet"}
+    for label, prec in (("fp64", B.FP64), ("mixed", B.MIXED)):
+        prm = P.params(c=1.0, kappa=1.0, f=(B.FUN_SIN3, (M.SIN3_AMPLITUDE,)), precision=prec)
+        run_pipeline(P, X0d, T0d, None, L, prm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            res = run_pipeline(P, X0d, T0d, None, L, prm)
+        e1.record()
+        torch.cuda.synchronize()
+        nE = res[1].shape[1]
+        ms = e0.elapsed_time(e1) / reps
+        out[label] = {"ms": round(ms, 4), "tets_per_s": round(nE / (ms * 1e-3), 1)}
+        del res
+    out["nE"] = nE
+    paper_s = sum(v for k, v in PAPER_L5.items() if k.endswith("_s"))
+    out["paper_matlab_level5"] = dict(PAPER_L5, sum_s=round(paper_s, 4),
+                                      note="one level's connectivity + refinement + local matrices; other machine")
+    log("paper mesh", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +305,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (per-kernel HIP events)")
     ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
     ap.add_argument("--no-reassembly", action="store_true", help="skip the pattern-reuse / batched-kappa timings")
+    ap.add_argument("--no-paper-mesh", action="store_true", help="skip the paper's 5-tet cube timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (the reference kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -358,6 +398,9 @@ def main():
                                                for k, v in sorted(fp64["kern"].items(), key=lambda kv: -kv[1]["ms"])}
     if not args.no_reassembly:
         line["reassembly"] = reassembly_block(torch, P, B, M, X0d, T0d, L)
+        torch.cuda.empty_cache()
+    if not args.no_paper_mesh:
+        line["paper_mesh"] = paper_mesh_block(torch, P, B, M)
         torch.cuda.empty_cache()
     if not args.no_solve:
         line["solve"] = solve_block(torch, P, B, M, args.solve_levels)
