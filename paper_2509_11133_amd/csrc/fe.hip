@@ -509,21 +509,21 @@ __global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const 
       lcol[base + rk[i]] = cf[i] == INT_MAX ? (int32_t)f : cf[i];
       lval[base + rk[i]] = cv[i];
     }
-    diag[f] = dg;
-    rhs[f] = rh;
+    st_nt(diag + f, dg);
+    st_nt(rhs + f, rh);
     if (rowptr) {
-      rowptr[f] = (int32_t)(6 * f);
+      st_nt(rowptr + f, (int32_t)(6 * f));
       if (f == nF - 1) rowptr[nF] = (int32_t)(6 * nF);
     }
   }
   __syncthreads();
   if (col) {
     for (int i = threadIdx.x; i < 6 * nb; i += FT) {
-      col[6 * f0 + i] = lcol[i];
-      val[6 * f0 + i] = lval[i];
+      st_nt(col + 6 * f0 + i, lcol[i]);
+      st_nt(val + 6 * f0 + i, lval[i]);
     }
   } else {
-    for (int i = threadIdx.x; i < 6 * nb; i += FT) val[6 * f0 + i] = lval[i];
+    for (int i = threadIdx.x; i < 6 * nb; i += FT) st_nt(val + 6 * f0 + i, lval[i]);
   }
 }
 

@@ -121,7 +121,7 @@ static_assert(first3(0, false) == 4 && first3(3, false) == 5, "first (M, C)");
 
 // Element i of an array addressed as its (wave-uniform) base plus an unsigned 32-bit byte
 // offset: the hardware adds the offset to a scalar base, so no 64-bit address arithmetic is
-// spent per access.  Valid while i * sizeof(T) < 2^32 (every array indexed this way holds
+// spent per access.  Stores (every one of them a write-once output) carry the nontemporal hint.  Valid while i * sizeof(T) < 2^32 (every array indexed this way holds
 // at most 16 nE' bytes < 2^32 by the entry point's size limits; two-dimensional outputs
 // take a per-row base).
 template <class T>
@@ -130,7 +130,7 @@ __device__ __forceinline__ T ldu(const T* p, uint32_t i) {
 }
 template <class T>
 __device__ __forceinline__ void stu(T* p, uint32_t i, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + i * (uint32_t)sizeof(T)) = v;
+  st_nt(reinterpret_cast<T*>(reinterpret_cast<char*>(p) + i * (uint32_t)sizeof(T)), v);
 }
 
 constexpr int RCT = 256;

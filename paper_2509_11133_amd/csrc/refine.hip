@@ -97,8 +97,8 @@ __global__ __launch_bounds__(RT) void k_refine(int64_t nC, const double* __restr
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     int32_t* o = To + i * nEo;
-    for (int k = l; k < nb; k += RT) o[t0 + k] = sT[i][k];
-    for (int k = l; k < 11 * nb; k += RT) o[nE + 11 * t0 + k] = sT[i][RT + k];
+    for (int k = l; k < nb; k += RT) st_nt(o + t0 + k, sT[i][k]);
+    for (int k = l; k < 11 * nb; k += RT) st_nt(o + nE + 11 * t0 + k, sT[i][RT + k]);
   }
 }
 
