@@ -1,0 +1,151 @@
+"""The gradient and Fichera workloads at full size, checked through properties that hold at
+any size (the oracle cannot solve these meshes in seconds).
+
+* Kuhn cube, 5 levels (1,492,992 tets), interior vertices jittered by +-0.1 h, lognormal
+  kappa (sigma 1), the kappa = 1 manufactured load, u_target = the FP64 solution at kappa = 1,
+  J = 1/2 |U - u_target|^2: forward solve and adjoint in FP64 and in mixed precision, both
+  to 1e-12.  Both true (matrix-free FP64) residuals <= 1e-10; mixed u_h within 1e-9 of FP64
+  (the FP64 PCG stops on its recurrence residual, and the true residual of the stored FP64
+  system's solution levels off near 3.5e-11 on this mesh, which bounds the FP64 reference's
+  own accuracy; the mixed solver converges on the true residual and reaches 1e-12); mixed
+  gradients within 1e-6 of FP64 (relative to the largest entry); the FP64 gradients against
+  central differences of J along smooth directions of log kappa and of the coordinates
+  (1e-6; smooth, so that the directional derivative is not a cancelling sum of per-tet
+  terms that solver noise would swamp); local conservation on sampled tets.
+* Fichera domain, 5 levels (10,450,944 tets), f = 1, zero Dirichlet data, lognormal kappa
+  (sigma 0.5): exhaustive connectivity properties, sampled condensed rows against the
+  oracle (FP64 1e-12, mixed 1e-5), the mixed solve (true FP64 residual 1e-11) with local
+  conservation on sampled tets, and the mixed adjoint against a central difference of J
+  along a smooth log-kappa direction (1e-5).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2509_11133_amd import meshes as M
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2509_11133_amd import pipeline as P  # noqa: E402
+
+from tests.gpu_checks import DEV, check_conservation, check_rows, check_topology, refined_counts  # noqa: E402
+
+FICHERA0 = (26, 42, 91, 108, 48)  # level-0 (nC, nE, nEd, nF, nB)
+SIN3 = (O.FUN_SIN3, (M.SIN3_AMPLITUDE,))
+
+
+def J_of(X, T, c, kappa, prm, mode, Ut, tol, stats=None):
+    sysm = P.condense(X, T, c, kappa, prm)
+    lam, U, st = P.solve(X, T, c, sysm, kappa, prm, mode=mode, tol=tol)
+    assert st["converged"]
+    if stats is not None:
+        stats.update(st)
+    return 0.5 * float(((U - Ut) ** 2).sum()), sysm, lam, U
+
+
+def smooth_tet_field(X, T):
+    """a smooth scalar per tet: sin(3x + 2y - z) at its centroid"""
+    xc = X[:, T.long()].mean(dim=1)
+    return torch.sin(3 * xc[0] + 2 * xc[1] - xc[2])
+
+
+def smooth_vertex_field(X):
+    """a smooth displacement per vertex"""
+    return torch.stack([torch.sin(2 * X[1] + X[2]), torch.cos(X[0] - X[2]), torch.sin(X[0] + X[1])])
+
+
+@pytest.fixture(scope="module")
+def jittered5():
+    X0, T0 = M.kuhn_cube()
+    Xd, Td, c = P.refine_connected_levels(torch.tensor(X0, device=DEV), torch.tensor(T0, device=DEV), 5)
+    X = torch.tensor(M.jitter_unit_cube(Xd.cpu().numpy(), Td.cpu().numpy(), 0.1), device=DEV)
+    kap = torch.tensor(M.lognormal_kappa(Td.shape[1], 1.0), device=DEV)
+    p64 = P.params(c=1.0, f=SIN3, precision=0)
+    _, _, _, Ut = J_of(X, Td, c, None, p64, 0, 0.0, 1e-12)  # u_target: FP64 solution at kappa = 1
+    return X, Td, c, kap, Ut
+
+
+def test_gradient_workload_mixed_vs_fp64(jittered5):
+    X, T, c, kap, Ut = jittered5
+    out = {}
+    for prec, mode in ((0, 0), (1, 1)):
+        prm = P.params(c=1.0, f=SIN3, precision=prec)
+        sst = {}
+        J, sysm, lam, U = J_of(X, T, c, kap, prm, mode, Ut, 1e-12, sst)
+        dlogk, dX, st = P.grad(X, T, c, sysm, kap, prm, U, lam, (U - Ut).contiguous(), mode=mode, tol=1e-12)
+        out[prec] = (J, U, lam, dlogk, dX)
+        print(f"precision {prec}: J={J:.10e} solve iters={sst['iters']} true rel. residual={sst['rel_res']:.2e} "
+              f"grad iters={st['iters']}", flush=True)
+        assert sst["rel_res"] <= 1e-10
+    J64, U64, lam64, g64, x64 = out[0]
+    J32, U32, _, g32, x32 = out[1]
+    assert float((U32 - U64).abs().max()) <= 1e-9 * float(U64.abs().max())
+    assert float((g32 - g64).abs().max()) <= 1e-6 * float(g64.abs().max())
+    assert float((x32 - x64).abs().max()) <= 1e-6 * float(x64.abs().max())
+    oprm = O.params(c=1.0, f=SIN3)
+    check_conservation(X, T, c, kap, oprm, U64, lam64, np.random.default_rng(41))
+
+
+def test_gradient_workload_central_differences(jittered5):
+    X, T, c, kap, Ut = jittered5
+    prm = P.params(c=1.0, f=SIN3, precision=0)
+    J, sysm, lam, U = J_of(X, T, c, kap, prm, 0, Ut, 1e-12)
+    dlogk, dX, _ = P.grad(X, T, c, sysm, kap, prm, U, lam, (U - Ut).contiguous(), mode=0, tol=1e-12)
+    # log kappa direction
+    d = smooth_tet_field(X, T)
+    eps = 2.5e-4  # central-difference truncation ~1e-7 relative; solver noise ~1e-8
+    Jp = J_of(X, T, c, kap * torch.exp(eps * d), prm, 0, Ut, 1e-12)[0]
+    Jm = J_of(X, T, c, kap * torch.exp(-eps * d), prm, 0, Ut, 1e-12)[0]
+    fd, an = (Jp - Jm) / (2 * eps), float((dlogk * d).sum())
+    print(f"log kappa: fd={fd:.10e} adjoint={an:.10e}", flush=True)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    # coordinate direction (every vertex, well below the mesh size)
+    dx = smooth_vertex_field(X)
+    eps = 1e-5
+    Jp = J_of(X + eps * dx, T, c, kap, prm, 0, Ut, 1e-12)[0]
+    Jm = J_of(X - eps * dx, T, c, kap, prm, 0, Ut, 1e-12)[0]
+    fd, an = (Jp - Jm) / (2 * eps), float((dX * dx).sum())
+    print(f"coordinates: fd={fd:.10e} adjoint={an:.10e}", flush=True)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+@pytest.fixture(scope="module")
+def fichera5():
+    X0, T0 = M.fichera()
+    X, T, c = P.refine_connected_levels(torch.tensor(X0, device=DEV), torch.tensor(T0, device=DEV), 5)
+    kap = torch.tensor(M.lognormal_kappa(T.shape[1], 0.5), device=DEV)
+    return X, T, c, kap
+
+
+def test_fichera_topology(fichera5):
+    X, T, c, _ = fichera5
+    check_topology(X, T, c, refined_counts(FICHERA0, 5), volume=7.0)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_fichera_condense_rows(fichera5, precision, tol):
+    X, T, c, kap = fichera5
+    f1 = (O.FUN_CONST, (1.0,))
+    sysm = P.condense(X, T, c, kap, P.params(c=1.0, f=f1, precision=precision))
+    check_rows(X, T, c, sysm, kap, O.params(c=1.0, kappa=1.0, f=f1), tol, np.random.default_rng(50 + precision))
+
+
+def test_fichera_mixed_solve_adjoint(fichera5):
+    X, T, c, kap = fichera5
+    f1 = (O.FUN_CONST, (1.0,))
+    prm = P.params(c=1.0, f=f1, precision=1)
+    J, sysm, lam, U = J_of(X, T, c, kap, prm, 1, 0.0, 1e-11)
+    check_conservation(X, T, c, kap, O.params(c=1.0, kappa=1.0, f=f1), U, lam, np.random.default_rng(51))
+    dlogk, _, st = P.grad(X, T, c, sysm, kap, prm, U, lam, U.contiguous(), mode=1, tol=1e-11, want_coord=False)
+    print(f"J={J:.10e} adjoint iters={st['iters']}", flush=True)
+    d = smooth_tet_field(X, T)
+    eps = 1e-3
+    Jp = J_of(X, T, c, kap * torch.exp(eps * d), prm, 1, 0.0, 1e-11)[0]
+    Jm = J_of(X, T, c, kap * torch.exp(-eps * d), prm, 1, 0.0, 1e-11)[0]
+    fd, an = (Jp - Jm) / (2 * eps), float((dlogk * d).sum())
+    print(f"log kappa: fd={fd:.10e} adjoint={an:.10e}", flush=True)
+    assert abs(fd - an) <= 1e-5 * abs(an)
