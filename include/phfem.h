@@ -275,7 +275,7 @@ enum { PHFEM_SOLVE_FP64_PCG = 0, PHFEM_SOLVE_FP32_PCG_FP64_IR = 1 };
 
 typedef struct {
   int32_t iters;    /* PCG iterations (all inner iterations in IR mode) */
-  int32_t ir_steps; /* outer refinement steps (IR mode) */
+  int32_t ir_steps; /* residual replacements (IR mode) / true-residual corrections (FP64 mode) */
   double rel_res;   /* final ||b_D - C U(lambda)|| / ||r+||, evaluated in FP64 matrix-free */
   double rhs_norm;  /* ||r+|| */
 } phfem_solve_stats;
@@ -287,7 +287,13 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  * (rowptr, col, val, diag, rhs) as phfem_condense writes them: 6 slots per row, rowptr[F] =
  * 6 F, column ids in [0, nF) -- checked on the device once per call (EINVAL otherwise); col
  * 8-byte and val 16-byte aligned (vector loads of a row's slots).
- *  mode FP64_PCG: PCG on the FP64 system to ||r|| <= tol ||r+||.
+ *  mode FP64_PCG: PCG on the FP64 system to ||r|| <= tol ||r+|| (recurrence residual); then,
+ *    while the true residual b_D - C U(lambda) (FP64, matrix-free) is above tol ||r+||, the
+ *    stored system is solved again for the correction (iterative refinement; the stored
+ *    system differs from the matrix-free operator by assembly rounding, so the recurrence
+ *    alone levels off near 3.5e-11 relative at Kuhn L5 with lognormal kappa).  Stops after 8
+ *    corrections or when one no longer halves the true residual; stats.rel_res is then the
+ *    attainable accuracy.
  *  mode FP32_PCG_FP64_IR: iterative refinement without restarts: one FP32 PCG recurrence on
  *    an FP32 copy of the system, whose residual is replaced by the true residual
  *    b_D - C U(lambda), recomputed per tet in FP64 from the geometry (not from the stored

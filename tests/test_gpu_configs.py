@@ -4,11 +4,10 @@ any size (the oracle cannot solve these meshes in seconds).
 * Kuhn cube, 5 levels (1,492,992 tets), interior vertices jittered by +-0.1 h, lognormal
   kappa (sigma 1), the kappa = 1 manufactured load, u_target = the FP64 solution at kappa = 1,
   J = 1/2 |U - u_target|^2: forward solve and adjoint in FP64 and in mixed precision, both
-  to 1e-12.  Both true (matrix-free FP64) residuals <= 1e-10; mixed u_h within 1e-9 of FP64
-  (the FP64 PCG stops on its recurrence residual, and the true residual of the stored FP64
-  system's solution levels off near 3.5e-11 on this mesh, which bounds the FP64 reference's
-  own accuracy; the mixed solver converges on the true residual and reaches 1e-12); mixed
-  gradients within 1e-6 of FP64 (relative to the largest entry); the FP64 gradients against
+  to a true (matrix-free FP64) relative residual of 1e-12 (the FP64 mode needs a
+  correction solve for it: its recurrence alone levels off near 3.5e-11 on this mesh);
+  mixed u_h within 1e-10 of FP64; mixed gradients within 1e-6 of FP64 (relative to the
+  largest entry); the FP64 gradients against
   central differences of J along smooth directions of log kappa and of the coordinates
   (1e-6; smooth, so that the directional derivative is not a cancelling sum of per-tet
   terms that solver noise would swamp); local conservation on sampled tets.
@@ -80,10 +79,12 @@ def test_gradient_workload_mixed_vs_fp64(jittered5):
         out[prec] = (J, U, lam, dlogk, dX)
         print(f"precision {prec}: J={J:.10e} solve iters={sst['iters']} true rel. residual={sst['rel_res']:.2e} "
               f"grad iters={st['iters']}", flush=True)
-        assert sst["rel_res"] <= 1e-10
+        assert sst["rel_res"] <= 1e-12
+        if prec == 0:
+            assert sst["ir_steps"] >= 1  # the recurrence alone does not reach 1e-12 here
     J64, U64, lam64, g64, x64 = out[0]
     J32, U32, _, g32, x32 = out[1]
-    assert float((U32 - U64).abs().max()) <= 1e-9 * float(U64.abs().max())
+    assert float((U32 - U64).abs().max()) <= 1e-10 * float(U64.abs().max())
     assert float((g32 - g64).abs().max()) <= 1e-6 * float(g64.abs().max())
     assert float((x32 - x64).abs().max()) <= 1e-6 * float(x64.abs().max())
     oprm = O.params(c=1.0, f=SIN3)
