@@ -301,7 +301,9 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  *    anything else means 0.7, measured best: rarer replacements let the FP32 recurrence
  *    drift from the true residual) since the last replacement; the FP32 iterate is then added to
  *    the FP64 solution and the search direction kept.  Stops when the true residual meets
- *    tol.  stats.ir_steps counts the replacements.
+ *    tol, or with ENOCONV when 6 replacements in a row gain less than 10 % (tol below the
+ *    attainable accuracy, about 6e-13 relative at Kuhn L5).  stats.ir_steps counts the
+ *    replacements.
  * Outputs: lambda[nF], U[4][nE] (float64).  Synchronizes (residual checks every few
  * iterations).  Errors: EINVAL, EDEGEN, ENOCONV (max_iter reached; outputs and stats hold
  * the last iterate), EWORKSPACE. */

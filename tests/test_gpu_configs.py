@@ -150,3 +150,15 @@ def test_fichera_mixed_solve_adjoint(fichera5):
     fd, an = (Jp - Jm) / (2 * eps), float((dlogk * d).sum())
     print(f"log kappa: fd={fd:.10e} adjoint={an:.10e}", flush=True)
     assert abs(fd - an) <= 1e-5 * abs(an)
+
+
+def test_mixed_solve_stagnation_reported(jittered5):
+    """A tolerance below the mixed mode's attainable accuracy ends with ENOCONV after a few
+    replacements without progress (not after max_iter), with the attained accuracy in the
+    stats."""
+    X, T, c, kap, _ = jittered5
+    prm = P.params(c=1.0, f=SIN3, precision=1)
+    sysm = P.condense(X, T, c, kap, prm)
+    lam, U, st = P.solve(X, T, c, sysm, kap, prm, mode=1, tol=1e-15, max_iter=400000, allow_noconv=True)
+    print(f"iters={st['iters']} replacements={st['ir_steps']} rel={st['rel_res']:.2e}", flush=True)
+    assert not st["converged"] and st["iters"] < 100000 and st["rel_res"] <= 1e-12
