@@ -201,12 +201,12 @@ def solve_block(torch, P, B, M, Ls):
         sysm = P.condense(X, T, conn, None, prm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lam, U, st = P.solve(X, T, conn, sysm, None, prm, mode=mode, tol=1e-10, inner_tol=0.7, max_iter=400000,
+        lam, U, st = P.solve(X, T, conn, sysm, None, prm, mode=mode, tol=1e-10, inner_tol=0.9, max_iter=400000,
                              allow_noconv=True)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         t0 = time.perf_counter()
-        dlogk, dX, st2 = P.grad(X, T, conn, sysm, None, prm, U, lam, U, mode=mode, tol=1e-10, inner_tol=0.7,
+        dlogk, dX, st2 = P.grad(X, T, conn, sysm, None, prm, U, lam, U, mode=mode, tol=1e-10, inner_tol=0.9,
                                 max_iter=400000)
         torch.cuda.synchronize()
         tg = time.perf_counter() - t0

@@ -298,8 +298,10 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  *    an FP32 copy of the system, whose residual is replaced by the true residual
  *    b_D - C U(lambda), recomputed per tet in FP64 from the geometry (not from the stored
  *    system), each time the FP32 residual has fallen by the factor inner_tol (in (0, 1);
- *    anything else means 0.7, measured best: rarer replacements let the FP32 recurrence
- *    drift from the true residual) since the last replacement; the FP32 iterate is then added to
+ *    anything else means 0.9, measured best: rarer replacements let the FP32 recurrence
+ *    drift from the true residual, which costs iterations as the condition number grows --
+ *    Kuhn L6 to 1e-10: 63.6K iterations at 0.9 against 83.4K at 0.7) since the last
+ *    replacement; the FP32 iterate is then added to
  *    the FP64 solution and the search direction kept.  Stops when the true residual meets
  *    tol, or with ENOCONV when 6 replacements in a row gain less than 10 % (tol below the
  *    attainable accuracy, about 6e-13 relative at Kuhn L5).  stats.ir_steps counts the

@@ -576,7 +576,7 @@ extern "C" int phfem_solve(int64_t nC, const double* coord, int64_t nE, const in
   MeshOp m{nC, nE, nF, coord, tetra, tet2face, sigma, kappa, to_dev(*p), nullptr, w.bD};
   rc = launch_face_init(nF, nC, coord, faces, face2tet, m.P, nullptr, nullptr, w.bD, s);
   if (rc) return rc;
-  if (!(inner_tol > 0 && inner_tol < 1)) inner_tol = 0.7;
+  if (!(inner_tol > 0 && inner_tol < 1)) inner_tol = 0.9;
   return face_solve(m, rowptr, col, val, diag, rhs, mode, tol, inner_tol, max_iter, w, lambda, U, stats, s);
 }
 
@@ -618,7 +618,7 @@ extern "C" int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int
   rc = launch_recover(nC, coord, nE, tetra, tet2face, sigma, kappa, P, nullptr, dJdU, Pv, radj, w.flags, s);
   if (rc) return rc;
   MeshOp m{nC, nE, nF, coord, tetra, tet2face, sigma, kappa, P, dJdU, nullptr};
-  if (!(inner_tol > 0 && inner_tol < 1)) inner_tol = 0.7;
+  if (!(inner_tol > 0 && inner_tol < 1)) inner_tol = 0.9;
   rc = face_solve(m, rowptr, col, val, diag, radj, mode, tol, inner_tol, max_iter, w, Q, Pv, stats, s);
   if (rc) return rc;  // Pv = A^-1 (dJdU + C'Q) on exit
   if (dJ_dcoord) PH_HIP(hipMemsetAsync(dJ_dcoord, 0, sizeof(double) * 3 * nC, s));

@@ -222,7 +222,7 @@ def condense_reuse(coord, tetra, conn, kappa, prm):
     return condense_batch(coord, tetra, conn, k, prm, pattern=conn["pattern"])[0]
 
 
-def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.7, max_iter=200000,
+def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.9, max_iter=200000,
           allow_noconv=False):
     """Face solve + recovery (a8-a9).  Returns (lambda, U, stats)."""
     dev = coord.device
@@ -241,7 +241,7 @@ def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, 
     return lam, U, stats
 
 
-def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.7,
+def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.9,
          max_iter=200000, want_coord=True):
     """Adjoint gradient (a10): (dJ/dlog kappa [nE], dJ/dX [3, nC], stats)."""
     dev = coord.device
