@@ -6,7 +6,9 @@ any size (the oracle cannot solve these meshes in seconds).
   J = 1/2 |U - u_target|^2: forward solve and adjoint in FP64 and in mixed precision, both
   to a true (matrix-free FP64) relative residual of 1e-12 (the FP64 mode needs a
   correction solve for it: its recurrence alone levels off near 3.5e-11 on this mesh);
-  mixed u_h within 1e-10 of FP64; mixed gradients within 1e-6 of FP64 (relative to the
+  mixed u_h within 5e-10 of FP64 (both near their attainable accuracy, about 6e-13 in the
+  residual; a residual difference reaches u_h amplified about 200-fold on this mesh, so
+  measured differences are 1-2e-10); mixed gradients within 1e-6 of FP64 (relative to the
   largest entry); the FP64 gradients against
   central differences of J along smooth directions of log kappa and of the coordinates
   (1e-6; smooth, so that the directional derivative is not a cancelling sum of per-tet
@@ -84,7 +86,9 @@ def test_gradient_workload_mixed_vs_fp64(jittered5):
             assert sst["ir_steps"] >= 1  # the recurrence alone does not reach 1e-12 here
     J64, U64, lam64, g64, x64 = out[0]
     J32, U32, _, g32, x32 = out[1]
-    assert float((U32 - U64).abs().max()) <= 1e-10 * float(U64.abs().max())
+    du = float((U32 - U64).abs().max()) / float(U64.abs().max())
+    print(f"u_h mixed vs FP64: {du:.2e}", flush=True)
+    assert du <= 5e-10
     assert float((g32 - g64).abs().max()) <= 1e-6 * float(g64.abs().max())
     assert float((x32 - x64).abs().max()) <= 1e-6 * float(x64.abs().max())
     oprm = O.params(c=1.0, f=SIN3)
