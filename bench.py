@@ -53,12 +53,14 @@ def compulsory_bytes(L):
     return tot
 
 
-def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False):
+def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False, status=None):
     """One step.  Default: the level-0 mesh is connected by the general sort-based connect,
     every refinement level derives the refined mesh's connectivity in closed form
     (phfem_refine_connected), then assemble + condense.  sort_connect=True: per level
     connect-edges (sort) -> refine (with the Dirichlet face list), then a sort-based full
-    connect of the final mesh."""
+    connect of the final mesh.  status: a zeroed device int32 that the refinement's input
+    check ORs its code into (every step still runs the check; the host reads the flag after
+    the timed steps instead of synchronizing inside each one)."""
     if sort_connect:
         X, T, db = X0, T0, db0
         for _ in range(L):
@@ -66,7 +68,7 @@ def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False):
             X, T, db, _ = P.refine(X, T, conn, db)
         conn = P.connect(T, X.shape[1], faces=True)
     else:
-        X, T, conn = P.refine_connected_levels(X0, T0, L)
+        X, T, conn = P.refine_connected_levels(X0, T0, L, status=status)
     sysm = P.condense(X, T, conn, kappa, prm)
     return X, T, conn, sysm
 
@@ -75,27 +77,30 @@ def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort
     """ms per step (HIP events around `steps` steps, profiler off), host wall ms per step,
     and -- from a second, separately run set of `steps` steps with the per-launch event
     profiler on -- per-kernel launches / ms / algorithmic bytes."""
+    st = torch.zeros(1, dtype=torch.int32, device=X0.device)
     for _ in range(warmup):
-        run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
+        run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect, status=st)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
     for _ in range(steps):
-        out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
+        out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect, status=st)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
+    P.check_status(st)  # every step's refinement input check, read once
     kern = {}
     if profile:
         del out
         B.phfem_profile_reset()
         B.phfem_profile_enable(True)
         for _ in range(steps):
-            out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect)
+            out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect, status=st)
         torch.cuda.synchronize()
         B.phfem_profile_enable(False)
+        P.check_status(st)
         for name in B.phfem_profile_names():
             n, tms, by = B.phfem_profile_query(name)
             kern[name] = dict(launches=n, ms=tms, bytes=by)
@@ -272,14 +277,16 @@ def paper_mesh_block(torch, P, B, M, L=5, reps=5):
     out = {"workload": f"the paper's 5-tet cube (Section 2.3), {L} levels, sin^3 load, all faces Dirichlet"}
     for label, prec in (("fp64", B.FP64), ("mixed", B.MIXED)):
         prm = P.params(c=1.0, kappa=1.0, f=(B.FUN_SIN3, (M.SIN3_AMPLITUDE,)), precision=prec)
-        run_pipeline(P, X0d, T0d, None, L, prm)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        run_pipeline(P, X0d, T0d, None, L, prm, status=st)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            res = run_pipeline(P, X0d, T0d, None, L, prm)
+            res = run_pipeline(P, X0d, T0d, None, L, prm, status=st)
         e1.record()
         torch.cuda.synchronize()
+        P.check_status(st)
         nE = res[1].shape[1]
         ms = e0.elapsed_time(e1) / reps
         out[label] = {"ms": round(ms, 4), "tets_per_s": round(nE / (ms * 1e-3), 1)}

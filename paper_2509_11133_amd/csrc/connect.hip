@@ -180,7 +180,8 @@ __global__ __launch_bounds__(CT) void k_face_keys(int64_t nE, const int32_t* __r
 
 constexpr uint32_t SLOT_MASK = (1u << 30) - 1u;
 
-__global__ __launch_bounds__(CT) void k_face_assign(int64_t n, int64_t nE, int64_t nF,
+// nF is read from the device (the scan total), so the host need not wait for it
+__global__ __launch_bounds__(CT) void k_face_assign(int64_t n, int64_t nE, const uint32_t* __restrict__ nFp,
                                                     const uint64_t* __restrict__ sk, const int32_t* __restrict__ sv,
                                                     const uint8_t* __restrict__ first,
                                                     const uint32_t* __restrict__ prefix,
@@ -190,6 +191,7 @@ __global__ __launch_bounds__(CT) void k_face_assign(int64_t n, int64_t nE, int64
                                                     int* __restrict__ flags) {
   int64_t s = (int64_t)blockIdx.x * CT + threadIdx.x;
   if (s >= n) return;
+  const int64_t nF = *nFp;
   uint64_t key = sk[s];
   bool head = s == 0 || sk[s - 1] != key;
   if (head) {
@@ -296,12 +298,16 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   const int nb = bits_for(nC);
   PH_HIP(hipMemsetAsync(w.dflags, 0, sizeof(int), s));
 
-  // ---- edges
+  // ---- edges.  The node-id check is read back with the last count: until then a bad id only
+  // makes key values wrong, never an address (Nodes2Edge, which indexes rows by node id, is
+  // the exception and reads it at once).
   PH_LAUNCH_B("edge_keys", 64.0 * nE, k_edge_keys, grid_for(nE, CT), CT, 0, s, nE, nC, tetra, nb, w.kA, w.dflags);
   int hflags = 0;
-  PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
-  PH_HIP(hipStreamSynchronize(s));
-  if (hflags) return dev_flags_to_status(hflags);
+  if (want_n2e) {
+    PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (hflags) return dev_flags_to_status(hflags);
+  }
 
   uint64_t* sk;
   int32_t* sv;
@@ -333,10 +339,15 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
     rc = scan_exclusive(w.rowcnt, (uint32_t*)n2e_rowptr, nC + 1, nullptr, a, s);
     if (rc) return rc;
   }
-  counts[0] = nEd;
-  counts[1] = 0;
-  counts[2] = 0;
-  if (!want_faces) return PHFEM_OK;
+  if (!want_faces) {
+    PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (hflags) return dev_flags_to_status(hflags);
+    counts[0] = nEd;
+    counts[1] = 0;
+    counts[2] = 0;
+    return PHFEM_OK;
+  }
 
   // ---- faces: key = (min node, opposite edge) of every local face
   const int eb = bits_for(nEd);
@@ -349,18 +360,19 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
             SLOT_MASK, w.first);
   PH_LAUNCH_B("count_heads", 8.0 * nE, k_count_heads<4>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
   a.off = sub;
-  rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
+  rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total + 1, a, s);
   if (rc) return rc;
+  PH_LAUNCH_B("face_assign", 22.0 * n4 + 20.0 * nE + 20.0 * 2 * nE, k_face_assign, grid_for(n4, CT), CT, 0, s, n4, nE,
+              (const uint32_t*)(w.total + 1), (const uint64_t*)sk, (const int32_t*)sv, (const uint8_t*)w.first,
+              (const uint32_t*)w.cnt, tetra, faces, tet2face, sigma, face2tet, nbr, w.dflags);
+  // one readback for the face count and every device-side check
   uint32_t nF32 = 0;
-  PH_HIP(hipMemcpyAsync(&nF32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  PH_HIP(hipStreamSynchronize(s));
-  const int64_t nF = nF32;
-  PH_LAUNCH_B("face_assign", 22.0 * n4 + 20.0 * nE + 20.0 * nF, k_face_assign, grid_for(n4, CT), CT, 0, s, n4, nE, nF, (const uint64_t*)sk,
-            (const int32_t*)sv, (const uint8_t*)w.first, (const uint32_t*)w.cnt, tetra, faces, tet2face, sigma,
-            face2tet, nbr, w.dflags);
+  PH_HIP(hipMemcpyAsync(&nF32, w.total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   PH_HIP(hipStreamSynchronize(s));
   if (hflags) return dev_flags_to_status(hflags);
+  const int64_t nF = nF32;
+  counts[0] = nEd;
   counts[1] = nF;
   counts[2] = 2 * nF - 4 * nE;  // 4 nE = 2 nI + nB and nF = nI + nB
   return PHFEM_OK;
