@@ -77,3 +77,34 @@ def test_validation_errors_on_host():
         rc = L.phfem_errors(8, 16, 6, 16, 18, 16, 16, None, C.addressof(p), 16, 16, 4, C.addressof(par), h, nq, 16,
                             1 << 20, C.addressof(out), None)
         assert rc == B.EINVAL
+
+
+def test_size_limits_on_host():
+    """Sizes beyond the int32 index ranges are refused before anything is enqueued (the
+    pointers below are never dereferenced)."""
+    L = B.lib()
+    counts = np.zeros(3, np.int64)
+    big = 1 << 27
+    rc = L.phfem_connect(8, big, 16, 3, 16, 1 << 40, *([16] * 12), counts.ctypes.data, None)
+    assert rc == B.EINVAL and b"too large" in L.phfem_last_error()
+    # one refinement of a 2^24-tet mesh: 6 nE' = 6 * 12 * 2^24 > 2^31
+    nE = 1 << 24
+    rc = L.phfem_refine_connected(4 * nE, 16, nE, 16, 2 * nE, 2 * nE, *([16] * 5), 16, 1 << 40, *([16] * 11),
+                                  counts.ctypes.data, None, None)
+    assert rc == B.EINVAL and b"index ranges" in L.phfem_last_error()
+    rc = L.phfem_refine(1 << 30, 16, nE * 16, 16, nE, *([16] * 3), None, None, None, 0, None, 0, None, 16, 16, None,
+                        None, None)
+    assert rc == B.EINVAL and b"int32" in L.phfem_last_error()
+    p = B.params(c=1.0)
+    nF = (1 << 31) // 6 + 1  # 6 nF >= 2^31
+    rc = L.phfem_condense(8, 16, 6, 16, nF, *([16] * 6), C.addressof(p), 16, 1 << 40, *([16] * 5), None)
+    assert rc == B.EINVAL and b"int32" in L.phfem_last_error()
+    rc = L.phfem_condense_batch(8, 16, 6, 16, 18, *([16] * 4), 0, 16, C.addressof(p), 16, 1 << 40, None, None, 16,
+                                16, 16, None)
+    assert rc == B.EINVAL  # nk < 1
+    rc = L.phfem_refine_connected_levels(8, 16, 6, 16, 19, 18, *([16] * 5), 17, 16, 1 << 40, *([16] * 11),
+                                         counts.ctypes.data, None, None)
+    assert rc == B.EINVAL and b"levels" in L.phfem_last_error()
+    out = np.zeros(4, np.int64)
+    assert L.phfem_refined_sizes(8, 6, 19, 18, -1, out.ctypes.data) == B.EINVAL
+    assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 17) == 0
