@@ -23,6 +23,7 @@ int launch_vjp(int64_t nC, const double* X, int64_t nE, const int32_t* tet, cons
 constexpr int ST = 256;
 constexpr int MAXG = 1024;
 constexpr int CHECK = 16;
+constexpr int REFRESH = 256;  // iterations between exact products q = A p (fused recurrence)
 
 static unsigned pcg_grid(int64_t n) {
   int64_t g = (n + ST - 1) / ST;
@@ -185,6 +186,52 @@ __global__ __launch_bounds__(ST) void k_pcg_dir(int64_t n, int G, const double* 
   }
 }
 
+// The direction update fused into the product: p = z + beta p and q = A z + beta q (= A p
+// by linearity, A p_old being the q of the previous iteration) in one pass over the rows,
+// with the partial dots p.q.  beta = (r.z)_new / (r.z)_old from the update kernel's
+// partials, 0 on the first iteration; block 0 stores (r.z)_new in scal[slot_old ^ 1] and
+// r.r in scal[2].  One kernel instead of two per iteration; the recurrence for q drifts
+// from A p by rounding, so the solver recomputes q = A p exactly at intervals.
+template <class T>
+__global__ __launch_bounds__(ST) void k_spmv_dir(int64_t n, const int32_t* __restrict__ col,
+                                                 const T* __restrict__ val, const T* __restrict__ diag,
+                                                 const T* __restrict__ z, T* __restrict__ p, T* __restrict__ q, int G,
+                                                 const double* __restrict__ part_rz,
+                                                 const double* __restrict__ part_rr, double* __restrict__ scal,
+                                                 int slot_old, int first, double* __restrict__ part_pq) {
+  using V2 = typename Vec2<T>::type;
+  __shared__ double lds[ST / 64];
+  const double rzn = sum_partials(part_rz, G, lds);
+  const double rr = sum_partials(part_rr, G, lds);
+  const T beta = first ? (T)0 : (T)(rzn / scal[slot_old]);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    const int2* c2 = reinterpret_cast<const int2*>(col + 6 * i);
+    const V2* v2 = reinterpret_cast<const V2*>(val + 6 * i);
+    const int2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
+    const V2 v01 = v2[0], v23 = v2[1], v45 = v2[2];
+    const T zi = z[i];
+    T s = diag[i] * zi;
+    s += v01.x * z[c01.x];
+    s += v01.y * z[c01.y];
+    s += v23.x * z[c23.x];
+    s += v23.y * z[c23.y];
+    s += v45.x * z[c45.x];
+    s += v45.y * z[c45.y];
+    const T pi = first ? zi : zi + beta * p[i];
+    const T qi = first ? s : s + beta * q[i];
+    p[i] = pi;
+    q[i] = qi;
+    acc += (double)pi * (double)qi;
+  }
+  double b = block_sum(acc, lds);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = b;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[slot_old ^ 1] = rzn;
+    scal[2] = rr;
+  }
+}
+
 __global__ __launch_bounds__(ST) void k_norm2(int64_t n, const double* __restrict__ v, double* __restrict__ part) {
   __shared__ double lds[ST / 64];
   double a = 0.0;
@@ -312,6 +359,27 @@ static int norm2(int64_t n, const double* v, PcgWS& w, double* out, hipStream_t 
   return rc;
 }
 
+// Direction step of iteration it (before its update): p = z + beta p and q = A p, fused
+// (k_spmv_dir) or, when `exact`, as the direction update followed by the plain product
+// (resets the drift of the fused recurrence).  scal[slot] receives the new r.z.
+template <class T>
+static int pcg_direction(int64_t n, const int32_t* col, const T* val, const T* diag, PcgWS& w, int slot, bool first,
+                         bool exact, hipStream_t s) {
+  const unsigned G = pcg_grid(n);
+  T *z = (T*)w.z, *p = (T*)w.p, *q = (T*)w.q;
+  if (exact && !first) {
+    PH_LAUNCH_B("pcg_dir", 3.0 * sizeof(T) * n, k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz,
+                (const double*)w.part_rr, w.scal, slot ^ 1, (const T*)z, p);
+    PH_LAUNCH_B("spmv_dot", (double)n * (3 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dot<T>, G, ST, 0, s, n,
+                col, val, diag, (const T*)p, q, w.part_pq);
+  } else {
+    PH_LAUNCH_B("spmv_dir", (double)n * (6 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dir<T>, G, ST, 0, s, n, col,
+                val, diag, (const T*)z, p, q, (int)G, (const double*)w.part_rz, (const double*)w.part_rr, w.scal,
+                slot ^ 1, first ? 1 : 0, w.part_pq);
+  }
+  return PHFEM_OK;
+}
+
 // PCG on the 6-slot system (col, val, diag) from x0 = 0; stops at ||r|| <= tol ||b|| or maxit.
 template <class T>
 static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const T* b, T* x,
@@ -331,14 +399,13 @@ static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const
   int slot = 0, it = 0;
   double rel = 1.0;
   while (it < maxit) {
-    PH_LAUNCH_B("spmv_dot", (double)n * (3 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dot<T>, G, ST, 0, s, n,
-                col, val, diag, (const T*)p, q, w.part_pq);
+    rc = pcg_direction<T>(n, col, val, diag, w, slot, it == 0, it > 0 && it % REFRESH == 0, s);
+    if (rc) return rc;
     PH_LAUNCH_B("pcg_update", 8.0 * sizeof(T) * n, k_pcg_update<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
               slot, x, r, (const T*)p, (const T*)q, diag, z, w.part_rz, w.part_rr);
-    PH_LAUNCH_B("pcg_dir", 3.0 * sizeof(T) * n, k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz, (const double*)w.part_rr,
-              w.scal, slot, (const T*)z, p);
     slot ^= 1;
     ++it;
+    // scal[2] holds r.r of the residual before this iteration's update (one iteration behind)
     if (it % CHECK == 0 || it == maxit) {
       double rr = 0;
       rc = read_scalar(w.scal + 2, &rr, s);
@@ -471,7 +538,7 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
             pw.scal, 0);
   double ref = r0, rel = 1.0, best = r0;
   int slot = 0, it = 0, steps = 0, stall = 0;
-  bool replace = false, done = false;
+  bool replace = false, done = false, exact = false;
   while (!done) {
     // below the attainable accuracy the true residual stops falling: 6 replacements in a row
     // without a 10 % gain end the solve early (as max_iter would, with the same error)
@@ -484,8 +551,10 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
                                              "reached; stats.rel_res holds it)"
                                            : "mixed refinement reached max_iter above tolerance");
     }
-    PH_LAUNCH_B("spmv_dot", (double)nF * (3 * 4) + 6.0 * nF * (4 + 4), k_spmv_dot<float>, G, ST, 0, s, nF, col,
-                (const float*)w.val32, (const float*)w.diag32, (const float*)p, q, pw.part_pq);
+    // direction step (exact product after a replacement and every REFRESH iterations)
+    rc = pcg_direction<float>(nF, col, w.val32, w.diag32, pw, slot, it == 0, exact || (it > 0 && it % REFRESH == 0), s);
+    if (rc) return rc;
+    exact = false;
     PH_LAUNCH_B("pcg_update", 8.0 * 4 * nF, k_pcg_update<float>, G, ST, 0, s, nF, (int)G, (const double*)pw.part_pq,
                 (const double*)pw.scal, slot, w.x32, r32, (const float*)p, (const float*)q, (const float*)w.diag32, z,
                 pw.part_rz, pw.part_rr);
@@ -510,11 +579,10 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
         PH_LAUNCH("replace", k_replace<false>, G, ST, 0, s, nF, (const double*)w.r64, (const float*)w.diag32, r32,
                   z, p, w.x32, pw.part_rz, pw.part_rr);
         ref = rn;
+        exact = true;
       }
       replace = false;
     }
-    PH_LAUNCH_B("pcg_dir", 3.0 * 4 * nF, k_pcg_dir<float>, G, ST, 0, s, nF, (int)G, (const double*)pw.part_rz,
-                (const double*)pw.part_rr, pw.scal, slot, (const float*)z, p);
     slot ^= 1;
     ++it;
     if (!done && it % CHECK == 0) {
