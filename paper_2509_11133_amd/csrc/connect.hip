@@ -98,7 +98,8 @@ __device__ __forceinline__ int64_t find_head(int64_t s, bool valid, uint64_t key
   return h;
 }
 
-__global__ __launch_bounds__(CT) void k_edge_assign(int64_t n, int64_t nE, int64_t nEd, int nb,
+// nEd is read from the device (the scan total)
+__global__ __launch_bounds__(CT) void k_edge_assign(int64_t n, int64_t nE, const uint32_t* __restrict__ nEdp, int nb,
                                                     const uint64_t* __restrict__ sk, const int32_t* __restrict__ sv,
                                                     const uint8_t* __restrict__ first,
                                                     const uint32_t* __restrict__ prefix,
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(CT) void k_edge_assign(int64_t n, int64_t nE, int64
   int j = (int)(p - 6 * t);
   tet2edge[j * nE + t] = id;
   if (head) {
+    const int64_t nEd = *nEdp;
     edges[id] = (int32_t)(key >> nb);
     edges[nEd + id] = (int32_t)(key & ((1ull << nb) - 1ull));
     eft[id] = (int32_t)t;
@@ -320,14 +322,22 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   a.off = sub;
   rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
   if (rc) return rc;
-  uint32_t nEd32 = 0;
-  PH_HIP(hipMemcpyAsync(&nEd32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  PH_HIP(hipStreamSynchronize(s));
-  const int64_t nEd = nEd32;
+  // The edge count sizes the face keys' edge field.  A small mesh takes a bound instead
+  // (min(6 nE, nC (nC - 1) / 2) distinct node pairs) and reads the count back with the face
+  // count at the end, one host round trip fewer; a large mesh reads it here, since a loose
+  // bound could add a radix pass there.
+  const bool small = nE <= (int64_t(1) << 16);
+  int64_t nEd = -1;
+  if (!small) {
+    uint32_t nEd32 = 0;
+    PH_HIP(hipMemcpyAsync(&nEd32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    nEd = nEd32;
+  }
   PH_HIP(hipMemcpyAsync(tet_edge_prefix, w.cnt, sizeof(int32_t) * nE, hipMemcpyDeviceToDevice, s));
-  PH_LAUNCH_B("edge_assign", 17.0 * n6 + 12.0 * nEd + 4.0 * nE, k_edge_assign, grid_for(n6, CT), CT, 0, s, n6, nE, nEd, nb, (const uint64_t*)sk,
-            (const int32_t*)sv, (const uint8_t*)w.first, (const uint32_t*)w.cnt, tet2edge, edges, edge_first_tet,
-            w.flag);
+  PH_LAUNCH_B("edge_assign", 17.0 * n6 + 12.0 * (nEd >= 0 ? nEd : 1.2 * nE) + 4.0 * nE, k_edge_assign,
+              grid_for(n6, CT), CT, 0, s, n6, nE, (const uint32_t*)w.total, nb, (const uint64_t*)sk, (const int32_t*)sv,
+              (const uint8_t*)w.first, (const uint32_t*)w.cnt, tet2edge, edges, edge_first_tet, w.flag);
   if (want_n2e) {
     a.off = sub;
     rc = scan_exclusive(w.flag, w.flag, n6, nullptr, a, s);  // in place: head flag -> unique rank
@@ -340,17 +350,19 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
     if (rc) return rc;
   }
   if (!want_faces) {
+    uint32_t nEd32 = 0;
+    PH_HIP(hipMemcpyAsync(&nEd32, w.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
     PH_HIP(hipStreamSynchronize(s));
     if (hflags) return dev_flags_to_status(hflags);
-    counts[0] = nEd;
+    counts[0] = nEd32;
     counts[1] = 0;
     counts[2] = 0;
     return PHFEM_OK;
   }
 
   // ---- faces: key = (min node, opposite edge) of every local face
-  const int eb = bits_for(nEd);
+  const int eb = bits_for(nEd >= 0 ? nEd : std::min<int64_t>(n6, nC * (nC - 1) / 2));
   PH_LAUNCH_B("face_keys", 88.0 * nE, k_face_keys, grid_for(nE, CT), CT, 0, s, nE, tetra, (const int32_t*)tet2edge, eb, w.kA,
             w.vA);
   a.off = sub;
@@ -365,14 +377,14 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   PH_LAUNCH_B("face_assign", 22.0 * n4 + 20.0 * nE + 20.0 * 2 * nE, k_face_assign, grid_for(n4, CT), CT, 0, s, n4, nE,
               (const uint32_t*)(w.total + 1), (const uint64_t*)sk, (const int32_t*)sv, (const uint8_t*)w.first,
               (const uint32_t*)w.cnt, tetra, faces, tet2face, sigma, face2tet, nbr, w.dflags);
-  // one readback for the face count and every device-side check
-  uint32_t nF32 = 0;
-  PH_HIP(hipMemcpyAsync(&nF32, w.total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  // one readback for the counts and every device-side check
+  uint32_t tot[2] = {0, 0};
+  PH_HIP(hipMemcpyAsync(tot, w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PH_HIP(hipMemcpyAsync(&hflags, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   PH_HIP(hipStreamSynchronize(s));
   if (hflags) return dev_flags_to_status(hflags);
-  const int64_t nF = nF32;
-  counts[0] = nEd;
+  const int64_t nF = tot[1];
+  counts[0] = tot[0];
   counts[1] = nF;
   counts[2] = 2 * nF - 4 * nE;  // 4 nE = 2 nI + nB and nF = nI + nB
   return PHFEM_OK;
