@@ -212,7 +212,6 @@ template <int C>
 __device__ __forceinline__ int rowc(int nE, int tt) { return C == 0 ? tt : nE + 11 * tt + (C - 1); }
 // order of the rows of one tet's children: child 0 first, then 1..11
 __host__ __device__ constexpr int rord(int c) { return c == 0 ? -1 : c; }
-__device__ __forceinline__ int loc4v(const int4& v, int x) { return v.x == x ? 0 : (v.y == x ? 1 : (v.z == x ? 2 : 3)); }
 
 // Both passes run one workgroup per RCW coarse tets: wave c handles child c of all of them,
 // so the child index is uniform across a wave and every rule above resolves at compile time
@@ -234,15 +233,30 @@ __device__ __forceinline__ void sfor(F&& f) {
   sfor_(f, std::make_integer_sequence<int, N>{});
 }
 
+// Values of a coarse tet that several of its 12 child rows look up, gathered once per
+// workgroup into LDS (item q of the workgroup's tet l at sh[q RCW + l]) rather than by each of
+// the 12 waves:
+//  QM + k       coarse face k: bits 2i, 2i+1 = position of local vertex i in the tet across
+//               face k (the tet itself on the boundary), bits 8, 9 = position of face k there
+//  QMI + 2j + s minI[2 e_j + s]
+//  QEF + j      efp[e_j]
+//  QFT + j      eft[e_j]       (pass 2 only)
+//  QPR          pre[t]         (pass 2 only)
+constexpr int QM = 0, QMI = 4, QEF = 16, QFT = 22, QPR = 28;
+constexpr int NQ1 = 22, NQ2 = 29;  // items of pass 1 and pass 2
+
 // coarse tet data of one lane
 struct CT {
   int t;
   int n[4], f[4], nb[4], e[6];
+  const int* sh;  // this tet's column of the shared items
+  __device__ __forceinline__ int item(int q) const { return sh[q * RCW]; }
 };
-__device__ __forceinline__ void load_ct(const RCArgs& A, int t, CT& T) {
+__device__ __forceinline__ void load_ct(const RCArgs& A, int t, const int* sh, CT& T) {
   const uint32_t u = (uint32_t)t;
   const int4 a = ldu(A.T4, u), b = ldu(A.F4, u), c = ldu(A.N4, u), d = ldu(A.E8, 2 * u), e = ldu(A.E8, 2 * u + 1);
   T.t = t;
+  T.sh = sh;
   T.n[0] = a.x, T.n[1] = a.y, T.n[2] = a.z, T.n[3] = a.w;
   T.f[0] = b.x, T.f[1] = b.y, T.f[2] = b.z, T.f[3] = b.w;
   T.nb[0] = c.x, T.nb[1] = c.y, T.nb[2] = c.z, T.nb[3] = c.w;
@@ -250,6 +264,42 @@ __device__ __forceinline__ void load_ct(const RCArgs& A, int t, CT& T) {
 }
 // the neighbour across coarse face k, or the tet itself (a valid address) on the boundary
 __device__ __forceinline__ int nb_or_self(const CT& T, int k) { return T.nb[k] >= 0 ? T.nb[k] : T.t; }
+__device__ __forceinline__ int loc4v(const int4& v, int x) { return v.x == x ? 0 : (v.y == x ? 1 : (v.z == x ? 2 : 3)); }
+
+// the first NQ shared items of the workgroup's tets: wave w fills items w, w + 12, ...
+template <int NQ>
+__device__ __forceinline__ void gather_items(const RCArgs& A, int t0, int nb, int* sh) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (lane >= nb) return;
+  const uint32_t t = (uint32_t)(t0 + lane);
+  const int32_t* E = reinterpret_cast<const int32_t*>(A.E8);  // e_j at 8 t + j
+#pragma unroll
+  for (int i = 0; i < (NQ + RCB / 64 - 1) / (RCB / 64); ++i) {
+    const int q = w + i * (RCB / 64);
+    if (q >= NQ) break;
+    int v;
+    if (q < QMI) {
+      const int k = q;
+      const int nk = ldu(reinterpret_cast<const int32_t*>(A.N4), 4 * t + k);
+      const uint32_t tn = nk >= 0 ? (uint32_t)nk : t;
+      const int4 own = ldu(A.T4, t), nn = ldu(A.T4, tn), nf = ldu(A.F4, tn);
+      const int fk = ldu(reinterpret_cast<const int32_t*>(A.F4), 4 * t + k);
+      v = loc4v(nn, own.x) | (loc4v(nn, own.y) << 2) | (loc4v(nn, own.z) << 4) | (loc4v(nn, own.w) << 6) |
+          (loc4v(nf, fk) << 8);
+    } else if (q < QEF) {
+      const int j = (q - QMI) >> 1, s = (q - QMI) & 1;
+      v = ldu(A.minI, (uint32_t)(2 * ldu(E, 8 * t + j) + s));
+    } else if (q < QFT) {
+      v = ldu(A.efp, (uint32_t)ldu(E, 8 * t + (q - QEF)));
+    } else if (q < QPR) {
+      v = ldu(A.eft, (uint32_t)ldu(E, 8 * t + (q - QFT)));
+    } else {
+      v = ldu(A.pre, t);
+    }
+    sh[q * RCW + lane] = v;
+  }
+}
 
 // first occurrence (row, local edge) of local edge J of child C
 template <int C, int J>
@@ -262,11 +312,11 @@ __device__ __forceinline__ void efirst(const RCArgs& A, const CT& T, int& er, in
     ej = first3(lo - 4, true);
   } else if constexpr (lo < 4) {  // (V_lo, M_j): half of coarse edge e_j at node v
     constexpr int j = hi - 4;
-    const int e = T.e[j], v = T.n[lo];
+    const int v = T.n[lo];
     const int na = T.n[ev0(j)], nb = T.n[ev1(j)];
     const bool vlo = v == (na < nb ? na : nb);
-    const int mi = ldu(A.minI, (uint32_t)(2 * e + (vlo ? 0 : 1)));
-    const int p0 = ldu(A.efp, (uint32_t)e);
+    const int mi = T.sh[(QMI + 2 * j + (vlo ? 0 : 1)) * RCW];  // minI of that end of e_j
+    const int p0 = T.item(QEF + j);
     // child 0 of the lowest tet whose vertex I is v (local edge j of (I, m_j)), else the
     // corner child of v in the first tet of e
     const int flip = p0 & 1, p = p0 >> 1;
@@ -282,8 +332,8 @@ __device__ __forceinline__ void efirst(const RCArgs& A, const CT& T, int& er, in
     constexpr int k = face_with(v, a, b);
     constexpr int jr = eidx(posv(v, i), posv(v, j));
     const int rr = rowc<v>(nE, T.t);
-    const int4 nn = ldu(A.T4, (uint32_t)(nb_or_self(T, k)));
-    const int v2 = loc4v(nn, T.n[v]), a2 = loc4v(nn, T.n[a]), b2 = loc4v(nn, T.n[b]);
+    const int mp = T.item(QM + k);  // positions of V_v, V_a, V_b in the tet across face k
+    const int v2 = (mp >> (2 * v)) & 3, a2 = (mp >> (2 * a)) & 3, b2 = (mp >> (2 * b)) & 3;
     const int le2 = eidx_r(posv_r(v2, eidx_r(v2, a2)), posv_r(v2, eidx_r(v2, b2)));
     const int r2 = rowof(nE, nb_or_self(T, k), v2);
     const bool there = T.nb[k] >= 0 && 6 * r2 + le2 < 6 * rr + jr;
@@ -320,12 +370,13 @@ __device__ __forceinline__ void fother(const RCArgs& A, const CT& T, int& fr, in
   } else {
     constexpr int k = fcoarse(C, K);
     const int tn = nb_or_self(T, k);
-    const int k2 = loc4v(ldu(A.F4, (uint32_t)tn), T.f[k]);
+    const int mp = T.item(QM + k);
+    const int k2 = (mp >> 8) & 3;
     if constexpr (kind == 2) {
       fr = rowof(nE, tn, 8 + k2);
       fk = 0;
     } else {
-      const int v2 = loc4v(ldu(A.T4, (uint32_t)tn), T.n[C]);  // corner child C holds vertex V_C
+      const int v2 = (mp >> (2 * C)) & 3;  // corner child C holds vertex V_C
       fr = rowof(nE, tn, v2);
       fk = cornerface(v2, k2);
     }
@@ -348,9 +399,9 @@ __device__ __forceinline__ int sym_node(const RCArgs& A, const CT& T) {
     return T.n[S];
   } else if constexpr (S < 10) {
     const int e = T.e[S - 4];
-    return (int)A.nC + ldu(A.eft, (uint32_t)e) + e + 1;
+    return (int)A.nC + T.item(QFT + S - 4) + e + 1;
   } else {
-    return (int)A.nC + T.t + ldu(A.pre, (uint32_t)T.t);
+    return (int)A.nC + T.t + T.item(QPR);
   }
 }
 
@@ -388,12 +439,15 @@ __device__ __forceinline__ bool rc_flush_slot(const RCArgs& A, const RCBlock& B,
 __global__ __launch_bounds__(RCB) void k_rc_pass1(RCArgs A) {
   __shared__ uint32_t sE[RCW * RCS], sF[RCW * RCS];
   __shared__ uint32_t lw[RCB / 64];
+  __shared__ int sh[NQ1 * RCW];
   const RCBlock B = rc_block(A);
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  CT T;  // loaded before the shared items so that both gathers are in flight together
+  if (lane < B.nb) load_ct(A, B.t0 + lane, sh + lane, T);
+  gather_items<NQ1>(A, B.t0, B.nb, sh);
+  __syncthreads();
   if (lane < B.nb) {
-    CT T;
-    load_ct(A, B.t0 + lane, T);
     sfor<12>([&](auto Cc) {
       constexpr int C = decltype(Cc)::value;
       if (c != C) return;
@@ -472,6 +526,7 @@ struct RCRange {  // one row range's first-seen edges and faces: [e0, e0 + ne), 
 __global__ __launch_bounds__(RCB) __attribute__((amdgpu_waves_per_eu(6))) void k_rc_pass2(RCArgs A) {
   __shared__ int32_t sW[RCL];
   __shared__ RCRange sR[2];
+  __shared__ int sh[NQ2 * RCW];
   const RCBlock B = rc_block(A);
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -496,9 +551,11 @@ __global__ __launch_bounds__(RCB) __attribute__((amdgpu_waves_per_eu(6))) void k
   // owned face (its edge and face ids and vertex node ids are read back from LDS)
   int me = 0, mf = 0, r = 0;
   int fnb[4];
+  CT T;
+  if (lane < B.nb) load_ct(A, B.t0 + lane, sh + lane, T);
+  gather_items<NQ2>(A, B.t0, B.nb, sh);
+  __syncthreads();
   if (lane < B.nb) {
-    CT T;
-    load_ct(A, B.t0 + lane, T);
     sfor<12>([&](auto Cc) {
       constexpr int C = decltype(Cc)::value;
       if (c != C) return;
