@@ -295,13 +295,15 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  *    corrections or when one no longer halves the true residual; stats.rel_res is then the
  *    attainable accuracy.
  *  mode FP32_PCG_FP64_IR: iterative refinement without restarts: one FP32 PCG recurrence on
- *    an FP32 copy of the system, whose residual is replaced by the true residual
- *    b_D - C U(lambda), recomputed per tet in FP64 from the geometry (not from the stored
- *    system), each time the FP32 residual has fallen by the factor inner_tol (in (0, 1);
- *    anything else means 0.9, measured best: rarer replacements let the FP32 recurrence
- *    drift from the true residual, which costs iterations as the condition number grows --
- *    Kuhn L6 to 1e-10: 63.6K iterations at 0.9 against 83.4K at 0.7) since the last
- *    replacement; the FP32 iterate is then added to
+ *    the Jacobi-scaled FP32 copy D^-1/2 S+ D^-1/2 of the system (unit diagonal, so CG there
+ *    is Jacobi-PCG on S+ with no diagonal reads and no z vector), whose residual is
+ *    replaced by the scaled true residual D^-1/2 (b_D - C U(lambda)), recomputed per tet in
+ *    FP64 from the geometry (not from the stored system), each time the FP32 residual has
+ *    fallen by the factor inner_tol in the scaled 2-norm (in (0, 1); anything else means
+ *    0.9, measured best: rarer replacements let the FP32 recurrence drift from the true
+ *    residual, which costs iterations as the condition number grows -- Kuhn L6 to 1e-10:
+ *    63.6K iterations at 0.9 against 83.4K at 0.7) since the last replacement; the FP32
+ *    iterate, scaled back by D^-1/2, is then added to
  *    the FP64 solution and the search direction kept.  Stops when the true residual meets
  *    tol, or with ENOCONV when 6 replacements in a row gain less than 10 % (tol below the
  *    attainable accuracy, about 6e-13 relative at Kuhn L5).  stats.ir_steps counts the

@@ -50,7 +50,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 }
 
 // The face system's fixed 6-slot rows (rowptr[i] = 6 i, as phfem_condense writes them):
-// y = (D + offdiag) x and the partial dots x.y.  A row's 6 column ids and values are read as
+// y = (D + offdiag) x and the partial dots x.y (UNIT: a unit diagonal, not read).  A row's 6 column ids and values are read as
 // three 8-byte (int2) and three 16- or 8-byte (double2 / float2) vector loads; the products
 // are summed in slot order, as a plain CSR loop would.
 template <class T>
@@ -64,7 +64,7 @@ struct Vec2<float> {
   using type = float2;
 };
 
-template <class T>
+template <class T, bool UNIT>
 __global__ __launch_bounds__(ST) void k_spmv_dot(int64_t n, const int32_t* __restrict__ col,
                                                  const T* __restrict__ val, const T* __restrict__ diag,
                                                  const T* __restrict__ x, T* __restrict__ y,
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(ST) void k_spmv_dot(int64_t n, const int32_t* __res
     const int2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
     const V2 v01 = v2[0], v23 = v2[1], v45 = v2[2];
     const T xi = x[i];
-    T s = diag[i] * xi;
+    T s = UNIT ? xi : diag[i] * xi;
     s += v01.x * x[c01.x];
     s += v01.y * x[c01.y];
     s += v23.x * x[c23.x];
@@ -142,7 +142,8 @@ __global__ __launch_bounds__(ST) void k_scalars(int G, const double* __restrict_
   }
 }
 
-template <class T>
+// UNIT: the system has a unit diagonal (Jacobi-scaled), so z = r is not stored
+template <class T, bool UNIT>
 __global__ __launch_bounds__(ST) void k_pcg_update(int64_t n, int G, const double* __restrict__ part_pq,
                                                    const double* __restrict__ scal, int slot, T* __restrict__ x,
                                                    T* __restrict__ r, const T* __restrict__ p,
@@ -158,8 +159,11 @@ __global__ __launch_bounds__(ST) void k_pcg_update(int64_t n, int G, const doubl
     x[i] += alpha * p[i];
     T ri = r[i] - alpha * q[i];
     r[i] = ri;
-    T zi = ri / diag[i];
-    z[i] = zi;
+    T zi = ri;
+    if (!UNIT) {
+      zi = ri / diag[i];
+      z[i] = zi;
+    }
     arz += (double)ri * (double)zi;
     arr += (double)ri * (double)ri;
   }
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(ST) void k_pcg_dir(int64_t n, int G, const double* 
 // partials, 0 on the first iteration; block 0 stores (r.z)_new in scal[slot_old ^ 1] and
 // r.r in scal[2].  One kernel instead of two per iteration; the recurrence for q drifts
 // from A p by rounding, so the solver recomputes q = A p exactly at intervals.
-template <class T>
+template <class T, bool UNIT>
 __global__ __launch_bounds__(ST) void k_spmv_dir(int64_t n, const int32_t* __restrict__ col,
                                                  const T* __restrict__ val, const T* __restrict__ diag,
                                                  const T* __restrict__ z, T* __restrict__ p, T* __restrict__ q, int G,
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(ST) void k_spmv_dir(int64_t n, const int32_t* __res
     const int2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
     const V2 v01 = v2[0], v23 = v2[1], v45 = v2[2];
     const T zi = z[i];
-    T s = diag[i] * zi;
+    T s = UNIT ? zi : diag[i] * zi;
     s += v01.x * z[c01.x];
     s += v01.y * z[c01.y];
     s += v23.x * z[c23.x];
@@ -246,8 +250,17 @@ __global__ __launch_bounds__(ST) void k_sum1(int G, const double* __restrict__ p
   if (threadIdx.x == 0) *out = a;
 }
 
-__global__ __launch_bounds__(ST) void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
-  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) b[i] = (float)a[i];
+// The Jacobi-scaled FP32 copy of the system, D^-1/2 (D + offdiag) D^-1/2 with its unit
+// diagonal implied: val32[6 i + q] = val[6 i + q] / sqrt(d_i d_col), rounded once from FP64.
+// CG on it is Jacobi-PCG on the original system (iterates scaled by D^1/2) without the
+// diagonal reads and the z vector.
+__global__ __launch_bounds__(ST) void k_scale_f32(int64_t n, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, const double* __restrict__ diag,
+                                                  float* __restrict__ val32) {
+  for (int64_t k = (int64_t)blockIdx.x * ST + threadIdx.x; k < 6 * n; k += (int64_t)gridDim.x * ST) {
+    const int64_t i = k / 6;
+    val32[k] = (float)(val[k] / std::sqrt(diag[i] * diag[col[k]]));
+  }
 }
 
 __global__ __launch_bounds__(ST) void k_add_f32(int64_t n, const float* __restrict__ d, double* __restrict__ x) {
@@ -258,39 +271,37 @@ __global__ __launch_bounds__(ST) void k_add_f64(int64_t n, const double* __restr
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) x[i] += d[i];
 }
 
-// residual replacement of the FP32 recurrence: r32 = (float) r64, z = r32 / diag; with
-// init also p = z, x32 = 0.  Partial r.z and r.r as k_pcg_update leaves them.
+// residual replacement of the scaled FP32 recurrence: r32 = (float) D^-1/2 r64; with init
+// also p = r32, x32 = 0.  Partial r.r (= r.z of the unscaled system) into both partial
+// arrays, as k_pcg_update<float, true> leaves them.
 template <bool INIT>
 __global__ __launch_bounds__(ST) void k_replace(int64_t n, const double* __restrict__ r64,
-                                                const float* __restrict__ diag, float* __restrict__ r,
-                                                float* __restrict__ z, float* __restrict__ p, float* __restrict__ x32,
+                                                const double* __restrict__ diag, float* __restrict__ r,
+                                                float* __restrict__ p, float* __restrict__ x32,
                                                 double* __restrict__ part_rz, double* __restrict__ part_rr) {
   __shared__ double lds[ST / 64];
-  double arz = 0.0, arr = 0.0;
+  double arr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
-    const float ri = (float)r64[i];
-    const float zi = ri / diag[i];
+    const float ri = (float)(r64[i] / std::sqrt(diag[i]));
     r[i] = ri;
-    z[i] = zi;
     if (INIT) {
-      p[i] = zi;
+      p[i] = ri;
       x32[i] = 0.0f;
     }
-    arz += (double)ri * (double)zi;
     arr += (double)ri * (double)ri;
   }
-  double s1 = block_sum(arz, lds);
   double s2 = block_sum(arr, lds);
   if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = s1;
+    part_rz[blockIdx.x] = s2;
     part_rr[blockIdx.x] = s2;
   }
 }
 
-// x += x32, x32 = 0
-__global__ __launch_bounds__(ST) void k_flush_x(int64_t n, float* __restrict__ x32, double* __restrict__ x) {
+// x += D^-1/2 x32 (the scaled iterate back in the original unknowns), x32 = 0
+__global__ __launch_bounds__(ST) void k_flush_x(int64_t n, const double* __restrict__ diag, float* __restrict__ x32,
+                                                double* __restrict__ x) {
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
-    x[i] += (double)x32[i];
+    x[i] += (double)x32[i] / std::sqrt(diag[i]);
     x32[i] = 0.0f;
   }
 }
@@ -320,7 +331,7 @@ static void pcg_layout(Arena& a, int64_t n, PcgWS& w) {
 struct SolveWS {
   PcgWS pcg;
   double *bD, *r64, *e64;
-  float *val32, *diag32, *b32, *x32;
+  float *val32, *x32;
   int* flags;
 };
 
@@ -334,11 +345,9 @@ static void solve_layout(Arena& a, int64_t nF, int32_t mode, SolveWS& w) {
   w.e64 = mode == PHFEM_SOLVE_FP32_PCG_FP64_IR ? nullptr : a.take<double>(nF);
   if (mode == PHFEM_SOLVE_FP32_PCG_FP64_IR) {
     w.val32 = a.take<float>(6 * nF);
-    w.diag32 = a.take<float>(nF);
-    w.b32 = a.take<float>(nF);
     w.x32 = a.take<float>(nF);
   } else {
-    w.val32 = w.diag32 = w.b32 = w.x32 = nullptr;
+    w.val32 = w.x32 = nullptr;
   }
   w.flags = a.take<int>(16);
 }
@@ -362,18 +371,20 @@ static int norm2(int64_t n, const double* v, PcgWS& w, double* out, hipStream_t 
 // Direction step of iteration it (before its update): p = z + beta p and q = A p, fused
 // (k_spmv_dir) or, when `exact`, as the direction update followed by the plain product
 // (resets the drift of the fused recurrence).  scal[slot] receives the new r.z.
-template <class T>
+template <class T, bool UNIT>
 static int pcg_direction(int64_t n, const int32_t* col, const T* val, const T* diag, PcgWS& w, int slot, bool first,
                          bool exact, hipStream_t s) {
   const unsigned G = pcg_grid(n);
-  T *z = (T*)w.z, *p = (T*)w.p, *q = (T*)w.q;
+  T *z = UNIT ? (T*)w.r : (T*)w.z, *p = (T*)w.p, *q = (T*)w.q;
   if (exact && !first) {
     PH_LAUNCH_B("pcg_dir", 3.0 * sizeof(T) * n, k_pcg_dir<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_rz,
                 (const double*)w.part_rr, w.scal, slot ^ 1, (const T*)z, p);
-    PH_LAUNCH_B("spmv_dot", (double)n * (3 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dot<T>, G, ST, 0, s, n,
+    PH_LAUNCH_B("spmv_dot", (double)n * ((UNIT ? 2 : 3) * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), (k_spmv_dot<T, UNIT>),
+                G, ST, 0, s, n,
                 col, val, diag, (const T*)p, q, w.part_pq);
   } else {
-    PH_LAUNCH_B("spmv_dir", (double)n * (6 * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), k_spmv_dir<T>, G, ST, 0, s, n, col,
+    PH_LAUNCH_B("spmv_dir", (double)n * ((UNIT ? 5 : 6) * sizeof(T)) + 6.0 * n * (4 + sizeof(T)), (k_spmv_dir<T, UNIT>),
+                G, ST, 0, s, n, col,
                 val, diag, (const T*)z, p, q, (int)G, (const double*)w.part_rz, (const double*)w.part_rr, w.scal,
                 slot ^ 1, first ? 1 : 0, w.part_pq);
   }
@@ -399,9 +410,9 @@ static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const
   int slot = 0, it = 0;
   double rel = 1.0;
   while (it < maxit) {
-    rc = pcg_direction<T>(n, col, val, diag, w, slot, it == 0, it > 0 && it % REFRESH == 0, s);
+    rc = pcg_direction<T, false>(n, col, val, diag, w, slot, it == 0, it > 0 && it % REFRESH == 0, s);
     if (rc) return rc;
-    PH_LAUNCH_B("pcg_update", 8.0 * sizeof(T) * n, k_pcg_update<T>, G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
+    PH_LAUNCH_B("pcg_update", 8.0 * sizeof(T) * n, (k_pcg_update<T, false>), G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
               slot, x, r, (const T*)p, (const T*)q, diag, z, w.part_rz, w.part_rr);
     slot ^= 1;
     ++it;
@@ -506,19 +517,19 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
       return err(PHFEM_ENOCONV, "PCG reached max_iter above tolerance");
     return PHFEM_OK;
   }
-  // mixed: FP32 copy of the system (6 nF off-diagonal slots)
-  PH_LAUNCH("to_f32", k_to_f32, pcg_grid(6 * nF), ST, 0, s, 6 * nF, val, w.val32);
-  PH_LAUNCH("to_f32", k_to_f32, pcg_grid(nF), ST, 0, s, nF, diag, w.diag32);
-  // Iterative refinement without restarts: one FP32 PCG recurrence on the FP32 system whose
-  // residual is replaced by the true FP64 residual b_D - C U(x) (matrix-free, per tet, from
-  // the geometry) whenever the recurrence residual has dropped by REPLACE since the last
-  // replacement; the accumulated FP32 iterate is then folded into the FP64 solution.  The
+  // mixed: the Jacobi-scaled FP32 copy of the system (6 nF off-diagonal slots, unit diagonal)
+  PH_LAUNCH("scale_f32", k_scale_f32, pcg_grid(6 * nF), ST, 0, s, nF, col, val, diag, w.val32);
+  // Iterative refinement without restarts: one FP32 CG recurrence on the scaled FP32 system
+  // (Jacobi-PCG in scaled unknowns) whose residual is replaced by the scaled true FP64
+  // residual D^-1/2 (b_D - C U(x)) (matrix-free, per tet, from the geometry) whenever the
+  // recurrence residual has dropped by REPLACE since the last replacement (both in the
+  // scaled 2-norm); the accumulated FP32 iterate is then folded into the FP64 solution.  The
   // search direction is kept, so the Krylov space is not rebuilt as restarted refinement
   // would; convergence is declared on the true FP64 residual only.
   const double REPLACE = inner_tol;
   const unsigned G = pcg_grid(nF);
   PcgWS& pw = w.pcg;
-  float *r32 = (float*)pw.r, *z = (float*)pw.z, *p = (float*)pw.p, *q = (float*)pw.q;
+  float *r32 = (float*)pw.r, *p = (float*)pw.p, *q = (float*)pw.q;
   PH_LAUNCH("fill0", k_fill0, G, ST, 0, s, nF, x);
   rc = residual(m, x, U, w.r64, w.flags, s);
   if (rc) return rc;
@@ -532,11 +543,15 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
     *st = loc;
     return PHFEM_OK;
   }
-  PH_LAUNCH("replace", k_replace<true>, G, ST, 0, s, nF, (const double*)w.r64, (const float*)w.diag32, r32, z, p,
-            w.x32, pw.part_rz, pw.part_rr);
+  PH_LAUNCH("replace", k_replace<true>, G, ST, 0, s, nF, (const double*)w.r64, diag, r32, p, w.x32, pw.part_rz,
+            pw.part_rr);
   PH_LAUNCH("pcg_scalars", k_scalars, 1, ST, 0, s, (int)G, (const double*)pw.part_rz, (const double*)pw.part_rr,
             pw.scal, 0);
-  double ref = r0, rel = 1.0, best = r0;
+  double ref = 0;  // scaled norm of the recurrence residual at the last replacement
+  rc = read_scalar(pw.scal + 2, &ref, s);
+  if (rc) return rc;
+  ref = std::sqrt(ref);
+  double rel = 1.0, best = r0;
   int slot = 0, it = 0, steps = 0, stall = 0;
   bool replace = false, done = false, exact = false;
   while (!done) {
@@ -552,14 +567,15 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
                                            : "mixed refinement reached max_iter above tolerance");
     }
     // direction step (exact product after a replacement and every REFRESH iterations)
-    rc = pcg_direction<float>(nF, col, w.val32, w.diag32, pw, slot, it == 0, exact || (it > 0 && it % REFRESH == 0), s);
+    rc = pcg_direction<float, true>(nF, col, w.val32, nullptr, pw, slot, it == 0, exact || (it > 0 && it % REFRESH == 0),
+                                    s);
     if (rc) return rc;
     exact = false;
-    PH_LAUNCH_B("pcg_update", 8.0 * 4 * nF, k_pcg_update<float>, G, ST, 0, s, nF, (int)G, (const double*)pw.part_pq,
-                (const double*)pw.scal, slot, w.x32, r32, (const float*)p, (const float*)q, (const float*)w.diag32, z,
-                pw.part_rz, pw.part_rr);
+    PH_LAUNCH_B("pcg_update", 6.0 * 4 * nF, (k_pcg_update<float, true>), G, ST, 0, s, nF, (int)G,
+                (const double*)pw.part_pq, (const double*)pw.scal, slot, w.x32, r32, (const float*)p, (const float*)q,
+                (const float*)nullptr, (float*)nullptr, pw.part_rz, pw.part_rr);
     if (replace) {
-      PH_LAUNCH("flush_x", k_flush_x, G, ST, 0, s, nF, w.x32, x);
+      PH_LAUNCH("flush_x", k_flush_x, G, ST, 0, s, nF, diag, w.x32, x);
       rc = residual(m, x, U, w.r64, w.flags, s);
       if (rc) return rc;
       double rn = 0;
@@ -576,9 +592,12 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
       if (!(rel > tol)) {
         done = true;  // x and U are the converged FP64 solution
       } else {
-        PH_LAUNCH("replace", k_replace<false>, G, ST, 0, s, nF, (const double*)w.r64, (const float*)w.diag32, r32,
-                  z, p, w.x32, pw.part_rz, pw.part_rr);
-        ref = rn;
+        PH_LAUNCH("replace", k_replace<false>, G, ST, 0, s, nF, (const double*)w.r64, diag, r32, p, w.x32,
+                  pw.part_rz, pw.part_rr);
+        PH_LAUNCH("sum1", k_sum1, 1, ST, 0, s, (int)G, (const double*)pw.part_rr, pw.scal + 4);
+        rc = read_scalar(pw.scal + 4, &ref, s);
+        if (rc) return rc;
+        ref = std::sqrt(ref);
         exact = true;
       }
       replace = false;
