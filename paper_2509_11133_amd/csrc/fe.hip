@@ -833,12 +833,12 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
     double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
     const double fb = fbv + (cl ? fbp : 0.0);
     if (mixed) {
-      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, FT), FT, 0, s, nC, XA, nE, tetra, tet2face,
+      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, elem_threads<float>()), elem_threads<float>(), 0, s, nC, XA, nE, tetra, tet2face,
                   sigma, kj, P, nF, (SlotRec<float>*)recs);
       PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
                   (const SlotRec<float>*)recs, rp, cl, vj, dj, rj);
     } else {
-      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, ET64), ET64, 0, s, nC, XA, nE, tetra,
+      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, elem_threads<double>()), elem_threads<double>(), 0, s, nC, XA, nE, tetra,
                   tet2face, sigma, kj, P, nF, (SlotRec<double>*)recs);
       PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
                   (const SlotRec<double>*)recs, rp, cl, vj, dj, rj);
