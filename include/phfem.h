@@ -128,7 +128,9 @@ size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags);
  *   face2tet[2][nF]      slot 4t+k of the owner, slot of the neighbour or -1; capacity 8 nE
  *   nbr[4][nE]           tet across local face k, -1 on the boundary (may be NULL)
  * counts (host int64[3]): nEd, nF, nB (boundary faces).  Face outputs may be NULL without
- * the FACES flag.  Synchronizes `stream` (counts are read back).
+ * the FACES flag.  Synchronizes `stream` (counts are read back).  Numbering is by a stable
+ * sort of the occurrence keys; a mesh of at most 256 tets without NODES2EDGE is connected in
+ * one workgroup (each occurrence compared with the earlier ones), with identical outputs.
  * Errors: EINVAL (nC, nE <= 0 or > 2^28 / 2^26, node out of range, repeated node in a tet),
  * EORIENT (a face held by two tets in the same orientation or by more than two tets). */
 int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, void* work, size_t work_bytes,

@@ -232,6 +232,165 @@ __global__ __launch_bounds__(CT) void k_face_assign(int64_t n, int64_t nE, const
   }
 }
 
+// ---------------------------------------------------------------- small meshes
+// A mesh of at most SMALL_NE tets in one workgroup with everything in LDS: the same keys and
+// the same numberings (rank of first appearance over positions 6t + j and 4t + k), with each
+// occurrence's first appearance found by comparing it with the earlier positions instead of
+// by a sort -- one launch instead of about twenty small ones (the level-0 mesh of a
+// refinement chain).  out3 = {nEd, nF, device flags}.
+constexpr int SMALL_NE = 256;
+constexpr int SMT = 1024;
+
+// exclusive prefix over positions [0, n) of flag(p), n <= 2 SMT, positions in chunks of two
+template <class F>
+__device__ __forceinline__ uint32_t small_scan(int n, F flag, int* spre, uint32_t* lw) {
+  const int p0 = 2 * (int)threadIdx.x;
+  const uint32_t f0 = p0 < n ? flag(p0) : 0u, f1 = p0 + 1 < n ? flag(p0 + 1) : 0u;
+  uint32_t total;
+  const uint32_t pre = block_excl_scan<SMT / 64>(f0 + f1, lw, total);
+  if (p0 < n) spre[p0] = (int)pre;
+  if (p0 + 1 < n) spre[p0 + 1] = (int)(pre + f0);
+  return total;
+}
+
+__global__ __launch_bounds__(SMT) void k_connect_small(int nC, int nE, const int32_t* __restrict__ tet, int want_faces,
+                                                       int32_t* __restrict__ edges, int32_t* __restrict__ tet2edge,
+                                                       int32_t* __restrict__ eft, int32_t* __restrict__ pre,
+                                                       int32_t* __restrict__ faces, int32_t* __restrict__ tet2face,
+                                                       int8_t* __restrict__ sigma, int32_t* __restrict__ face2tet,
+                                                       int32_t* __restrict__ nbr, uint32_t* __restrict__ out3) {
+  __shared__ int sv[4 * SMALL_NE];       // node ids, 4 t + i
+  __shared__ uint64_t sk[6 * SMALL_NE];  // keys in position order (edges, then faces)
+  __shared__ int sh[6 * SMALL_NE];       // position of the first occurrence of the same key
+  __shared__ int spre[6 * SMALL_NE];     // exclusive count of first occurrences before a position
+  __shared__ int sid[6 * SMALL_NE];      // edge id per edge position
+  __shared__ uint8_t spar[4 * SMALL_NE];
+  __shared__ uint32_t lw[SMT / 64];
+  __shared__ int sflag;
+  const int n6 = 6 * nE, n4 = 4 * nE;
+  if (threadIdx.x == 0) sflag = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nE; t += SMT) {
+    int v[4];
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i] = tet[i * nE + t];
+      sv[4 * t + i] = v[i];
+      bad |= v[i] < 0 || v[i] >= nC;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 4; ++j) bad |= v[i] == v[j];
+    if (bad) atomicOr(&sflag, DEV_BADNODE);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint32_t a = (uint32_t)v[ev0(j)], b = (uint32_t)v[ev1(j)];
+      sk[6 * t + j] = ((uint64_t)(a < b ? a : b) << 32) | (a < b ? b : a);
+    }
+  }
+  __syncthreads();
+  // edges: first occurrence of every key, ranks of the first occurrences in position order
+  for (int p = threadIdx.x; p < n6; p += SMT) {
+    const uint64_t key = sk[p];
+    int h = p;
+    for (int q = 0; q < p; ++q)
+      if (sk[q] == key) {
+        h = q;
+        break;
+      }
+    sh[p] = h;
+  }
+  __syncthreads();
+  const uint32_t nEd = small_scan(n6, [&](int p) { return sh[p] == p ? 1u : 0u; }, spre, lw);
+  __syncthreads();
+  for (int p = threadIdx.x; p < n6; p += SMT) {
+    const int t = p / 6, j = p - 6 * t, id = spre[sh[p]];
+    sid[p] = id;
+    tet2edge[j * nE + t] = id;
+    if (sh[p] == p) {
+      edges[id] = (int32_t)(sk[p] >> 32);
+      edges[nEd + id] = (int32_t)(sk[p] & 0xffffffffu);
+      eft[id] = t;
+    }
+    if (j == 0) pre[t] = spre[p];
+  }
+  __syncthreads();
+  uint32_t nF = 0;
+  if (want_faces) {
+    // faces: key (min node, id of the edge opposite it within the face), parity of the tuple
+    for (int p = threadIdx.x; p < n4; p += SMT) {
+      const int t = p >> 2, k = p & 3;
+      const int a = fv(k, 0), b = fv(k, 1), c = fv(k, 2);
+      const int na = sv[4 * t + a], nb_ = sv[4 * t + b], nc = sv[4 * t + c];
+      int lo, oe;
+      if (na < nb_ && na < nc) {
+        lo = na;
+        oe = sid[6 * t + eidx(b, c)];
+      } else if (nb_ < nc) {
+        lo = nb_;
+        oe = sid[6 * t + eidx(a, c)];
+      } else {
+        lo = nc;
+        oe = sid[6 * t + eidx(a, b)];
+      }
+      sk[p] = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)oe;
+      spar[p] = (uint8_t)(((na > nb_) + (na > nc) + (nb_ > nc)) & 1);
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n4; p += SMT) {
+      const uint64_t key = sk[p];
+      int h = p;
+      for (int q = 0; q < p; ++q)
+        if (sk[q] == key) {
+          h = q;
+          break;
+        }
+      sh[p] = h;
+    }
+    __syncthreads();
+    nF = small_scan(n4, [&](int p) { return sh[p] == p ? 1u : 0u; }, spre, lw);
+    __syncthreads();
+    for (int p = threadIdx.x; p < n4; p += SMT) {
+      const int h = sh[p], t = p >> 2, k = p & 3, id = spre[h];
+      const uint64_t key = sk[p];
+      if (h == p) {  // owner: the later occurrences give the neighbour and the orientation check
+        int q1 = -1, more = 0;
+        for (int q = p + 1; q < n4; ++q)
+          if (sk[q] == key) {
+            if (q1 < 0)
+              q1 = q;
+            else
+              more = 1;
+          }
+        if (more || (q1 >= 0 && spar[q1] == spar[p])) atomicOr(&sflag, DEV_ORIENT);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) faces[m * nF + id] = sv[4 * t + fv(k, m)];
+        face2tet[id] = p;
+        face2tet[nF + id] = q1;
+        tet2face[k * nE + t] = id;
+        sigma[k * nE + t] = 1;
+        if (nbr) nbr[k * nE + t] = q1 >= 0 ? (q1 >> 2) : -1;
+      } else {
+        bool second = true;  // a third occurrence is left to the owner's check
+        for (int q = h + 1; q < p; ++q) second = second && sk[q] != key;
+        if (second) {
+          tet2face[k * nE + t] = id;
+          sigma[k * nE + t] = -1;
+          if (nbr) nbr[k * nE + t] = h >> 2;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out3[0] = nEd;
+    out3[1] = nF;
+    out3[2] = (uint32_t)sflag;
+  }
+}
+
 // ---------------------------------------------------------------- workspace layout
 struct ConnWS {
   uint64_t *kA, *kB;
@@ -297,6 +456,19 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   conn_layout(a, nC, nE, flags, w);
   const size_t sub = w.sub;
   const int64_t n6 = 6 * nE, n4 = 4 * nE;
+  if (nE <= SMALL_NE && !want_n2e) {
+    PH_LAUNCH_B("connect_small", 16.0 * nE + 36.0 * nE + 3.6 * nE * 4 + (want_faces ? 26.0 * n4 : 0.0), k_connect_small,
+                1, SMT, 0, s, (int)nC, (int)nE, tetra, want_faces ? 1 : 0, edges, tet2edge, edge_first_tet,
+                tet_edge_prefix, faces, tet2face, sigma, face2tet, nbr, w.total);
+    uint32_t h3[3] = {0, 0, 0};
+    PH_HIP(hipMemcpyAsync(h3, w.total, sizeof(h3), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (h3[2]) return dev_flags_to_status((int)h3[2]);
+    counts[0] = h3[0];
+    counts[1] = want_faces ? h3[1] : 0;
+    counts[2] = want_faces ? 2 * (int64_t)h3[1] - 4 * nE : 0;
+    return PHFEM_OK;
+  }
   const int nb = bits_for(nC);
   PH_HIP(hipMemsetAsync(w.dflags, 0, sizeof(int), s));
 

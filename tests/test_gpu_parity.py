@@ -91,6 +91,43 @@ def test_connect_permuted_relabelled(seed):
         assert np.array_equal(host(gc[k]), oc[k]), k
 
 
+CONN_KEYS = ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma", "face2tet", "nbr")
+
+
+def _permuted(X, T, seed):
+    rng = np.random.default_rng(seed)
+    T = T[:, rng.permutation(T.shape[1])]
+    return X, rng.permutation(X.shape[1])[T].astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["kuhn0", "kuhn1_perm", "fichera0_perm", "single2", "paper", "disjoint256",
+                                  "disjoint257"])
+def test_connect_small_path(case):
+    """Meshes of at most 256 tets are connected in one workgroup (when Nodes2Edge is not asked
+    for): the same numbering as the oracle and as the sort-based path (which a Nodes2Edge
+    request takes), edges-only calls included; 257 tets take the sort-based path."""
+    if case == "paper":
+        X, T = M.paper_cube()[:2]
+    elif case.startswith("disjoint"):
+        X, T = disjoint_tets(int(case[8:]))
+    else:
+        make = {"kuhn": M.kuhn_cube, "fich": M.fichera, "sing": single_tet}[case[:4]]
+        X, T, _, _ = levels(make, int(case.split("_")[0][-1]))
+        if case.endswith("_perm"):
+            X, T = _permuted(X, T, len(case))
+    oc = O.connect(X.shape[1], T)
+    small = P.connect(dev(T), X.shape[1])
+    sort = P.connect(dev(T), X.shape[1], faces=True, n2e=True)
+    edges_only = P.connect(dev(T), X.shape[1], faces=False)
+    for g in (small, sort):
+        assert g["nEd"] == oc["nEd"] and g["nF"] == oc["nF"] and g["nB"] == oc["nB"]
+        for k in CONN_KEYS:
+            assert np.array_equal(host(g[k]), oc[k]), k
+    assert edges_only["nEd"] == oc["nEd"]
+    for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix"):
+        assert np.array_equal(host(edges_only[k]), oc[k]), k
+
+
 def test_connect_paper_mesh_example():
     """Listing 1 mesh on the GPU: 16 Faces rows, tet 5 -> [16 7 12 4] (Section 3.3)."""
     from tests import golden_io as G
@@ -102,17 +139,27 @@ def test_connect_paper_mesh_example():
     assert np.array_equal(host(gc["tet2face"])[:, 4] + 1, tet5)
 
 
-def test_connect_errors():
+@pytest.mark.parametrize("n2e", [False, True])  # the one-workgroup path and the sort-based one
+def test_connect_errors(n2e):
     X, T = M.kuhn_cube()
     flip = T.copy()
     flip[[2, 3], 1] = flip[[3, 2], 1]
     with pytest.raises(P.PhfemError) as e:
-        P.connect(dev(flip), 8)
+        P.connect(dev(flip), 8, n2e=n2e)
+    assert e.value.code == P.B.EORIENT
+    three = np.array([[0, 1, 2, 3], [0, 2, 1, 4], [0, 1, 2, 5]], np.int32).T.copy()  # one face in three tets
+    with pytest.raises(P.PhfemError) as e:
+        P.connect(dev(three), 6, n2e=n2e)
     assert e.value.code == P.B.EORIENT
     bad = T.copy()
     bad[0, 3] = 8
     with pytest.raises(P.PhfemError) as e:
-        P.connect(dev(bad), 8)
+        P.connect(dev(bad), 8, n2e=n2e)
+    assert e.value.code == P.B.EINVAL
+    rep = T.copy()
+    rep[1, 2] = rep[0, 2]  # a repeated node in one tet
+    with pytest.raises(P.PhfemError) as e:
+        P.connect(dev(rep), 8, n2e=n2e)
     assert e.value.code == P.B.EINVAL
 
 
