@@ -289,7 +289,9 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  * (rowptr, col, val, diag, rhs) as phfem_condense writes them: 6 slots per row, rowptr[F] =
  * 6 F, column ids in [0, nF) -- checked on the device once per call (EINVAL otherwise); col
  * 8-byte and val 16-byte aligned (vector loads of a row's slots).
- *  mode FP64_PCG: PCG on the FP64 system to ||r|| <= tol ||r+|| (recurrence residual); then,
+ *  mode FP64_PCG: Jacobi-PCG on the FP64 system, run as CG on its Jacobi-scaled FP64 copy
+ *    D^-1/2 S+ D^-1/2 (same iterates; no diagonal in the product, no z vector), to
+ *    ||r|| <= tol ||r+|| (the unscaled recurrence residual); then,
  *    while the true residual b_D - C U(lambda) (FP64, matrix-free) is above tol ||r+||, the
  *    stored system is solved again for the correction (iterative refinement; the stored
  *    system differs from the matrix-free operator by assembly rounding, so the recurrence

@@ -129,6 +129,38 @@ __global__ __launch_bounds__(ST) void k_pcg_init(int64_t n, const T* __restrict_
   }
 }
 
+// the same start on the Jacobi-scaled system: r = D^-1/2 b, x = 0, p = r; partial r.r and
+// the unscaled b.b (= sum d_i r_i^2)
+template <class T>
+__global__ __launch_bounds__(ST) void k_pcg_init_scaled(int64_t n, const T* __restrict__ b, const T* __restrict__ diag,
+                                                        T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
+                                                        double* __restrict__ part_rz, double* __restrict__ part_rr) {
+  __shared__ double lds[ST / 64];
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) {
+    const T bi = b[i];
+    const T ri = bi / std::sqrt(diag[i]);
+    x[i] = (T)0;
+    r[i] = ri;
+    p[i] = ri;
+    arz += (double)ri * (double)ri;
+    arr += (double)bi * (double)bi;
+  }
+  double s1 = block_sum(arz, lds);
+  double s2 = block_sum(arr, lds);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = s1;
+    part_rr[blockIdx.x] = s2;
+  }
+}
+
+// x = D^-1/2 x (a scaled solution back in the original unknowns)
+template <class T>
+__global__ __launch_bounds__(ST) void k_unscale(int64_t n, const T* __restrict__ diag, T* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST)
+    x[i] = x[i] / std::sqrt(diag[i]);
+}
+
 // scal[slot] = sum part_rz, scal[2] = sum part_rr (single block)
 __global__ __launch_bounds__(ST) void k_scalars(int G, const double* __restrict__ part_rz,
                                                 const double* __restrict__ part_rr, double* __restrict__ scal,
@@ -142,7 +174,8 @@ __global__ __launch_bounds__(ST) void k_scalars(int G, const double* __restrict_
   }
 }
 
-// UNIT: the system has a unit diagonal (Jacobi-scaled), so z = r is not stored
+// UNIT: the system has a unit diagonal (Jacobi-scaled), so z = r is not stored; the partial
+// r.r is then weighted by diag when diag is given (the unscaled residual's 2-norm, sum d_i r_i^2)
 template <class T, bool UNIT>
 __global__ __launch_bounds__(ST) void k_pcg_update(int64_t n, int G, const double* __restrict__ part_pq,
                                                    const double* __restrict__ scal, int slot, T* __restrict__ x,
@@ -165,7 +198,8 @@ __global__ __launch_bounds__(ST) void k_pcg_update(int64_t n, int G, const doubl
       z[i] = zi;
     }
     arz += (double)ri * (double)zi;
-    arr += (double)ri * (double)ri;
+    const double wi = (UNIT && diag) ? (double)diag[i] : 1.0;
+    arr += wi * ((double)ri * (double)ri);
   }
   double s1 = block_sum(arz, lds);
   double s2 = block_sum(arr, lds);
@@ -263,6 +297,16 @@ __global__ __launch_bounds__(ST) void k_scale_f32(int64_t n, const int32_t* __re
   }
 }
 
+// the Jacobi-scaled FP64 copy, val64s[6 i + q] = val[6 i + q] / sqrt(d_i d_col)
+__global__ __launch_bounds__(ST) void k_scale_f64(int64_t n, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, const double* __restrict__ diag,
+                                                  double* __restrict__ vals) {
+  for (int64_t k = (int64_t)blockIdx.x * ST + threadIdx.x; k < 6 * n; k += (int64_t)gridDim.x * ST) {
+    const int64_t i = k / 6;
+    vals[k] = val[k] / std::sqrt(diag[i] * diag[col[k]]);
+  }
+}
+
 __global__ __launch_bounds__(ST) void k_add_f32(int64_t n, const float* __restrict__ d, double* __restrict__ x) {
   for (int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x; i < n; i += (int64_t)gridDim.x * ST) x[i] += (double)d[i];
 }
@@ -330,7 +374,7 @@ static void pcg_layout(Arena& a, int64_t n, PcgWS& w) {
 
 struct SolveWS {
   PcgWS pcg;
-  double *bD, *r64, *e64;
+  double *bD, *r64, *e64, *val64s;
   float *val32, *x32;
   int* flags;
 };
@@ -343,6 +387,7 @@ static void solve_layout(Arena& a, int64_t nF, int32_t mode, SolveWS& w) {
   w.bD = a.take<double>(nF);
   w.r64 = a.take<double>(nF);
   w.e64 = mode == PHFEM_SOLVE_FP32_PCG_FP64_IR ? nullptr : a.take<double>(nF);
+  w.val64s = mode == PHFEM_SOLVE_FP32_PCG_FP64_IR ? nullptr : a.take<double>(6 * nF);
   if (mode == PHFEM_SOLVE_FP32_PCG_FP64_IR) {
     w.val32 = a.take<float>(6 * nF);
     w.x32 = a.take<float>(nF);
@@ -391,13 +436,20 @@ static int pcg_direction(int64_t n, const int32_t* col, const T* val, const T* d
   return PHFEM_OK;
 }
 
-// PCG on the 6-slot system (col, val, diag) from x0 = 0; stops at ||r|| <= tol ||b|| or maxit.
-template <class T>
+// Jacobi-PCG on the 6-slot system (col, val, diag) from x0 = 0; stops at ||r|| <= tol ||b||
+// (2-norm of the unscaled residual) or maxit.  SCALED: val is the Jacobi-scaled copy
+// D^-1/2 (offdiag) D^-1/2 with the unit diagonal implied, and the iteration is CG on that
+// system -- the same iterates in exact arithmetic, without the diagonal in the product and
+// without the z vector; x is scaled back on exit.
+template <class T, bool SCALED>
 static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const T* b, T* x,
                double tol, int maxit, PcgWS& w, int* iters, double* relres, hipStream_t s) {
   const unsigned G = pcg_grid(n);
   T *r = (T*)w.r, *z = (T*)w.z, *p = (T*)w.p, *q = (T*)w.q;
-  PH_LAUNCH("pcg_init", k_pcg_init<T>, G, ST, 0, s, n, b, diag, x, r, z, p, w.part_rz, w.part_rr);
+  if (SCALED)
+    PH_LAUNCH("pcg_init", k_pcg_init_scaled<T>, G, ST, 0, s, n, b, diag, x, r, p, w.part_rz, w.part_rr);
+  else
+    PH_LAUNCH("pcg_init", k_pcg_init<T>, G, ST, 0, s, n, b, diag, x, r, z, p, w.part_rz, w.part_rr);
   PH_LAUNCH("pcg_scalars", k_scalars, 1, ST, 0, s, (int)G, (const double*)w.part_rz, (const double*)w.part_rr, w.scal,
             0);
   double rr0 = 0;
@@ -406,14 +458,16 @@ static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const
   const double bn = std::sqrt(rr0);
   *iters = 0;
   *relres = 0;
-  if (bn == 0) return PHFEM_OK;
+  if (bn == 0) return PHFEM_OK;  // x = 0 either way
   int slot = 0, it = 0;
   double rel = 1.0;
   while (it < maxit) {
-    rc = pcg_direction<T, false>(n, col, val, diag, w, slot, it == 0, it > 0 && it % REFRESH == 0, s);
+    rc = pcg_direction<T, SCALED>(n, col, val, SCALED ? nullptr : diag, w, slot, it == 0,
+                                  it > 0 && it % REFRESH == 0, s);
     if (rc) return rc;
-    PH_LAUNCH_B("pcg_update", 8.0 * sizeof(T) * n, (k_pcg_update<T, false>), G, ST, 0, s, n, (int)G, (const double*)w.part_pq, (const double*)w.scal,
-              slot, x, r, (const T*)p, (const T*)q, diag, z, w.part_rz, w.part_rr);
+    PH_LAUNCH_B("pcg_update", (SCALED ? 7.0 : 8.0) * sizeof(T) * n, (k_pcg_update<T, SCALED>), G, ST, 0, s, n, (int)G,
+                (const double*)w.part_pq, (const double*)w.scal, slot, x, r, (const T*)p, (const T*)q, diag, z,
+                w.part_rz, w.part_rr);
     slot ^= 1;
     ++it;
     // scal[2] holds r.r of the residual before this iteration's update (one iteration behind)
@@ -425,6 +479,7 @@ static int pcg(int64_t n, const int32_t* col, const T* val, const T* diag, const
       if (!(rel > tol)) break;  // also stops on NaN
     }
   }
+  if (SCALED) PH_LAUNCH("unscale", k_unscale<T>, G, ST, 0, s, n, diag, x);
   *iters = it;
   *relres = rel;
   return PHFEM_OK;
@@ -490,7 +545,9 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
     rc = norm2(nF, rhs, w.pcg, &bn, s);
     if (rc) return rc;
     loc.rhs_norm = bn;
-    rc = pcg<double>(nF, col, val, diag, rhs, x, tol, maxit, w.pcg, &it, &rel, s);
+    // the Jacobi-scaled copy the PCG iterates on (every solve below uses it)
+    PH_LAUNCH("scale_f64", k_scale_f64, pcg_grid(6 * nF), ST, 0, s, nF, col, val, diag, w.val64s);
+    rc = pcg<double, true>(nF, col, w.val64s, diag, rhs, x, tol, maxit, w.pcg, &it, &rel, s);
     if (rc) return rc;
     total = it;
     for (int steps = 0;; ++steps) {
@@ -504,8 +561,8 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
       if (rc) return rc;
       loc.ir_steps = steps;
       if (!(rn > tol * bn) || total >= maxit || steps == 8 || (steps > 0 && !(rn < 0.5 * prev))) break;
-      rc = pcg<double>(nF, col, val, diag, w.r64, w.e64, std::max(0.5 * tol * bn / rn, 1e-12), maxit - total, w.pcg,
-                       &it, &rel, s);
+      rc = pcg<double, true>(nF, col, w.val64s, diag, w.r64, w.e64, std::max(0.5 * tol * bn / rn, 1e-12),
+                             maxit - total, w.pcg, &it, &rel, s);
       if (rc) return rc;
       total += it;
       PH_LAUNCH("add_f64", k_add_f64, pcg_grid(nF), ST, 0, s, nF, (const double*)w.e64, x);
