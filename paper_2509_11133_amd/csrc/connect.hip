@@ -488,9 +488,11 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   a.off = sub;
   int rc = radix_sort(w.kA, w.vA, w.kB, w.vB, nullptr, n6, 2 * nb, &sk, &sv, a, s);
   if (rc) return rc;
-  PH_LAUNCH_B("mark_heads", 13.0 * n6, k_mark_heads, grid_for(n6, CT), CT, 0, s, n6, (const uint64_t*)sk, (const int32_t*)sv,
+  PH_LAUNCH_B("mark_heads", 13.0 * n6, k_mark_heads, grid_for(n6, CT), CT, 0, s, n6, (const uint64_t*)sk,
+              (const int32_t*)sv,
             0xffffffffu, w.first);
-  PH_LAUNCH_B("count_heads", 10.0 * nE, k_count_heads<6>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
+  PH_LAUNCH_B("count_heads", 10.0 * nE, k_count_heads<6>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first,
+              w.cnt);
   a.off = sub;
   rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
   if (rc) return rc;
@@ -535,14 +537,17 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
 
   // ---- faces: key = (min node, opposite edge) of every local face
   const int eb = bits_for(nEd >= 0 ? nEd : std::min<int64_t>(n6, nC * (nC - 1) / 2));
-  PH_LAUNCH_B("face_keys", 88.0 * nE, k_face_keys, grid_for(nE, CT), CT, 0, s, nE, tetra, (const int32_t*)tet2edge, eb, w.kA,
+  PH_LAUNCH_B("face_keys", 88.0 * nE, k_face_keys, grid_for(nE, CT), CT, 0, s, nE, tetra, (const int32_t*)tet2edge, eb,
+              w.kA,
             w.vA);
   a.off = sub;
   rc = radix_sort(w.kA, w.vA, w.kB, w.vB, w.vA, n4, nb + eb, &sk, &sv, a, s);
   if (rc) return rc;
-  PH_LAUNCH_B("mark_heads", 13.0 * n4, k_mark_heads, grid_for(n4, CT), CT, 0, s, n4, (const uint64_t*)sk, (const int32_t*)sv,
+  PH_LAUNCH_B("mark_heads", 13.0 * n4, k_mark_heads, grid_for(n4, CT), CT, 0, s, n4, (const uint64_t*)sk,
+              (const int32_t*)sv,
             SLOT_MASK, w.first);
-  PH_LAUNCH_B("count_heads", 8.0 * nE, k_count_heads<4>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first, w.cnt);
+  PH_LAUNCH_B("count_heads", 8.0 * nE, k_count_heads<4>, grid_for(nE + 1, CT), CT, 0, s, nE, (const uint8_t*)w.first,
+              w.cnt);
   a.off = sub;
   rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total + 1, a, s);
   if (rc) return rc;

@@ -52,7 +52,8 @@ static GL1 gauss_legendre01(int n) {
 }
 
 __global__ __launch_bounds__(ERT) void k_errors(int64_t nC, const double* __restrict__ X, int64_t nE,
-                                                int64_t nF, const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                                int64_t nF, const int32_t* __restrict__ tet,
+                                                const int32_t* __restrict__ t2f,
                                                 const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
                                                 DevParams P, const double* __restrict__ U,
                                                 const double* __restrict__ lambda, int uk, Fun4 up, double h, GL1 q,
@@ -230,8 +231,8 @@ extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const i
   for (int i = 0; i < 4; ++i) up.p[i] = u_par[i];
   const GL1 q = gauss_legendre01(nq);
   PH_HIP(hipMemsetAsync(bad, 0, sizeof(uint32_t), s));
-  PH_LAUNCH("errors", k_errors, (unsigned)nb, ERT, 0, s, nC, coord, nE, nF, tetra, tet2face, sigma, kappa, to_dev(*p), U,
-            lambda, u_kind, up, h, q, part, bad);
+  PH_LAUNCH("errors", k_errors, (unsigned)nb, ERT, 0, s, nC, coord, nE, nF, tetra, tet2face, sigma, kappa, to_dev(*p),
+            U, lambda, u_kind, up, h, q, part, bad);
   PH_LAUNCH("errors_sum", k_errors_sum, 1, ERT, 0, s, nb, (const double*)part, dout);
   double res[3];
   uint32_t hbad = 0;

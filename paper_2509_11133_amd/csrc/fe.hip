@@ -100,8 +100,11 @@ struct Elem {
     R A11 = N[0][0] * N[2][2] - N[0][2] * N[2][0];
     R A12 = N[0][2] * N[1][0] - N[0][0] * N[1][2];
     R A22 = N[0][0] * N[1][1] - N[0][1] * N[1][0];
-    R idn = (R)1 / (N[0][0] * A00 + N[0][1] * (N[1][2] * N[2][0] - N[1][0] * N[2][2]) + N[0][2] * (N[1][0] * N[2][1] - N[1][1] * N[2][0]));
-    R Ni[3][3] = {{A00 * idn, A01 * idn, A02 * idn}, {A01 * idn, A11 * idn, A12 * idn}, {A02 * idn, A12 * idn, A22 * idn}};
+    R idn = (R)1 / (N[0][0] * A00 + N[0][1] * (N[1][2] * N[2][0] - N[1][0] * N[2][2]) +
+                    N[0][2] * (N[1][0] * N[2][1] - N[1][1] * N[2][0]));
+    R Ni[3][3] = {{A00 * idn, A01 * idn, A02 * idn},
+                  {A01 * idn, A11 * idn, A12 * idn},
+                  {A02 * idn, A12 * idn, A22 * idn}};
     // Y = Q Ni (4x3), q_m[i] = 0.5 * sign pattern
     const int sg[3][4] = {{1, 1, -1, -1}, {1, -1, 1, -1}, {1, -1, -1, 1}};
     R Y[4][3];
@@ -737,22 +740,25 @@ __global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict
 int launch_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f,
                    const int8_t* sigma, const double* kappa, const DevParams& P, const double* lambda,
                    const double* gsrc, double* U, double* res, int* flags, hipStream_t s) {
-  PH_LAUNCH_B("recover", (36.0 + (kappa ? 8.0 : 0.0) + (gsrc ? 32.0 : 0.0) + (U ? 32.0 : 0.0)) * nE + 24.0 * nC + (lambda ? 8.0 : 0.0) * nE + (res ? 16.0 : 0.0) * nE, k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, kappa, P, lambda, gsrc, U,
-            res, flags);
+  const double bytes = (36.0 + (kappa ? 8.0 : 0.0) + (gsrc ? 32.0 : 0.0) + (U ? 32.0 : 0.0)) * nE + 24.0 * nC +
+                       (lambda ? 8.0 : 0.0) * nE + (res ? 16.0 : 0.0) * nE;
+  PH_LAUNCH_B("recover", bytes, k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, kappa, P, lambda,
+              gsrc, U, res, flags);
   return PHFEM_OK;
 }
 
 int launch_face_init(int64_t nF, int64_t nC, const double* X, const int32_t* faces, const int32_t* face2tet,
                      const DevParams& P, uint32_t* cnt, double* diag, double* rhs, hipStream_t s) {
-  PH_LAUNCH_B("face_init", (8.0 + (cnt ? 4.0 : 0.0) + (diag ? 8.0 : 0.0) + (rhs ? 8.0 : 0.0)) * nF, k_face_init, grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
+  PH_LAUNCH_B("face_init", (8.0 + (cnt ? 4.0 : 0.0) + (diag ? 8.0 : 0.0) + (rhs ? 8.0 : 0.0)) * nF, k_face_init,
+              grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
   return PHFEM_OK;
 }
 
 int launch_vjp(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f, const int8_t* sigma,
                const int32_t* nbr, const double* kappa, const DevParams& P, const double* U, const double* Pp,
                const double* lambda, const double* Q, double* dlogk, double* dX, hipStream_t s) {
-  PH_LAUNCH_B("vjp", (124.0 + (kappa ? 8.0 : 0.0)) * nE + 16.0 * nE + 72.0 * nC, k_vjp, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q,
-            dlogk, dX);
+  PH_LAUNCH_B("vjp", (124.0 + (kappa ? 8.0 : 0.0)) * nE + 16.0 * nE + 72.0 * nC, k_vjp, grid_for(nE, FT), FT, 0, s, nC,
+              X, nE, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q, dlogk, dX);
   return PHFEM_OK;
 }
 
@@ -833,13 +839,13 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
     double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
     const double fb = fbv + (cl ? fbp : 0.0);
     if (mixed) {
-      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, elem_threads<float>()), elem_threads<float>(), 0, s, nC, XA, nE, tetra, tet2face,
-                  sigma, kj, P, nF, (SlotRec<float>*)recs);
+      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, elem_threads<float>()), elem_threads<float>(), 0,
+                  s, nC, XA, nE, tetra, tet2face, sigma, kj, P, nF, (SlotRec<float>*)recs);
       PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
                   (const SlotRec<float>*)recs, rp, cl, vj, dj, rj);
     } else {
-      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, elem_threads<double>()), elem_threads<double>(), 0, s, nC, XA, nE, tetra,
-                  tet2face, sigma, kj, P, nF, (SlotRec<double>*)recs);
+      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, elem_threads<double>()), elem_threads<double>(),
+                  0, s, nC, XA, nE, tetra, tet2face, sigma, kj, P, nF, (SlotRec<double>*)recs);
       PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
                   (const SlotRec<double>*)recs, rp, cl, vj, dj, rj);
     }

@@ -63,7 +63,9 @@ __device__ __forceinline__ int eidx_r(int i, int j) { return (int)((eidx_pack() 
 static_assert(((posv_pack() >> (2 * (6 * 1 + 3))) & 3) == (uint64_t)posv(1, 3), "posv pack");
 
 // local face of corner child v that lies on coarse face k (15 if none)
-__host__ __device__ constexpr int cornerface(int v, int k) { return (int)((0x12f1f2021f0f210ull >> (4 * (4 * v + k))) & 15ull); }
+__host__ __device__ constexpr int cornerface(int v, int k) {
+  return (int)((0x12f1f2021f0f210ull >> (4 * (4 * v + k))) & 15ull);
+}
 static_assert(cornerface(0, 0) == 0 && cornerface(0, 2) == 2 && cornerface(1, 2) == 1 && cornerface(2, 1) == 2 &&
                   cornerface(3, 3) == 0 && cornerface(0, 3) == 15,
               "corner faces");
@@ -94,10 +96,18 @@ __host__ __device__ constexpr int first3(int j, bool want_edge) {
 
 // faces: kind 0 inside t, 1 corner triangle on a coarse face, 2 middle triangle of a coarse face
 __host__ __device__ constexpr int fs(int c, int kk, int m) { return ch(c, fv(kk, m)); }
-__host__ __device__ constexpr int nverts(int c, int kk) { return (fs(c, kk, 0) < 4) + (fs(c, kk, 1) < 4) + (fs(c, kk, 2) < 4); }
-__host__ __device__ constexpr bool has_c(int c, int kk) { return fs(c, kk, 0) == 10 || fs(c, kk, 1) == 10 || fs(c, kk, 2) == 10; }
-__host__ __device__ constexpr int vmask_of(int s) { return s < 4 ? (1 << s) : (s < 10 ? ((1 << ev0(s - 4)) | (1 << ev1(s - 4))) : 0); }
-__host__ __device__ constexpr int span(int c, int kk) { return vmask_of(fs(c, kk, 0)) | vmask_of(fs(c, kk, 1)) | vmask_of(fs(c, kk, 2)); }
+__host__ __device__ constexpr int nverts(int c, int kk) {
+  return (fs(c, kk, 0) < 4) + (fs(c, kk, 1) < 4) + (fs(c, kk, 2) < 4);
+}
+__host__ __device__ constexpr bool has_c(int c, int kk) {
+  return fs(c, kk, 0) == 10 || fs(c, kk, 1) == 10 || fs(c, kk, 2) == 10;
+}
+__host__ __device__ constexpr int vmask_of(int s) {
+  return s < 4 ? (1 << s) : (s < 10 ? ((1 << ev0(s - 4)) | (1 << ev1(s - 4))) : 0);
+}
+__host__ __device__ constexpr int span(int c, int kk) {
+  return vmask_of(fs(c, kk, 0)) | vmask_of(fs(c, kk, 1)) | vmask_of(fs(c, kk, 2));
+}
 __host__ __device__ constexpr int popc4(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
 __host__ __device__ constexpr int fkind(int c, int kk) {
   return has_c(c, kk) ? 0 : (nverts(c, kk) == 1 ? 1 : (popc4(span(c, kk)) == 3 ? 2 : 0));
@@ -106,7 +116,9 @@ __host__ __device__ constexpr int fkind(int c, int kk) {
 __host__ __device__ constexpr int fcoarse(int c, int kk) {
   return opp((span(c, kk) & 1) == 0 ? 0 : ((span(c, kk) & 2) == 0 ? 1 : ((span(c, kk) & 4) == 0 ? 2 : 3)));
 }
-__host__ __device__ constexpr int symset(int c, int kk) { return (1 << fs(c, kk, 0)) | (1 << fs(c, kk, 1)) | (1 << fs(c, kk, 2)); }
+__host__ __device__ constexpr int symset(int c, int kk) {
+  return (1 << fs(c, kk, 0)) | (1 << fs(c, kk, 1)) | (1 << fs(c, kk, 2));
+}
 // partner (child * 4 + local face) of a kind-0 face inside t
 __host__ __device__ constexpr int fpartner(int c, int kk) {
   for (int c2 = 0; c2 < 12; ++c2)
@@ -121,8 +133,9 @@ static_assert(first3(0, false) == 4 && first3(3, false) == 5, "first (M, C)");
 
 // Element i of an array addressed as its (wave-uniform) base plus an unsigned 32-bit byte
 // offset: the hardware adds the offset to a scalar base, so no 64-bit address arithmetic is
-// spent per access.  Stores (every one of them a write-once output) carry the nontemporal hint.  Valid while i * sizeof(T) < 2^32 (every array indexed this way holds
-// at most 16 nE' bytes < 2^32 by the entry point's size limits; two-dimensional outputs
+// spent per access.  Stores (every one of them a write-once output) carry the nontemporal
+// hint.  Valid while i * sizeof(T) < 2^32 (every array indexed this way holds at most
+// 16 nE' bytes < 2^32 by the entry point's size limits; two-dimensional outputs
 // take a per-row base).
 template <class T>
 __device__ __forceinline__ T ldu(const T* p, uint32_t i) {

@@ -50,9 +50,9 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 }
 
 // The face system's fixed 6-slot rows (rowptr[i] = 6 i, as phfem_condense writes them):
-// y = (D + offdiag) x and the partial dots x.y (UNIT: a unit diagonal, not read).  A row's 6 column ids and values are read as
-// three 8-byte (int2) and three 16- or 8-byte (double2 / float2) vector loads; the products
-// are summed in slot order, as a plain CSR loop would.
+// y = (D + offdiag) x and the partial dots x.y (UNIT: a unit diagonal, not read).  A row's 6
+// column ids and values are read as three 8-byte (int2) and three 16- or 8-byte (double2 /
+// float2) vector loads; the products are summed in slot order, as a plain CSR loop would.
 template <class T>
 struct Vec2;
 template <>
