@@ -109,3 +109,16 @@ def test_size_limits_on_host():
     out = np.zeros(4, np.int64)
     assert L.phfem_refined_sizes(8, 6, 19, 18, -1, out.ctypes.data) == B.EINVAL
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 17) == 0
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says so."""
+    import json
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
