@@ -567,6 +567,19 @@ def test_neumann_grad_rejected():
         P.grad(dev(X), dev(T), gc, sysm, None, gp, gU, glam, gU)
 
 
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
+def test_solve_zero_data(mode, precision):
+    """f = 0 and u_D = 0: lambda and U are exactly zero, reached without an iteration (both
+    solvers start from zero and stop on a zero right-hand side)."""
+    X, T, _, _ = levels(M.kuhn_cube, 1)
+    gc = P.connect(dev(T), X.shape[1])
+    gp = P.params(c=1.0, kappa=1.0, precision=precision)
+    sysm = P.condense(dev(X), dev(T), gc, None, gp)
+    lam, U, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=mode, tol=1e-12)
+    assert st["converged"] and st["iters"] == 0
+    assert float(lam.abs().max()) == 0.0 and float(U.abs().max()) == 0.0
+
+
 def test_solve_pattern_check():
     """phfem_solve takes the 6-slot layout condense writes; another row pointer or a column id
     outside [0, nF) is found by the device-side check and refused before any iteration."""
