@@ -280,6 +280,14 @@ def tet_rule(n):
     return pts, w
 
 
+def tri_rule(n):
+    m = n ** 2
+    pts = np.zeros((2, m))
+    w = np.zeros(m)
+    _chk(lib().orc_tri_rule(C.c_int32(n), _p(pts), _p(w)))
+    return pts, w
+
+
 def connect(nC, tet):
     """Edges + faces of a mesh in one dict (oracle numbering)."""
     d = edges(nC, tet)

@@ -583,6 +583,8 @@ void tet_rule(int n, std::vector<std::array<long double, 4>>& q) {
       }
 }
 
+// The same collapse on the unit triangle: u, v(1-u), Jacobian (1-u).  Exact for total degree
+// <= 2n-2.
 void tri_rule(int n, std::vector<std::array<long double, 3>>& q) {
   std::vector<long double> x, w;
   gauss_legendre01(n, x, w);
@@ -1279,6 +1281,19 @@ int orc_tet_rule(int32_t n, double* pts, double* wts) {
   for (int64_t i = 0; i < m; ++i) {
     for (int d = 0; d < 3; ++d) pts[d * m + i] = (double)q[i][d];
     wts[i] = (double)q[i][3];
+  }
+  return ORC_OK;
+}
+
+// Quadrature rule on the unit triangle {u, v >= 0, u + v <= 1} (for pinning the rule itself):
+// pts [2][m], wts [m], m = n^2.
+int orc_tri_rule(int32_t n, double* pts, double* wts) {
+  std::vector<std::array<long double, 3>> q;
+  tri_rule(n, q);
+  int64_t m = (int64_t)q.size();
+  for (int64_t i = 0; i < m; ++i) {
+    for (int d = 0; d < 2; ++d) pts[d * m + i] = (double)q[i][d];
+    wts[i] = (double)q[i][2];
   }
   return ORC_OK;
 }

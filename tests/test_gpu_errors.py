@@ -12,14 +12,14 @@ oracle, and the convergence orders Table 4 prints.
 * The paper's example with its Dirichlet / Neumann faces, solved on the GPU at levels 1-5:
   the orders of ||u - u_h||_Y and of the multiplier's h-norm match Table 4's within 0.15.
 """
-from fractions import Fraction
-from math import factorial, sqrt
+from math import sqrt
 
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2509_11133_amd import meshes as M
+from tests import closed_forms as CF
 from tests import golden_io as G
 
 torch = pytest.importorskip("torch")
@@ -39,15 +39,6 @@ def dev(a):
     return torch.tensor(np.ascontiguousarray(a), device=DEV)
 
 
-def simplex_monomial(e, dim):
-    """integral of prod x_i^e_i over the unit dim-simplex (the last coordinate 1 - sum of the
-    others when len(e) = dim + 1)"""
-    num = 1
-    for a in e:
-        num *= factorial(a)
-    return Fraction(num, factorial(sum(e) + dim))
-
-
 def test_errors_closed_form_unit_tet():
     X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float).T.copy()
     T = np.array([[0, 2, 1, 3]], np.int32).T.copy()
@@ -57,22 +48,11 @@ def test_errors_closed_form_unit_tet():
     lam = torch.zeros(4, dtype=torch.float64, device=DEV)
     h = 0.75
     er = P.errors(dev(X), dev(T), gc, None, gp, U, lam, O.FUN_X2Y2Z2, (1.0,), h, nq=8)
-    # ||u||^2 = int x^4 y^4 z^4;  ||grad u||^2 = 3 * 4 int x^2 y^4 z^4
-    l22 = simplex_monomial((4, 4, 4), 3)
-    grad2 = 12 * simplex_monomial((2, 4, 4), 3)
-    # faces x = 0, y = 0, z = 0: grad u . nu = 0; face x + y + z = 1: grad u . nu =
-    # 2 xyz (xy + yz + zx) / sqrt 3, dS = sqrt 3 dx dy on the projected triangle
-    sq = {}
-    for a, b, w in [((1, 1, 0), (1, 1, 0), 1), ((0, 1, 1), (0, 1, 1), 1), ((1, 0, 1), (1, 0, 1), 1),
-                    ((1, 1, 0), (0, 1, 1), 2), ((1, 1, 0), (1, 0, 1), 2), ((0, 1, 1), (1, 0, 1), 2)]:
-        m = tuple(2 + i + j for i, j in zip(a, b))  # x^2 y^2 z^2 (xy + yz + zx)^2 term by term
-        sq[m] = sq.get(m, 0) + w
-    face = sum(w * simplex_monomial(m, 2) for m, w in sq.items())  # int over the projected triangle
-    lam_h2 = h * 4 / 3 * sqrt(3) * float(face)
-    assert abs(er["l22"] - float(l22)) <= 1e-14 * float(l22)
-    assert abs(er["grad2"] - float(grad2)) <= 1e-14 * float(grad2)
+    grad2, l22, lam_h2 = CF.unit_tet_x2y2z2(h)
+    assert abs(er["l22"] - l22) <= 1e-14 * l22
+    assert abs(er["grad2"] - grad2) <= 1e-14 * grad2
     assert abs(er["lam_h2"] - lam_h2) <= 1e-14 * lam_h2
-    assert abs(er["Y"] - sqrt(float(grad2) + float(l22) / h ** 2)) <= 1e-14 * er["Y"]
+    assert abs(er["Y"] - sqrt(grad2 + l22 / h ** 2)) <= 1e-14 * er["Y"]
 
 
 def test_errors_linear_exact():

@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 from paper_2509_11133_amd import meshes as M
+from tests import closed_forms as CF
 from tests import golden_io as G
 
 pytestmark = pytest.mark.cpu
@@ -561,6 +562,39 @@ def test_quadrature_monomials():
         exact = factorial(a) * factorial(b) * factorial(cc) / factorial(a + b + cc + 3)
         got = np.sum(w * pts[0] ** a * pts[1] ** b * pts[2] ** cc)
         assert got == pytest.approx(exact, rel=1e-13)
+
+
+def test_tri_quadrature_monomials():
+    """Collapsed Gauss rule on the unit triangle integrates x^a y^b = a!b!/(a+b+2)! for degree
+    <= 2n-2, and nothing of higher degree is claimed (degree 2n-1 is off)."""
+    from math import factorial
+    for n in (1, 2, 3, 5, 8):
+        pts, w = O.tri_rule(n)
+        assert pts.shape == (2, n * n)
+        assert np.all(pts >= 0) and np.all(pts.sum(0) <= 1) and np.all(w > 0)
+        for a in range(2 * n - 1):
+            for b in range(2 * n - 1 - a):
+                exact = factorial(a) * factorial(b) / factorial(a + b + 2)
+                got = np.sum(w * pts[0] ** a * pts[1] ** b)
+                assert got == pytest.approx(exact, rel=1e-13, abs=1e-300), (n, a, b)
+    pts, w = O.tri_rule(2)  # x^3 is degree 2n - 1 = 3: not exact
+    assert abs(np.sum(w * pts[0] ** 3) - 1 / 20) > 1e-6
+
+
+def test_errors_closed_form_unit_tet():
+    """The oracle's error sums on the unit tet with u = x^2 y^2 z^2, u_h = 0, lambda = 0 equal
+    the exact monomial integrals (rational arithmetic): pins the tet rule, the face rule with
+    its area factor, the outward normals and the factor h of the multiplier norm."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float).T.copy()
+    for T in (np.array([[0, 2, 1, 3]], np.int32).T.copy(), np.array([[3, 1, 2, 0]], np.int32).T.copy()):
+        conn = O.connect(4, T)
+        p = O.params(c=1.0, f=(O.FUN_X2Y2Z2_LOAD, (1.0, 1.0)), ud=(O.FUN_X2Y2Z2, (1.0,)))
+        for h in (0.75, 0.1):
+            er = O.errors(X, T, conn, None, p, np.zeros((4, 1)), np.zeros(4), O.FUN_X2Y2Z2, (1.0,), h, nq=8)
+            grad2, l22, lam_h2 = CF.unit_tet_x2y2z2(h)
+            assert abs(er["l22"] - l22) <= 1e-14 * l22
+            assert abs(er["grad2"] - grad2) <= 1e-14 * grad2
+            assert abs(er["lam_h2"] - lam_h2) <= 1e-14 * lam_h2
 
 
 # ------------------------------------------------------------------ adjoint (a10)
