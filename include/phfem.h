@@ -150,15 +150,34 @@ int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, v
  * Inputs: the coarse mesh and its phfem_connect edge outputs (+ Nodes2Edge CSR when
  * nDb + nNb > 0).  Outputs: coord_out[3][nC + nEd + nE], tetra_out[4][12 nE],
  * db_out[3][4 nDb], nb_out[3][4 nNb] (row strides = those counts).  Coordinates are
- * bitwise those of the paper's formulas.  Synchronizes only when nDb + nNb > 0
- * (EINVAL if a boundary face is not a mesh face).  A tet whose vertex, edge or derived
+ * bitwise those of the paper's formulas.  With boundary faces the call takes a workspace
+ * (phfem_refine_workspace; work may be NULL without them) for its error word and
+ * synchronizes once (EINVAL if a boundary face is not a mesh face; EWORKSPACE).  A tet whose vertex, edge or derived
  * node ids fall outside the mesh is skipped (its outputs are left unwritten, nothing is
  * written out of range); phfem_refine_connected reports such input. */
+size_t phfem_refine_workspace(int64_t nDb, int64_t nNb); /* 0 without boundary faces */
 int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
                  const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
                  const int32_t* n2e_rowptr, const int32_t* n2e_col, const int32_t* n2e_edge, int64_t nDb,
-                 const int32_t* db, int64_t nNb, const int32_t* nb, double* coord_out, int32_t* tetra_out,
-                 int32_t* db_out, int32_t* nb_out, phfem_stream_t stream);
+                 const int32_t* db, int64_t nNb, const int32_t* nb, void* work, size_t work_bytes,
+                 double* coord_out, int32_t* tetra_out, int32_t* db_out, int32_t* nb_out, phfem_stream_t stream);
+
+/* ---------------------------------------------------------------- face lookup ------- */
+/* Boundary faces of the mesh numbering named by node triples: the lookup the Multiplier
+ * routine of Section 4.4 makes for its Neumann faces (g_NFs) before it forms the load LN and
+ * removes those faces from the multiplier space.  tris[3][n]: n triangles (nodes in any
+ * order, e.g. a refined Nb list of phfem_refine); faces[3][nF], face2tet[2][nF]: the face
+ * numbering of phfem_connect / phfem_refine_connected.  Outputs: flags[nF] (uint8, 1 = the
+ * face is a boundary face whose node set is one of the triangles, else 0; the
+ * params.neumann array) and face_of[n] (may be NULL: the face id of each triangle).  n = 0
+ * writes zero flags and needs no workspace.  Triangles go into a hash table in the
+ * workspace (phfem_face_lookup_workspace(n)), probed once per face.  Synchronizes (one
+ * readback).  Errors: EINVAL (a triangle with a node out of range or a repeated node, or one
+ * that is not a boundary face of the mesh; outputs then unspecified), EWORKSPACE. */
+size_t phfem_face_lookup_workspace(int64_t n);
+int phfem_face_lookup(int64_t nC, int64_t nF, const int32_t* faces, const int32_t* face2tet, int64_t n,
+                      const int32_t* tris, void* work, size_t work_bytes, uint8_t* flags, int32_t* face_of,
+                      phfem_stream_t stream);
 
 /* Refinement with connectivity: phfem_refine's outputs plus the refined mesh's full
  * phfem_connect outputs (edges, tet2edge, edge_first_tet, tet_edge_prefix, faces,
@@ -239,10 +258,14 @@ size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t prec
  *   explicit zeros in column F (boundary faces are O(nF^(2/3)), so the padding is a
  *   vanishing fraction and the row pointers need no scan).
  * Each off-diagonal has exactly one contributing tet; a diagonal / rhs entry is the owner
- * tet's term plus the neighbour's (in that order).  Two coalesced passes: four slot records
- * per tet (row k of the element Schur block, (C A^-1 B)_k, the other face ids; FP32 records
- * in mixed precision), then one thread per face writes its whole row.  Inputs from
- * phfem_connect (nbr is not read and may be NULL).
+ * tet's term plus the neighbour's (in that order).  Tiles of 256 consecutive tets, two
+ * passes: every tet whose face is owned by a tet of another tile writes that face's row of
+ * its element block as a record (row k of the element Schur block, (C A^-1 B)_k, the other
+ * face ids; FP32 records in mixed precision); then each tile recomputes its tets' blocks in
+ * LDS and writes the rows of the faces it owns (a contiguous id range, faces being numbered
+ * at their owner), taking the second tet's row from LDS or from its record.  Inputs from
+ * phfem_connect or phfem_refine_connected (nbr required: it tells the tets with cross-tile
+ * faces apart).  col 8-byte and val 16-byte aligned (vector stores of a row's slots).
  * Errors: EINVAL, ESINGULAR, EWORKSPACE.  Does not synchronize (EDEGEN is reported by
  * phfem_solve). */
 int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
@@ -261,15 +284,15 @@ int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* t
  * stays valid; it saves the 28 B/face of col and row pointers).  The coordinate copy is built
  * once per call and the fields are condensed in turn (measured faster than one fused pass,
  * whose per-field registers cost occupancy); field j's arrays equal phfem_condense's with
- * kappa + j nE, bit for bit.  Workspace: phfem_condense_batch_workspace (one field's slot
- * records, independent of nk).
+ * kappa + j nE, bit for bit.  Workspace: phfem_condense_batch_workspace (one field's
+ * cross-tile records, independent of nk).
  * Errors: EINVAL (also for only one of rowptr / col), ESINGULAR, EWORKSPACE.  Does not
  * synchronize. */
 size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision, int32_t nk);
 int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
-                         const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
-                         int32_t nk, const double* kappa, const phfem_params* p, void* work, size_t work_bytes,
-                         int32_t* rowptr, int32_t* col, double* val, double* diag, double* rhs,
+                         const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* nbr,
+                         const int32_t* face2tet, int32_t nk, const double* kappa, const phfem_params* p, void* work,
+                         size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag, double* rhs,
                          phfem_stream_t stream);
 
 /* ---------------------------------------------------------------- solve (a8-a9) ------ */
@@ -296,8 +319,8 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  *    stored system is solved again for the correction (iterative refinement; the stored
  *    system differs from the matrix-free operator by assembly rounding, so the recurrence
  *    alone levels off near 3.5e-11 relative at Kuhn L5 with lognormal kappa).  Stops after 8
- *    corrections or when one no longer halves the true residual; stats.rel_res is then the
- *    attainable accuracy.
+ *    corrections or when one no longer halves the true residual, then with ENOCONV if the
+ *    true residual is still above tol (stats.rel_res is the attainable accuracy).
  *  mode FP32_PCG_FP64_IR: iterative refinement without restarts: one FP32 PCG recurrence on
  *    the Jacobi-scaled FP32 copy D^-1/2 S+ D^-1/2 of the system (unit diagonal, so CG there
  *    is Jacobi-PCG on S+ with no diagonal reads and no z vector), whose residual is
@@ -312,9 +335,13 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  *    tol, or with ENOCONV when 6 replacements in a row gain less than 10 % (tol below the
  *    attainable accuracy, about 6e-13 relative at Kuhn L5).  stats.ir_steps counts the
  *    replacements.
+ * The true residual is summed per face from the per-tet terms, owner's first, so the
+ * whole solve is bitwise reproducible run to run.
  * Outputs: lambda[nF], U[4][nE] (float64).  Synchronizes (residual checks every few
- * iterations).  Errors: EINVAL, EDEGEN, ENOCONV (max_iter reached; outputs and stats hold
- * the last iterate), EWORKSPACE. */
+ * iterations).  Errors: EINVAL (also a vertex, face or slot id out of range, found on the
+ * device), EDEGEN (zero-volume tet), ENOCONV (max_iter reached, or -- either mode -- the
+ * refinement stopped gaining above tol: outputs and stats hold the last iterate and its
+ * attainable rel_res), EWORKSPACE. */
 int phfem_solve(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
                 const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
                 const double* kappa, const phfem_params* p, const int32_t* rowptr, const int32_t* col,
@@ -331,8 +358,11 @@ size_t phfem_grad_workspace(int64_t nE, int64_t nF, int32_t mode);
  *   dJ/dlog kappa_T = -kappa_T P_T' K_T U_T,
  *   dJ/dX = -d/dX [P'A U - lambda'C P - P'B - Q'C U + Q'b_D]  (P, U, lambda, Q fixed).
  * Outputs: dJ_dlogkappa[nE] (may be NULL), dJ_dcoord[3][nC] (may be NULL; zeroed and
- * accumulated with atomics).  Synchronizes.  Errors as phfem_solve; EINVAL when
- * params.neumann is set (the gradient covers Dirichlet boundaries only). */
+ * accumulated with atomics, the one result that is not bitwise reproducible).
+ * Synchronizes.  Errors as phfem_solve (ids out of range and zero volumes are also checked
+ * in the gradient pass; ENOCONV: the adjoint solve stopped above tol, and the outputs hold
+ * the gradient of its last iterate); EINVAL when params.neumann is set (the gradient covers
+ * Dirichlet boundaries only). */
 int phfem_grad(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF, const int32_t* faces,
                const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet, const int32_t* nbr,
                const double* kappa, const phfem_params* p, const int32_t* rowptr, const int32_t* col,

@@ -28,7 +28,8 @@ EXPORTS = [
     "phfem_grad_workspace", "phfem_grad", "phfem_profile_enable", "phfem_profile_reset", "phfem_profile_query",
     "phfem_profile_names", "phfem_refine_connected_workspace", "phfem_refine_connected", "phfem_refined_sizes",
     "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels", "phfem_errors_workspace",
-    "phfem_errors", "phfem_condense_batch_workspace", "phfem_condense_batch",
+    "phfem_errors", "phfem_condense_batch_workspace", "phfem_condense_batch", "phfem_refine_workspace",
+    "phfem_face_lookup_workspace", "phfem_face_lookup",
 ]
 
 
@@ -97,7 +98,7 @@ def lib():
         for n in ("phfem_connect_workspace", "phfem_condense_workspace", "phfem_solve_workspace",
                   "phfem_grad_workspace", "phfem_refine_connected_workspace",
                   "phfem_refine_connected_levels_workspace", "phfem_errors_workspace",
-                  "phfem_condense_batch_workspace"):
+                  "phfem_condense_batch_workspace", "phfem_refine_workspace", "phfem_face_lookup_workspace"):
             getattr(L, n).restype = SZ
         L.phfem_connect_workspace.argtypes = [I64, I64, I32]
         L.phfem_condense_workspace.argtypes = [I64, I64, I64, I32]
@@ -110,7 +111,11 @@ def lib():
                                                     + [VP] * 11 + [VP] * 3)
         L.phfem_refine_connected.argtypes = [I64, VP, I64, VP, I64, I64] + [VP] * 5 + [VP, SZ] + [VP] * 11 + [VP] * 3
         L.phfem_connect.argtypes = [I64, I64, VP, I32, VP, SZ] + [VP] * 12 + [VP, VP]
-        L.phfem_refine.argtypes = [I64, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP]
+        L.phfem_refine_workspace.argtypes = [I64, I64]
+        L.phfem_refine.argtypes = ([I64, VP, I64, VP, I64, VP, VP, VP, VP, VP, VP, I64, VP, I64, VP, VP, SZ]
+                                   + [VP] * 4 + [VP])
+        L.phfem_face_lookup_workspace.argtypes = [I64]
+        L.phfem_face_lookup.argtypes = [I64, I64, VP, VP, I64, VP, VP, SZ, VP, VP, VP]
         L.phfem_assemble.argtypes = [I64, VP, I64, VP, VP, VP, VP] + [VP] * 6 + [VP]
         L.phfem_condense.argtypes = [I64, VP, I64, VP, I64] + [VP] * 7 + [VP, SZ] + [VP] * 5 + [VP]
         L.phfem_solve.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 6 + [VP] * 5 + [I32, DBL, DBL, I32, VP, SZ]
@@ -119,7 +124,7 @@ def lib():
                                  + [I32, DBL, DBL, I32, VP, SZ] + [VP] * 3 + [VP])
         L.phfem_errors_workspace.argtypes = [I64]
         L.phfem_condense_batch_workspace.argtypes = [I64, I64, I64, I32, I32]
-        L.phfem_condense_batch.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [I32, VP, VP, VP, SZ] + [VP] * 5 + [VP]
+        L.phfem_condense_batch.argtypes = [I64, VP, I64, VP, I64] + [VP] * 5 + [I32, VP, VP, VP, SZ] + [VP] * 5 + [VP]
         L.phfem_errors.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, SZ, VP, VP]
         L.phfem_profile_enable.argtypes = [I32]
         L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
@@ -162,10 +167,16 @@ def phfem_connect(nC, nE, tetra, flags, work, edges, tet2edge, edge_first_tet, t
 
 
 def phfem_refine(nC, coord, nE, tetra, nEd, tet2edge, edge_first_tet, tet_edge_prefix, n2e_rowptr, n2e_col, n2e_edge,
-                 nDb, db, nNb, nb, coord_out, tetra_out, db_out, nb_out):
+                 nDb, db, nNb, nb, work, coord_out, tetra_out, db_out, nb_out):
     _chk(lib().phfem_refine(nC, _p(coord), nE, _p(tetra), nEd, _p(tet2edge), _p(edge_first_tet), _p(tet_edge_prefix),
-                            _p(n2e_rowptr), _p(n2e_col), _p(n2e_edge), nDb, _p(db), nNb, _p(nb), _p(coord_out),
-                            _p(tetra_out), _p(db_out), _p(nb_out), _stream()))
+                            _p(n2e_rowptr), _p(n2e_col), _p(n2e_edge), nDb, _p(db), nNb, _p(nb), _p(work),
+                            0 if work is None else work.numel(), _p(coord_out), _p(tetra_out), _p(db_out),
+                            _p(nb_out), _stream()))
+
+
+def phfem_face_lookup(nC, nF, faces, face2tet, n, tris, work, flags, face_of):
+    _chk(lib().phfem_face_lookup(nC, nF, _p(faces), _p(face2tet), n, _p(tris), _p(work),
+                                 0 if work is None else work.numel(), _p(flags), _p(face_of), _stream()))
 
 
 def phfem_refine_connected(nC, coord, nE, tetra, nEd, nF, tet2edge, edge_first_tet, tet_edge_prefix, tet2face, nbr,
@@ -209,9 +220,9 @@ def phfem_condense(nC, coord, nE, tetra, nF, faces, tet2face, sigma, nbr, face2t
                               _p(val), _p(diag), _p(rhs), _stream()))
 
 
-def phfem_condense_batch(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, nk, kappa, prm, work, rowptr,
-                         col, val, diag, rhs):
-    _chk(lib().phfem_condense_batch(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma),
+def phfem_condense_batch(nC, coord, nE, tetra, nF, faces, tet2face, sigma, nbr, face2tet, nk, kappa, prm, work,
+                         rowptr, col, val, diag, rhs):
+    _chk(lib().phfem_condense_batch(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(nbr),
                                     _p(face2tet), nk, _p(kappa), C.addressof(prm), _p(work), work.numel(), _p(rowptr),
                                     _p(col), _p(val), _p(diag), _p(rhs), _stream()))
 
@@ -227,11 +238,14 @@ def phfem_solve(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, kapp
 
 
 def phfem_grad(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, nbr, kappa, prm, rowptr, col, val, diag, U,
-               lam, dJdU, mode, tol, inner_tol, max_iter, work, dlogk, dX, stats):
-    _chk(lib().phfem_grad(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(face2tet), _p(nbr),
+               lam, dJdU, mode, tol, inner_tol, max_iter, work, dlogk, dX, stats, check=True):
+    rc = lib().phfem_grad(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(face2tet), _p(nbr),
                           _p(kappa), C.addressof(prm), _p(rowptr), _p(col), _p(val), _p(diag), _p(U), _p(lam),
                           _p(dJdU), mode, tol, inner_tol, max_iter, _p(work), work.numel(), _p(dlogk), _p(dX),
-                          C.addressof(stats), _stream()))
+                          C.addressof(stats), _stream())
+    if check:
+        _chk(rc)
+    return rc
 
 
 def phfem_errors(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, prm, U, lam, u_kind, u_par, h, nq, work):

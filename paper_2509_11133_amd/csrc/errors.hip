@@ -196,24 +196,20 @@ __global__ __launch_bounds__(ERT) void k_errors_sum(int64_t nb, const double* __
   }
 }
 
-}  // namespace ph
+__global__ void k_errors_clear(uint32_t* __restrict__ bad) { *bad = 0u; }
 
-using namespace ph;
-
-extern "C" size_t phfem_errors_workspace(int64_t nE) {
-  if (nE <= 0) return 0;
+static size_t errors_scratch_bytes(int64_t nE) {
   Arena a;
-  a.take<double>(3 * ((nE + ERT - 1) / ERT) + 4);
+  a.take<double>(3 * ((nE + ERT - 1) / ERT));
+  a.take<double>(4);
   a.take<uint32_t>(1);
   return a.size();
 }
 
-extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
-                            const int32_t* tet2face, const int8_t* sigma, const double* kappa, const phfem_params* p,
-                            const double* U, const double* lambda, int32_t u_kind, const double* u_par, double h,
-                            int32_t nq, void* work, size_t work_bytes, double* out, phfem_stream_t stream_) {
-  clear_error();
-  hipStream_t s = (hipStream_t)stream_;
+static int errors_args_ok(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                          const int32_t* tet2face, const int8_t* sigma, const phfem_params* p, const double* U,
+                          const double* lambda, int32_t u_kind, const double* u_par, double h, int32_t nq,
+                          double* out) {
   int rc = check_params(p);
   if (rc) return rc;
   if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !tet2face || !sigma || !U || !lambda || !out || !u_par)
@@ -221,8 +217,15 @@ extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const i
   if (u_kind < 0 || u_kind > PHFEM_FUN_X2Y2Z2_LOAD) return err(PHFEM_EINVAL, "bad u_kind");
   if (nq < 1 || nq > ERMAXQ) return err(PHFEM_EINVAL, "nq must be in [1, 12]");
   if (!(h > 0)) return err(PHFEM_EINVAL, "h must be > 0");
-  if (!work || work_bytes < phfem_errors_workspace(nE)) return err(PHFEM_EWORKSPACE, "errors workspace too small");
-  Arena a(work, work_bytes);
+  return PHFEM_OK;
+}
+
+// the error sums with their scratch in (base, cap): per-block partials, totals, check word
+static int errors_run(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                      const int32_t* tet2face, const int8_t* sigma, const double* kappa, const phfem_params* p,
+                      const double* U, const double* lambda, int32_t u_kind, const double* u_par, double h,
+                      int32_t nq, void* base, size_t cap, double* out, hipStream_t s) {
+  Arena a(base, cap);
   const int64_t nb = (nE + ERT - 1) / ERT;
   double* part = a.take<double>(3 * nb);
   double* dout = a.take<double>(4);
@@ -230,7 +233,7 @@ extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const i
   Fun4 up;
   for (int i = 0; i < 4; ++i) up.p[i] = u_par[i];
   const GL1 q = gauss_legendre01(nq);
-  PH_HIP(hipMemsetAsync(bad, 0, sizeof(uint32_t), s));
+  PH_LAUNCH("errors_clear", k_errors_clear, 1, 1, 0, s, bad);
   PH_LAUNCH("errors", k_errors, (unsigned)nb, ERT, 0, s, nC, coord, nE, nF, tetra, tet2face, sigma, kappa, to_dev(*p),
             U, lambda, u_kind, up, h, q, part, bad);
   PH_LAUNCH("errors_sum", k_errors_sum, 1, ERT, 0, s, nb, (const double*)part, dout);
@@ -242,4 +245,25 @@ extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const i
   if (hbad) return err(PHFEM_EINVAL, "vertex or face id out of range");
   for (int i = 0; i < 3; ++i) out[i] = res[i];
   return PHFEM_OK;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" size_t phfem_errors_workspace(int64_t nE) {
+  if (nE <= 0) return 0;
+  return errors_scratch_bytes(nE);
+}
+
+extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                            const int32_t* tet2face, const int8_t* sigma, const double* kappa, const phfem_params* p,
+                            const double* U, const double* lambda, int32_t u_kind, const double* u_par, double h,
+                            int32_t nq, void* work, size_t work_bytes, double* out, phfem_stream_t stream_) {
+  clear_error();
+  int rc = errors_args_ok(nC, coord, nE, tetra, nF, tet2face, sigma, p, U, lambda, u_kind, u_par, h, nq, out);
+  if (rc) return rc;
+  if (!work || work_bytes < phfem_errors_workspace(nE)) return err(PHFEM_EWORKSPACE, "errors workspace too small");
+  return errors_run(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, p, U, lambda, u_kind, u_par, h, nq, work,
+                    work_bytes, out, (hipStream_t)stream_);
 }

@@ -21,7 +21,6 @@
 namespace ph {
 
 constexpr int FT = 256;
-constexpr int ET64 = 128;
 
 template <class R>
 struct Elem {
@@ -275,7 +274,7 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
                                                   const int32_t* __restrict__ faces,
                                                   const int32_t* __restrict__ face2tet, DevParams P,
                                                   uint32_t* __restrict__ cnt, double* __restrict__ diag,
-                                                  double* __restrict__ rhs) {
+                                                  double* __restrict__ rhs, int* __restrict__ flags) {
   int64_t f = (int64_t)blockIdx.x * FT + threadIdx.x;
   if (f > nF) return;
   if (f == nF) {
@@ -289,12 +288,18 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
   double b = 0.0;
   if (!interior && P.uk != PHFEM_FUN_ZERO && !(P.nm && P.nm[f])) {
     double x[3][3];
+    bool inr = true;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       int v = faces[m * nF + f];
+      if ((uint32_t)v >= (uint64_t)nC) {
+        inr = false;
+        v = 0;
+      }
 #pragma unroll
       for (int e = 0; e < 3; ++e) x[m][e] = X[e * nC + v];
     }
+    if (!inr && flags) atomicOr(flags, DEV_BADNODE);
     double u0 = x[2][0] - x[0][0], u1 = x[2][1] - x[0][1], u2 = x[2][2] - x[0][2];
     double s0 = x[1][0] - x[0][0], s1 = x[1][1] - x[0][1], s2 = x[1][2] - x[0][2];
     double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
@@ -306,15 +311,24 @@ __global__ __launch_bounds__(FT) void k_face_init(int64_t nF, int64_t nC, const 
   rhs[f] = b;
 }
 
-// Condensation in two passes (no atomics):
-//  k_elem_rec: one tet -> four slot records (slot 4t+k: row k of S(T), (C A^-1 B)_k and the
-//              ids of the other three faces), staged in LDS and stored with coalesced
-//              full-line writes;
-//  k_face_rows: one face -> its whole CSR row from the slots of its owner and neighbour
-//              (face2tet): off-diagonals sorted by column, diagonal S_owner + S_neighbour
-//              and rhs (b_D - r_owner) - r_neighbour in that order.
-// The neighbour slot is a random read; scattering the records to face order instead would
-// turn it into a random partial-line write, which costs more.
+// Condensation (no atomics), tiles of CT consecutive tets (the workgroup).  A face is numbered
+// at its owner (lowest tet index), so the faces owned by a tile's tets form one contiguous id
+// range, and in the meshes the refinement produces about three quarters of the interior
+// faces have their second tet in the owner's tile as well (siblings are numbered close
+// together).  Two passes:
+//  k_cond_cross: every tet computes its element block; a tet whose face is owned by a tet of
+//                another tile writes that face's row of its block (S_kk, (C A^-1 B)_k, the
+//                three S_kl and their face ids) as a 32-byte record at slot 4t+k;
+//  k_cond_tile:  the tile recomputes its tets' blocks into LDS and writes the rows of the
+//                faces it owns: owner's row and, for the second tet, its row from LDS when it
+//                lies in the tile, else its record; off-diagonals sorted by column, diagonal
+//                S_owner + S_neighbour and rhs (b_D - r_owner) - r_neighbour in that order.
+// The element arithmetic is done twice (it is cheap next to the memory traffic); what
+// crosses HBM is the input once per pass, one record per cross-tile face and the rows.
+// Neumann faces (params.neumann): LN in the load, the face's row becomes lambda_F = g (S_kk
+// = 1, r_k = -g, no coupling), and its coupling entries in every other row are zero (S_kl =
+// S_lk = 0), the paper's system over the other faces without renumbering.
+
 // position of S_kl (either order) in the row-major upper triangle of a 4x4 matrix
 __host__ __device__ constexpr int uidx(int k, int l) {
   return k <= l ? (k * (7 - k)) / 2 + l : (l * (7 - l)) / 2 + k;
@@ -322,6 +336,8 @@ __host__ __device__ constexpr int uidx(int k, int l) {
 static_assert(uidx(0, 0) == 0 && uidx(0, 3) == 3 && uidx(1, 1) == 4 && uidx(2, 1) == 5 && uidx(2, 2) == 7 &&
                   uidx(3, 3) == 9,
               "upper-triangle index");
+
+constexpr int CT = 256;  // tets per tile = threads per workgroup of both passes
 
 template <class R>
 struct SlotRec {  // row k of one tet's element Schur block S(T) and (C A^-1 B)_k
@@ -332,18 +348,38 @@ struct SlotRec {  // row k of one tet's element Schur block S(T) and (C A^-1 B)_
 };
 static_assert(sizeof(SlotRec<float>) == 32 && sizeof(SlotRec<double>) == 56, "packed slot records");
 
-// the four slot records of one tet for one coefficient value, into the thread's LDS slots
+// a record as whole 16-byte stores (32 B in FP32, 56 B in FP64)
 template <class R>
-__device__ __forceinline__ void elem_records(const double (&x)[4][3], const int (&sig)[4], const int (&F)[4],
-                                             double kap, const DevParams& P, int64_t nF, uint2* lrec) {
+__device__ __forceinline__ void store_rec(SlotRec<R>* p, const SlotRec<R>& q) {
   constexpr int W = sizeof(SlotRec<R>) / 8;
+  union {
+    SlotRec<R> rec;
+    uint2 w[W];
+  } u;
+  u.rec = q;
+  uint2* d = reinterpret_cast<uint2*>(p);
+  if (W % 2 == 0) {
+#pragma unroll
+    for (int m = 0; m < W; m += 2)
+      *reinterpret_cast<uint4*>(d + m) = make_uint4(u.w[m].x, u.w[m].y, u.w[m + 1].x, u.w[m + 1].y);
+  } else {
+#pragma unroll
+    for (int m = 0; m < W; ++m) d[m] = u.w[m];
+  }
+}
+
+// One tet's element Schur block (upper triangle su) and r = C A^-1 B, with the Neumann rows
+// and columns of its faces set as described above.  F: its face ids (nF bounds the flag reads).
+template <class R>
+__device__ __forceinline__ void elem_block(const double (&x)[4][3], const int (&sig)[4], const int (&F)[4], double kap,
+                                           const DevParams& P, int64_t nF, R (&su)[10], R (&r)[4]) {
   Elem<R> E;
   E.init(x, kap, P.c, sig);
-  R B[4], r[4], su[10];
+  R B[4];
   load_vec<R>(x, E.vol, P, B);
   bool neu[4] = {false, false, false, false};
   double gN[4] = {0, 0, 0, 0};
-  if (P.nm) {  // Neumann faces: LN in the load; their rows become lambda_F = g
+  if (P.nm) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       neu[k] = (uint32_t)F[k] < (uint64_t)nF && P.nm[F[k]];
@@ -357,121 +393,99 @@ __device__ __forceinline__ void elem_records(const double (&x)[4][3], const int 
   }
   E.CAinv(B, r);
   E.Supper(su);
+  if (P.nm) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    union {
-      SlotRec<R> rec;
-      uint2 w[W];
-    } u;
-    u.rec.d = neu[k] ? (R)1 : su[uidx(k, k)];
-    u.rec.r = neu[k] ? (R)(-gN[k]) : r[k];
-    int n = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (!neu[k]) continue;
+      r[k] = (R)(-gN[k]);
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      if (l == k) continue;
-      u.rec.o[n] = neu[k] ? (R)0 : su[uidx(k, l)];
-      u.rec.c[n] = neu[l] ? (int32_t)((uint32_t)F[l] | 0x80000000u) : F[l];  // a Neumann column: no coupling
-      ++n;
+      for (int l = 0; l < 4; ++l) su[uidx(k, l)] = l == k ? (R)1 : (R)0;
     }
-#pragma unroll
-    for (int m = 0; m < W; ++m) lrec[k * W + m] = u.w[m];
   }
 }
 
-// workgroup size of k_elem_rec: FP64 records (56 B) stage 4 x 56 B per thread, so FP64 takes
-// smaller workgroups to keep several resident per CU
-template <class R>
-constexpr int elem_threads() {
-  return sizeof(R) == 8 ? ET64 : FT;
+// the tet's vertex ids (clamped into range: invalid input gives garbage, never a read out of
+// range), sigma, face ids and coordinates
+__device__ __forceinline__ void elem_inputs(int64_t nC, const double4* __restrict__ XA, int64_t nE, int64_t t,
+                                            const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                            const int8_t* __restrict__ sigma, int (&sig)[4], int (&F)[4],
+                                            double (&x)[4][3]) {
+  int v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = tet[i * nE + t];
+    if ((uint32_t)v[i] >= (uint64_t)nC) v[i] = 0;
+    sig[i] = sigma[i * nE + t];
+    F[i] = t2f[i * nE + t];
+  }
+  gather_xa(XA, v, x);
 }
 
+// A workgroup scans CX consecutive tets for cross-tile faces and computes the element blocks
+// of the ones that have any (about a third in refined meshes) from a compacted LDS list, so
+// the element arithmetic runs only where a record is written.
+constexpr int CXK = 4;
+constexpr int CX = CT * CXK;
+
 template <class R>
-__global__ __launch_bounds__(elem_threads<R>()) void k_elem_rec(int64_t nC, const double4* __restrict__ XA, int64_t nE,
-                                                 const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
-                                                 const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
-                                                 DevParams P, int64_t nF, SlotRec<R>* __restrict__ recs) {
-  constexpr int W = sizeof(SlotRec<R>) / 8;
-  constexpr int NT = elem_threads<R>();
-  __shared__ uint2 lrec[4 * NT * W];
-  const int64_t t0 = (int64_t)blockIdx.x * NT;
-  const int64_t t = t0 + threadIdx.x;
-  if (t < nE) {
-    int v[4], sig[4], F[4];
+__global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __restrict__ XA, int64_t nE,
+                                                   const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                                   const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
+                                                   const double* __restrict__ kappa, DevParams P, int64_t nF,
+                                                   SlotRec<R>* __restrict__ recs) {
+  __shared__ int32_t lt[CX];
+  __shared__ int32_t lcnt;
+  const int64_t T0 = (int64_t)blockIdx.x * CX;
+  if (threadIdx.x == 0) lcnt = 0;
+  __syncthreads();
+  int nbv[CXK][4], sgv[CXK][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v[i] = tet[i * nE + t];
-      if ((uint32_t)v[i] >= (uint64_t)nC) v[i] = 0;
-      sig[i] = sigma[i * nE + t];
-      F[i] = t2f[i * nE + t];
+  for (int j = 0; j < CXK; ++j) {
+    const int64_t t = T0 + j * CT + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      nbv[j][k] = t < nE ? nbr[k * nE + t] : -1;
+      sgv[j][k] = t < nE ? sigma[k * nE + t] : 1;
     }
-    double x[4][3];
-    gather_xa(XA, v, x);
-    elem_records<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, lrec + 4 * threadIdx.x * W);
+  }
+#pragma unroll
+  for (int j = 0; j < CXK; ++j) {
+    const int64_t t = T0 + j * CT + threadIdx.x;
+    const int64_t tile = t / CT;
+    int cross = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (sgv[j][k] < 0 && nbv[j][k] >= 0 && nbv[j][k] / CT != tile) cross |= 1 << k;
+    if (cross) lt[atomicAdd(&lcnt, 1)] = (int32_t)((t - T0) << 4 | cross);
   }
   __syncthreads();
-  const int64_t nb = nE - t0 < NT ? nE - t0 : NT;
-  uint2* out = reinterpret_cast<uint2*>(recs + 4 * t0);
-  for (int i = threadIdx.x; i < 4 * nb * W; i += NT) out[i] = lrec[i];
-}
-
-// One face's row from its owner's slot q0 and its neighbour's slot q1 (-1 on the boundary):
-// the 6 (column, value) pairs unsorted (boundary: 3 pads INT_MAX / 0), diagonal, and the rhs
-// b_D - r_owner - r_neighbour.
-template <class R>
-__device__ __forceinline__ void face_row(const SlotRec<R>* __restrict__ recs, int q0, int q1, double bD,
-                                         const DevParams& P, int (&cf)[6], double (&cv)[6], double& dg,
-                                         double& rh) {
-  const SlotRec<R> a = recs[q0];  // owner's slot: row k of its element block
-  dg = (double)a.d;
-  rh = bD - (double)a.r;
+  const int n = lcnt;
+  for (int i = threadIdx.x; i < n; i += CT) {
+    const int w = lt[i];
+    const int64_t t = T0 + (w >> 4);
+    const int cross = w & 15;
+    int sig[4], F[4];
+    double x[4][3];
+    elem_inputs(nC, XA, nE, t, tet, t2f, sigma, sig, F, x);
+    R su[10], r[4];
+    elem_block<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, su, r);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    cf[i] = a.c[i];
-    cv[i] = (double)a.o[i];
-  }
-  if (q1 >= 0) {
-    const SlotRec<R> bq = recs[q1];  // neighbour's slot
-    dg += (double)bq.d;
-    rh -= (double)bq.r;
+    for (int k = 0; k < 4; ++k) {
+      if (!(cross & (1 << k))) continue;
+      SlotRec<R> q;
+      q.d = su[uidx(k, k)];
+      q.r = r[k];
+      int m = 0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      cf[3 + i] = bq.c[i];
-      cv[3 + i] = (double)bq.o[i];
-    }
-  } else {
-#pragma unroll
-    for (int i = 3; i < 6; ++i) {
-      cf[i] = INT_MAX;  // sorts last; written as column F with value 0
-      cv[i] = 0.0;
-    }
-  }
-  if (P.nm) {  // columns of Neumann faces carry no coupling
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-      if (cf[i] != INT_MAX && (cf[i] & 0x80000000)) {
-        cf[i] &= 0x7fffffff;
-        cv[i] = 0.0;
+      for (int l = 0; l < 4; ++l) {
+        if (l == k) continue;
+        q.o[m] = su[uidx(k, l)];
+        q.c[m] = F[l];
+        ++m;
       }
+      store_rec(recs + 4 * t + k, q);
+    }
   }
-}
-
-// b_D = |F| u_D(centroid) of a Dirichlet boundary face (0 elsewhere)
-__device__ __forceinline__ double face_bD(int64_t nF, int64_t nC, const double* __restrict__ X,
-                                          const int32_t* __restrict__ faces, const DevParams& P, int64_t f, int q1) {
-  if (q1 >= 0 || P.uk == PHFEM_FUN_ZERO || (P.nm && P.nm[f])) return 0.0;
-  double xx[3][3];
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    int vv = faces[m * nF + f];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) xx[m][e] = X[e * nC + vv];
-  }
-  double u0 = xx[2][0] - xx[0][0], u1 = xx[2][1] - xx[0][1], u2 = xx[2][2] - xx[0][2];
-  double s0 = xx[1][0] - xx[0][0], s1 = xx[1][1] - xx[0][1], s2 = xx[1][2] - xx[0][2];
-  double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
-  double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-  return area * fun_at<double>(P.uk, P.up, (xx[0][0] + xx[1][0] + xx[2][0]) / 3.0,
-                               (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
 }
 
 // rank of each of the 6 columns (ties by position; pads last)
@@ -485,68 +499,221 @@ __device__ __forceinline__ void col_ranks(const int (&cf)[6], int (&rk)[6]) {
   }
 }
 
-// rowptr and col are written only when given (null: the pattern an earlier call wrote for the
-// same connectivity is reused).
-template <class R>
-__global__ __launch_bounds__(FT) void k_face_rows(int64_t nF, int64_t nC, const double* __restrict__ X,
-                                                  const int32_t* __restrict__ faces,
-                                                  const int32_t* __restrict__ face2tet, DevParams P,
+// b_D = |F| u_D(centroid) of a Dirichlet boundary face (0 elsewhere)
+__device__ __forceinline__ double face_bD(int64_t nF, int64_t nC, const double* __restrict__ X,
+                                          const int32_t* __restrict__ faces, const DevParams& P, int64_t f, int q1) {
+  if (q1 >= 0 || P.uk == PHFEM_FUN_ZERO || (P.nm && P.nm[f])) return 0.0;
+  double xx[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    int vv = faces[m * nF + f];
+    if ((uint32_t)vv >= (uint64_t)nC) vv = 0;  // invalid input: no read out of range
+#pragma unroll
+    for (int e = 0; e < 3; ++e) xx[m][e] = X[e * nC + vv];
+  }
+  double u0 = xx[2][0] - xx[0][0], u1 = xx[2][1] - xx[0][1], u2 = xx[2][2] - xx[0][2];
+  double s0 = xx[1][0] - xx[0][0], s1 = xx[1][1] - xx[0][1], s2 = xx[1][2] - xx[0][2];
+  double n0 = u1 * s2 - u2 * s1, n1 = u2 * s0 - u0 * s2, n2 = u0 * s1 - u1 * s0;
+  double area = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+  return area * fun_at<double>(P.uk, P.up, (xx[0][0] + xx[1][0] + xx[2][0]) / 3.0,
+                               (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
+}
+
+// Rows of the faces owned by tile blockIdx.x.  PATTERN: also rowptr and col (values-only
+// re-assembly leaves them to an earlier call).
+template <class R, bool PATTERN>
+__global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __restrict__ XA,
+                                                  const double* __restrict__ X, int64_t nE,
+                                                  const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
+                                                  const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
+                                                  DevParams P, int64_t nF, const int32_t* __restrict__ faces,
+                                                  const int32_t* __restrict__ face2tet,
                                                   const SlotRec<R>* __restrict__ recs, int32_t* __restrict__ rowptr,
                                                   int32_t* __restrict__ col, double* __restrict__ val,
                                                   double* __restrict__ diag, double* __restrict__ rhs) {
-  __shared__ int32_t lcol[6 * FT];
-  __shared__ double lval[6 * FT];
-  const int64_t f0 = (int64_t)blockIdx.x * FT;
-  const int64_t f = f0 + threadIdx.x;
-  const int nb = nF - f0 < FT ? (int)(nF - f0) : FT;
-  const int base = 6 * (int)(f - f0);
-  if (f < nF) {
-    const int q0 = face2tet[f], q1 = face2tet[nF + f];
-    const double bD = face_bD(nF, nC, X, faces, P, f, q1);
-    int cf[6], rk[6];
-    double cv[6], dg, rh;
-    face_row<R>(recs, q0, q1, bD, P, cf, cv, dg, rh);
-    col_ranks(cf, rk);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      lcol[base + rk[i]] = cf[i] == INT_MAX ? (int32_t)f : cf[i];
-      lval[base + rk[i]] = cv[i];
-    }
-    st_nt(diag + f, dg);
-    st_nt(rhs + f, rh);
-    if (rowptr) {
-      st_nt(rowptr + f, (int32_t)(6 * f));
-      if (f == nF - 1) rowptr[nF] = (int32_t)(6 * nF);
-    }
+  __shared__ R lS[10][CT];
+  __shared__ R lr[4][CT];
+  __shared__ int32_t lF[4][CT];
+  __shared__ int32_t lcol[PATTERN ? 6 * CT : 1];
+  __shared__ double lval[6 * CT];
+  __shared__ int32_t lrange[2];
+  const int64_t T0 = (int64_t)blockIdx.x * CT;
+  const int nb = nE - T0 < CT ? (int)(nE - T0) : CT;
+  const int o = threadIdx.x;
+  if (o == 0) {
+    lrange[0] = INT_MAX;
+    lrange[1] = -1;
   }
   __syncthreads();
-  if (col) {
-    for (int i = threadIdx.x; i < 6 * nb; i += FT) {
-      st_nt(col + 6 * f0 + i, lcol[i]);
-      st_nt(val + 6 * f0 + i, lval[i]);
+  int fmin = INT_MAX, fmax = -1;
+  if (o < nb) {
+    const int64_t t = T0 + o;
+    int sig[4], F[4];
+    double x[4][3];
+    elem_inputs(nC, XA, nE, t, tet, t2f, sigma, sig, F, x);
+    R su[10], r[4];
+    elem_block<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, su, r);
+#pragma unroll
+    for (int j = 0; j < 10; ++j) lS[j][o] = su[j];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lr[k][o] = r[k];
+      lF[k][o] = F[k];
+      if (sig[k] > 0) {
+        fmin = min(fmin, F[k]);
+        fmax = max(fmax, F[k]);
+      }
     }
-  } else {
-    for (int i = threadIdx.x; i < 6 * nb; i += FT) st_nt(val + 6 * f0 + i, lval[i]);
+  }
+  // the tile's owned face range (faces are numbered in owner order)
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    fmin = min(fmin, __shfl_xor(fmin, d, 64));
+    fmax = max(fmax, __shfl_xor(fmax, d, 64));
+  }
+  if ((o & 63) == 0) {
+    atomicMin(&lrange[0], fmin);
+    atomicMax(&lrange[1], fmax);
+  }
+  __syncthreads();
+  const int64_t F0 = lrange[0] < 0 ? 0 : lrange[0];  // (a negative id: invalid input)
+  int64_t F1 = (int64_t)lrange[1] + 1;
+  if (F1 > nF) F1 = nF;                    // invalid input: stay in range
+  if (F1 - F0 > 4 * CT) F1 = F0 + 4 * CT;  // (a tile owns at most 4 CT faces)
+  // rows in chunks of CT faces: built into LDS, then stored as contiguous ranges
+  for (int64_t base = F0; base < F1; base += CT) {
+    const int nloc = F1 - base < CT ? (int)(F1 - base) : CT;
+    const int64_t f = base + o;
+    if (o < nloc) {
+      const int q0 = face2tet[f], q1 = face2tet[nF + f];
+      const int oo = (q0 >> 2) - (int)T0, k = q0 & 3;
+      int cf[6], rk[6];
+      double cv[6];
+      double dg = 0.0, rh = 0.0;
+      if (q0 >= 0 && oo >= 0 && oo < nb) {
+        dg = (double)lS[uidx(k, k)][oo];
+        rh = face_bD(nF, nC, X, faces, P, f, q1) - (double)lr[k][oo];
+        int n = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          if (l == k) continue;
+          cf[n] = lF[l][oo];
+          cv[n] = (double)lS[uidx(k, l)][oo];
+          ++n;
+        }
+      } else {  // not owned here: invalid input (the row is written as zeros)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          cf[i] = INT_MAX;
+          cv[i] = 0.0;
+        }
+      }
+      if (q1 >= 0 && (uint64_t)q1 < (uint64_t)(4 * nE)) {
+        const int o2 = (q1 >> 2) - (int)T0, k2 = q1 & 3;
+        if (o2 >= 0 && o2 < nb) {  // second tet in the tile
+          dg += (double)lS[uidx(k2, k2)][o2];
+          rh -= (double)lr[k2][o2];
+          int n = 3;
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            if (l == k2) continue;
+            cf[n] = lF[l][o2];
+            cv[n] = (double)lS[uidx(k2, l)][o2];
+            ++n;
+          }
+        } else {  // its record
+          const SlotRec<R> b = recs[q1];
+          dg += (double)b.d;
+          rh -= (double)b.r;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            cf[3 + i] = b.c[i];
+            cv[3 + i] = (double)b.o[i];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 3; i < 6; ++i) {
+          cf[i] = INT_MAX;  // sorts last; written as column f with value 0
+          cv[i] = 0.0;
+        }
+      }
+      col_ranks(cf, rk);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        if (PATTERN) lcol[6 * o + rk[i]] = cf[i] == INT_MAX ? (int32_t)f : cf[i];
+        lval[6 * o + rk[i]] = cv[i];
+      }
+      st_nt(diag + f, dg);
+      st_nt(rhs + f, rh);
+      if (PATTERN) {
+        st_nt(rowptr + f, (int32_t)(6 * f));
+        if (f == nF - 1) rowptr[nF] = (int32_t)(6 * nF);
+      }
+    }
+    __syncthreads();
+    for (int i = o; i < 6 * nloc; i += CT) {
+      st_nt(val + 6 * base + i, lval[i]);
+      if (PATTERN) st_nt(col + 6 * base + i, lcol[i]);
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- recovery / residual (FP64)
-// U(T) = A^-1 (Bsrc + C' lambda) with Bsrc = load vector (gsrc == null) or gsrc[4][nE];
-// res[F] -= (C U)_k for every local face when res != null (res preset to b_D or 0).
-__global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __restrict__ X, int64_t nE,
+// hi + lo = a + b exactly (Knuth's two-sum)
+__device__ __forceinline__ void two_sum(double a, double b, double& hi, double& lo) {
+  hi = a + b;
+  const double bb = hi - a;
+  lo = (a - (hi - bb)) + (b - bb);
+}
+
+// sum_i B_i + sum_k d_k f_k rounded once from a double-double accumulation (each product
+// enters with its exact rounding error from an fma)
+__device__ __forceinline__ double dd_mean_sum(const double (&B)[4], const double (&d)[4], const double (&f)[4]) {
+  double hi = B[0], lo = 0.0, h, l;
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    two_sum(hi, B[i], h, l);
+    hi = h;
+    lo += l;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double p = d[k] * f[k];
+    two_sum(hi, p, h, l);
+    hi = h;
+    lo += l + fma(d[k], f[k], -p);
+  }
+  return hi + lo;
+}
+
+// U(T) = A^-1 (Bsrc + C' lambda) with Bsrc = load vector (gsrc == null) or gsrc[4][nE].
+// cu != null: cu[4t+k] = (C U)_k, the term local face k of tet t takes off the residual of
+// its face (a Neumann row lambda_F = g takes lambda_F - g); k_face_residual then forms each
+// face's residual from its owner's and neighbour's slots in that order, so the sums do not
+// depend on scheduling.  A vertex or face id out of range sets DEV_BADNODE (nothing of that
+// tet is read or written), a zero volume DEV_DEGEN.
+__global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __restrict__ X, int64_t nE, int64_t nF,
                                                 const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                                 const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
                                                 DevParams P, const double* __restrict__ lambda,
                                                 const double* __restrict__ gsrc, double* __restrict__ U,
-                                                double* __restrict__ res, int* __restrict__ flags) {
+                                                double* __restrict__ cu, int* __restrict__ flags) {
   int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
   if (t >= nE) return;
   int v[4], sig[4], F[4];
+  bool inr = true;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     v[i] = tet[i * nE + t];
     sig[i] = sigma[i * nE + t];
     F[i] = t2f[i * nE + t];
+    inr = inr && (uint32_t)v[i] < (uint64_t)nC && (uint32_t)F[i] < (uint64_t)nF;
+  }
+  if (!inr) {
+    if (flags) atomicOr(flags, DEV_BADNODE);
+    return;
   }
   double x[4][3];
   gather_x(nC, X, v, x);
@@ -572,14 +739,19 @@ __global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __rest
       if (neu[k]) gN[k] = neumann_flux(E, x, k, kap, P);
     }
   }
-  if (lambda) {
+  double fac[4];  // mu_k = d_k fac_k: the multiplier, g on a Neumann face
 #pragma unroll
-    for (int k = 0; k < 4; ++k) mu[k] = E.d[k] * (neu[k] ? gN[k] : lambda[F[k]]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) mu[k] = neu[k] ? E.d[k] * gN[k] : 0.0;
+  for (int k = 0; k < 4; ++k) {
+    fac[k] = neu[k] ? gN[k] : (lambda ? lambda[F[k]] : 0.0);
+    mu[k] = E.d[k] * fac[k];
   }
-  const double s = ((B[0] + B[1]) + (B[2] + B[3]) + ((mu[0] + mu[1]) + (mu[2] + mu[3]))) * E.icv;
+  // The mean mode s = (sum B + sum mu) / (c vol): the four mu_k = sigma_k |F_k| lambda_k nearly
+  // cancel (their sum is the flux balance of the tet, O(h) smaller than the terms), so the sum
+  // is carried in double-double (error-free products and sums); otherwise its rounding,
+  // amplified by 1 / (c vol), sets the floor of the true residual (about 1e-12 relative at
+  // h = 1/32 with lognormal kappa).
+  const double dk[4] = {E.d[0], E.d[1], E.d[2], E.d[3]};
+  const double s = dd_mean_sum(B, dk, fac) * E.icv;
   double y[4], u[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) y[i] = B[i] - mu[opp(i)] / 3.0;  // face opposite vertex i is opp(i)
@@ -589,36 +761,66 @@ __global__ __launch_bounds__(FT) void k_recover(int64_t nC, const double* __rest
 #pragma unroll
     for (int i = 0; i < 4; ++i) U[i * nE + t] = u[i];
   }
-  if (res) {
+  if (cu) {
     const double su = (u[0] + u[1]) + (u[2] + u[3]);
+    double c4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)  // a Neumann row is lambda_F = g
-      atomicAdd(&res[F[k]], neu[k] ? gN[k] - (lambda ? lambda[F[k]] : 0.0) : -E.d[k] * (su - u[opp(k)]) / 3.0);
+      c4[k] = neu[k] ? (lambda ? lambda[F[k]] : 0.0) - gN[k] : E.d[k] * (su - u[opp(k)]) / 3.0;
+    reinterpret_cast<double4*>(cu)[t] = make_double4(c4[0], c4[1], c4[2], c4[3]);
   }
+}
+
+// res[F] = b_D[F] - cu[owner slot] - cu[neighbour slot] (b_D null: 0), the two terms in that
+// order; a slot out of range sets DEV_BADNODE and leaves res[F] unwritten.
+__global__ __launch_bounds__(FT) void k_face_residual(int64_t nF, int64_t nE, const int32_t* __restrict__ face2tet,
+                                                      const double* __restrict__ bD, const double* __restrict__ cu,
+                                                      double* __restrict__ res, int* __restrict__ flags) {
+  const int64_t f = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (f >= nF) return;
+  const int q0 = face2tet[f], q1 = face2tet[nF + f];
+  if ((uint32_t)q0 >= (uint64_t)(4 * nE) || (q1 != -1 && (uint32_t)q1 >= (uint64_t)(4 * nE))) {
+    if (flags) atomicOr(flags, DEV_BADNODE);
+    return;
+  }
+  double r = (bD ? bD[f] : 0.0) - cu[q0];
+  if (q1 >= 0) r -= cu[q1];
+  res[f] = r;
 }
 
 // ---------------------------------------------------------------- adjoint VJP (FP64)
 // G_i = dPhi_T/dx_i for Phi_T = P'A U - lambda'C P - P'B - Q'C U + sum_bnd Q_F b_D,F;
 // dJ/dX_v -= G_i, dJ/dlog kappa_T = -kappa vol gP.gU.
-__global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict__ X, int64_t nE,
+// A vertex or face id out of range sets DEV_BADNODE, a zero volume DEV_DEGEN (that tet then
+// contributes nothing).
+__global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict__ X, int64_t nE, int64_t nF,
                                             const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                             const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
                                             const double* __restrict__ kappa, DevParams P,
                                             const double* __restrict__ Uu, const double* __restrict__ Pp,
                                             const double* __restrict__ lambda, const double* __restrict__ Q,
-                                            double* __restrict__ dlogk, double* __restrict__ dX) {
+                                            double* __restrict__ dlogk, double* __restrict__ dX,
+                                            int* __restrict__ flags) {
   int64_t t = (int64_t)blockIdx.x * FT + threadIdx.x;
   if (t >= nE) return;
-  int v[4], sig[4];
+  int v[4], sig[4], Fi[4];
   double U[4], Pv[4], lam[4], Qf[4];
-  bool bnd[4];
+  bool bnd[4], inr = true;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     v[i] = tet[i * nE + t];
+    Fi[i] = t2f[i * nE + t];
+    inr = inr && (uint32_t)v[i] < (uint64_t)nC && (uint32_t)Fi[i] < (uint64_t)nF;
+  }
+  if (!inr) {
+    atomicOr(flags, DEV_BADNODE);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
     sig[i] = sigma[i * nE + t];
-    int Fi = t2f[i * nE + t];
-    lam[i] = lambda[Fi];
-    Qf[i] = Q[Fi];
+    lam[i] = lambda[Fi[i]];
+    Qf[i] = Q[Fi[i]];
     bnd[i] = nbr[i * nE + t] < 0;
     U[i] = Uu[i * nE + t];
     Pv[i] = Pp[i * nE + t];
@@ -627,7 +829,10 @@ __global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict
   gather_x(nC, X, v, x);
   const double kap = kappa ? kappa[t] : P.kc;
   Elem<double> E;
-  if (!E.init(x, kap, P.c, sig)) return;
+  if (!E.init(x, kap, P.c, sig)) {
+    atomicOr(flags, DEV_DEGEN);
+    return;
+  }
   const double vol = E.vol, c = P.c;
   double gU[3] = {0, 0, 0}, gP[3] = {0, 0, 0};
 #pragma unroll
@@ -737,28 +942,35 @@ __global__ __launch_bounds__(FT) void k_vjp(int64_t nC, const double* __restrict
 }
 
 // instantiations used by the solver / grad drivers (solve.hip)
-int launch_recover(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f,
-                   const int8_t* sigma, const double* kappa, const DevParams& P, const double* lambda,
-                   const double* gsrc, double* U, double* res, int* flags, hipStream_t s) {
+// U = A^-1 (Bsrc + C' lambda) per tet and, with res, res = b_D - C U per face (b_D null: 0);
+// cu is a 4 nE scratch array of per-slot terms (required with res)
+int launch_recover(int64_t nC, const double* X, int64_t nE, int64_t nF, const int32_t* tet, const int32_t* t2f,
+                   const int8_t* sigma, const int32_t* face2tet, const double* kappa, const DevParams& P,
+                   const double* lambda, const double* gsrc, const double* bD, double* U, double* cu, double* res,
+                   int* flags, hipStream_t s) {
   const double bytes = (36.0 + (kappa ? 8.0 : 0.0) + (gsrc ? 32.0 : 0.0) + (U ? 32.0 : 0.0)) * nE + 24.0 * nC +
-                       (lambda ? 8.0 : 0.0) * nE + (res ? 16.0 : 0.0) * nE;
-  PH_LAUNCH_B("recover", bytes, k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, tet, t2f, sigma, kappa, P, lambda,
-              gsrc, U, res, flags);
+                       (lambda ? 8.0 : 0.0) * nE + (res ? 32.0 : 0.0) * nE;
+  PH_LAUNCH_B("recover", bytes, k_recover, grid_for(nE, FT), FT, 0, s, nC, X, nE, nF, tet, t2f, sigma, kappa, P, lambda,
+              gsrc, U, res ? cu : nullptr, flags);
+  if (res)
+    PH_LAUNCH_B("face_residual", (8.0 + (bD ? 8.0 : 0.0) + 16.0 + 8.0) * nF, k_face_residual, grid_for(nF, FT), FT, 0,
+                s, nF, nE, face2tet, bD, (const double*)cu, res, flags);
   return PHFEM_OK;
 }
 
 int launch_face_init(int64_t nF, int64_t nC, const double* X, const int32_t* faces, const int32_t* face2tet,
-                     const DevParams& P, uint32_t* cnt, double* diag, double* rhs, hipStream_t s) {
+                     const DevParams& P, uint32_t* cnt, double* diag, double* rhs, int* flags, hipStream_t s) {
   PH_LAUNCH_B("face_init", (8.0 + (cnt ? 4.0 : 0.0) + (diag ? 8.0 : 0.0) + (rhs ? 8.0 : 0.0)) * nF, k_face_init,
-              grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs);
+              grid_for(nF + 1, FT), FT, 0, s, nF, nC, X, faces, face2tet, P, cnt, diag, rhs, flags);
   return PHFEM_OK;
 }
 
-int launch_vjp(int64_t nC, const double* X, int64_t nE, const int32_t* tet, const int32_t* t2f, const int8_t* sigma,
-               const int32_t* nbr, const double* kappa, const DevParams& P, const double* U, const double* Pp,
-               const double* lambda, const double* Q, double* dlogk, double* dX, hipStream_t s) {
+int launch_vjp(int64_t nC, const double* X, int64_t nE, int64_t nF, const int32_t* tet, const int32_t* t2f,
+               const int8_t* sigma, const int32_t* nbr, const double* kappa, const DevParams& P, const double* U,
+               const double* Pp, const double* lambda, const double* Q, double* dlogk, double* dX, int* flags,
+               hipStream_t s) {
   PH_LAUNCH_B("vjp", (124.0 + (kappa ? 8.0 : 0.0)) * nE + 16.0 * nE + 72.0 * nC, k_vjp, grid_for(nE, FT), FT, 0, s, nC,
-              X, nE, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q, dlogk, dX);
+              X, nE, nF, tet, t2f, sigma, nbr, kappa, P, U, Pp, lambda, Q, dlogk, dX, flags);
   return PHFEM_OK;
 }
 
@@ -788,7 +1000,7 @@ extern "C" size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t
                                                  int32_t nk) {
   (void)nF;
   if (nk < 1) return 0;
-  Arena a;  // the AoS coordinates and one field's slot records (the fields run in turn)
+  Arena a;  // the AoS coordinates and one field's cross-tile records (the fields run in turn)
   a.take<double4>(nC);
   if (precision == PHFEM_MIXED)
     a.take<SlotRec<float>>(4 * nE);
@@ -803,19 +1015,22 @@ extern "C" size_t phfem_condense_workspace(int64_t nC, int64_t nE, int64_t nF, i
 
 extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
                                     const int32_t* faces, const int32_t* tet2face, const int8_t* sigma,
-                                    const int32_t* face2tet, int32_t nk, const double* kappa, const phfem_params* p,
-                                    void* work, size_t work_bytes, int32_t* rowptr, int32_t* col, double* val,
-                                    double* diag, double* rhs, phfem_stream_t stream_) {
+                                    const int32_t* nbr, const int32_t* face2tet, int32_t nk, const double* kappa,
+                                    const phfem_params* p, void* work, size_t work_bytes, int32_t* rowptr,
+                                    int32_t* col, double* val, double* diag, double* rhs, phfem_stream_t stream_) {
   clear_error();
   hipStream_t s = (hipStream_t)stream_;
   int rc = check_params(p);
   if (rc) return rc;
-  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !face2tet || !val ||
+  if (nC <= 0 || nE <= 0 || nF <= 0 || !coord || !tetra || !faces || !tet2face || !sigma || !nbr || !face2tet || !val ||
       !diag || !rhs)
     return err(PHFEM_EINVAL, "bad condense arguments");
   if (nk < 1 || (nk > 1 && !kappa)) return err(PHFEM_EINVAL, "nk >= 1 coefficient fields (kappa required for nk > 1)");
   if ((rowptr == nullptr) != (col == nullptr)) return err(PHFEM_EINVAL, "rowptr and col: both or neither");
-  if (6 * nF >= (int64_t(1) << 31)) return err(PHFEM_EINVAL, "face system exceeds int32 indexing");
+  if (6 * nF >= (int64_t(1) << 31) || 4 * nE >= (int64_t(1) << 31))
+    return err(PHFEM_EINVAL, "face system exceeds int32 indexing");
+  if ((reinterpret_cast<uintptr_t>(val) & 15) || (col && (reinterpret_cast<uintptr_t>(col) & 7)))
+    return err(PHFEM_EINVAL, "val must be 16-byte and col 8-byte aligned");
   if (!work || work_bytes < phfem_condense_batch_workspace(nC, nE, nF, p->precision, nk))
     return err(PHFEM_EWORKSPACE, "condense workspace too small");
   Arena a(work, work_bytes);
@@ -823,13 +1038,14 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
   double4* XA = a.take<double4>(nC);
   void* recs = mixed ? (void*)a.take<SlotRec<float>>(4 * nE) : (void*)a.take<SlotRec<double>>(4 * nE);
   DevParams P = to_dev(*p);
-  // algorithmic bytes per field: tets, faces, sigma (+ kappa) once per tet, four records per
-  // tet written once and read once, face2tet once, every off-diagonal value, diagonal and rhs
-  // written once, the pattern (col + row pointer) once when written; coordinates once per call
-  const double rb = 4.0 * (double)(mixed ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>));
-  const double eb = (36.0 + (kappa ? 8.0 : 0.0)) * nE + 24.0 * nC + rb * nE;
-  const double fbv = rb * nE + 8.0 * nF + (8.0 * 6.0 + 16.0) * nF, fbp = 4.0 * 7.0 * nF;
-  const unsigned gf = grid_for(nF, FT);
+  // algorithmic bytes per field.  cross: tets, tet2face, sigma, nbr (+ kappa) once; tile:
+  // tets, tet2face, sigma (+ kappa) once, face2tet once, off-diagonal values, diagonal and rhs
+  // written once, the pattern (col + row pointer) once when written; coordinates once per
+  // pass (the records crossing tiles are left out: an intermediate of this design)
+  const double kb = kappa ? 8.0 : 0.0;
+  const double cb = (52.0 + kb) * nE + 32.0 * nC;
+  const double tbv = (36.0 + kb) * nE + 32.0 * nC + 8.0 * nF + (8.0 * 6.0 + 16.0) * nF, tbp = 4.0 * 7.0 * nF;
+  const unsigned gt = grid_for(nE, CT), gx = grid_for(nE, CX);
   PH_LAUNCH_B("coords_aos", 56.0 * nC, k_coords_aos, grid_for(nC, FT), FT, 0, s, nC, coord, XA);
   for (int j = 0; j < nk; ++j) {
     // field j; the pattern (when asked for) with the first field only
@@ -837,17 +1053,27 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
     int32_t* rp = j == 0 ? rowptr : nullptr;
     int32_t* cl = j == 0 ? col : nullptr;
     double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
-    const double fb = fbv + (cl ? fbp : 0.0);
+    const double tb = tbv + (cl ? tbp : 0.0);
     if (mixed) {
-      PH_LAUNCH_B("elem_rec_f32", eb, k_elem_rec<float>, grid_for(nE, elem_threads<float>()), elem_threads<float>(), 0,
-                  s, nC, XA, nE, tetra, tet2face, sigma, kj, P, nF, (SlotRec<float>*)recs);
-      PH_LAUNCH_B("face_rows_f32", fb, k_face_rows<float>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
-                  (const SlotRec<float>*)recs, rp, cl, vj, dj, rj);
+      auto* rc32 = (SlotRec<float>*)recs;
+      PH_LAUNCH_B("cond_cross_f32", cb, k_cond_cross<float>, gx, CT, 0, s, nC, XA, nE, tetra, tet2face, sigma, nbr, kj,
+                  P, nF, rc32);
+      if (cl)
+        PH_LAUNCH_B("cond_tile_f32", tb, (k_cond_tile<float, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra, tet2face,
+                    sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl, vj, dj, rj);
+      else
+        PH_LAUNCH_B("cond_tile_f32", tb, (k_cond_tile<float, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl, vj, dj, rj);
     } else {
-      PH_LAUNCH_B("elem_rec_f64", eb, k_elem_rec<double>, grid_for(nE, elem_threads<double>()), elem_threads<double>(),
-                  0, s, nC, XA, nE, tetra, tet2face, sigma, kj, P, nF, (SlotRec<double>*)recs);
-      PH_LAUNCH_B("face_rows_f64", fb, k_face_rows<double>, gf, FT, 0, s, nF, nC, coord, faces, face2tet, P,
-                  (const SlotRec<double>*)recs, rp, cl, vj, dj, rj);
+      auto* rc64 = (SlotRec<double>*)recs;
+      PH_LAUNCH_B("cond_cross_f64", cb, k_cond_cross<double>, gx, CT, 0, s, nC, XA, nE, tetra, tet2face, sigma, nbr,
+                  kj, P, nF, rc64);
+      if (cl)
+        PH_LAUNCH_B("cond_tile_f64", tb, (k_cond_tile<double, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp, cl, vj, dj, rj);
+      else
+        PH_LAUNCH_B("cond_tile_f64", tb, (k_cond_tile<double, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp, cl, vj, dj, rj);
     }
   }
   return PHFEM_OK;
@@ -858,11 +1084,10 @@ extern "C" int phfem_condense(int64_t nC, const double* coord, int64_t nE, const
                               const int32_t* face2tet, const double* kappa, const phfem_params* p, void* work,
                               size_t work_bytes, int32_t* rowptr, int32_t* col, double* val, double* diag,
                               double* rhs, phfem_stream_t stream) {
-  (void)nbr;
   if (!rowptr || !col) {
     clear_error();
     return err(PHFEM_EINVAL, "bad condense arguments");
   }
-  return phfem_condense_batch(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, 1, kappa, p, work,
+  return phfem_condense_batch(nC, coord, nE, tetra, nF, faces, tet2face, sigma, nbr, face2tet, 1, kappa, p, work,
                               work_bytes, rowptr, col, val, diag, rhs, stream);
 }

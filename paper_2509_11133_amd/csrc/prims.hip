@@ -16,7 +16,7 @@ void set_error(const std::string& msg) { g_error = msg; }
 void clear_error() { g_error.clear(); }
 
 int dev_flags_to_status(int f) {
-  if (f & DEV_BADNODE) return err(PHFEM_EINVAL, "node index out of range or repeated node in a tet");
+  if (f & DEV_BADNODE) return err(PHFEM_EINVAL, "node, face or slot index out of range, or repeated node in a tet");
   if (f & DEV_ORIENT) return err(PHFEM_EORIENT, "a face occurs twice with the same orientation or in more than two tets");
   if (f & DEV_DEGEN) return err(PHFEM_EDEGEN, "zero-volume tet");
   if (f & DEV_NOFACE) return err(PHFEM_EINVAL, "boundary face is not a face of the mesh");
@@ -320,7 +320,7 @@ int radix_sort(uint64_t* keysA, int32_t* valsA, uint64_t* keysB, int32_t* valsB,
 extern "C" {
 
 const char* phfem_last_error(void) { return ph::g_error.c_str(); }
-int phfem_abi_version(void) { return 1; }
+int phfem_abi_version(void) { return 2; }
 
 void phfem_profile_enable(int32_t on) { ph::g_prof = on != 0; }
 

@@ -14,8 +14,6 @@ namespace ph {
 
 constexpr int RT = 256;
 
-__device__ int g_face_flag;
-
 // one tet: its new coordinates (written directly) and its children (into the LDS rows)
 __device__ __forceinline__ void refine_tet(int64_t nC, const double* __restrict__ X, int64_t nE,
                                            const int32_t* __restrict__ tet, const int32_t* __restrict__ t2e,
@@ -154,11 +152,19 @@ int launch_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* te
 
 using namespace ph;
 
+extern "C" size_t phfem_refine_workspace(int64_t nDb, int64_t nNb) {
+  if (nDb < 0 || nNb < 0 || nDb + nNb == 0) return 0;
+  Arena a;  // the face lookups' error word
+  a.take<int>(1);
+  return a.size();
+}
+
 extern "C" int phfem_refine(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nEd,
                             const int32_t* tet2edge, const int32_t* edge_first_tet, const int32_t* tet_edge_prefix,
                             const int32_t* n2e_rowptr, const int32_t* n2e_col, const int32_t* n2e_edge, int64_t nDb,
-                            const int32_t* db, int64_t nNb, const int32_t* nb, double* coord_out, int32_t* tetra_out,
-                            int32_t* db_out, int32_t* nb_out, phfem_stream_t stream_) {
+                            const int32_t* db, int64_t nNb, const int32_t* nb, void* work, size_t work_bytes,
+                            double* coord_out, int32_t* tetra_out, int32_t* db_out, int32_t* nb_out,
+                            phfem_stream_t stream_) {
   clear_error();
   hipStream_t s = (hipStream_t)stream_;
   if (nC <= 0 || nE <= 0 || nEd <= 0 || nDb < 0 || nNb < 0) return err(PHFEM_EINVAL, "bad sizes");
@@ -169,16 +175,16 @@ extern "C" int phfem_refine(int64_t nC, const double* coord, int64_t nE, const i
   const bool faces = nDb + nNb > 0;
   if (faces && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "boundary faces need Nodes2Edge");
   if ((nDb > 0 && (!db || !db_out)) || (nNb > 0 && (!nb || !nb_out))) return err(PHFEM_EINVAL, "null face list");
+  if (faces && (!work || work_bytes < phfem_refine_workspace(nDb, nNb)))
+    return err(PHFEM_EWORKSPACE, "refine workspace too small");
   int rc = launch_refine(nC, coord, nE, tetra, tet2edge, edge_first_tet, tet_edge_prefix, nCo, coord_out, tetra_out, s,
                          nullptr);
   if (rc) return rc;
   if (!faces) return PHFEM_OK;
-  // error flag of the face lookups: a 4-byte device global (calls on one device that
-  // overlap in time share it)
-  int* dflag = nullptr;
-  PH_HIP(hipGetSymbolAddress((void**)&dflag, HIP_SYMBOL(g_face_flag)));
-  const int zero = 0;
-  PH_HIP(hipMemcpyAsync(dflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  // error flag of the face lookups, in the caller's workspace
+  Arena a(work, work_bytes);
+  int* dflag = a.take<int>(1);
+  PH_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
   if (nDb > 0)
     PH_LAUNCH("refine_faces", k_refine_faces, grid_for(nDb, RT), RT, 0, s, nDb, db, nC, n2e_rowptr, n2e_col,
               n2e_edge, edge_first_tet, db_out, dflag);

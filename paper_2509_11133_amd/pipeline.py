@@ -59,28 +59,31 @@ def refine(coord, tetra, conn, db=None, nb=None):
     nNb = 0 if nb is None else nb.shape[1]
     dbo = torch.empty((3, 4 * nDb), dtype=I32, device=dev) if nDb else None
     nbo = torch.empty((3, 4 * nNb), dtype=I32, device=dev) if nNb else None
+    wb = B.lib().phfem_refine_workspace(nDb, nNb)
+    work = B.workspace(wb, dev) if wb else None
     B.phfem_refine(nC, coord, nE, tetra, nEd, conn["tet2edge"], conn["edge_first_tet"], conn["tet_edge_prefix"],
                    conn.get("n2e_rowptr"), conn.get("n2e_col"), conn.get("n2e_edge"), nDb, db if nDb else None, nNb,
-                   nb if nNb else None, Xo, To, dbo, nbo)
+                   nb if nNb else None, work, Xo, To, dbo, nbo)
     return Xo, To, dbo, nbo
 
 
-def neumann_flags(conn, tris):
-    """Device uint8 flags [nF] (1 = Neumann face) for the boundary triangles tris [3][n]
-    (node triples in any order, e.g. a refined Nb list).  Matched on the host against the
-    boundary faces only (a vanishing fraction of the faces); every triangle must be one."""
+def neumann_flags(conn, tris, face_of=False):
+    """Device uint8 flags [nF] (1 = Neumann face) for the boundary triangles tris [3][n] (node
+    triples in any order, e.g. a refined Nb list), matched to the face numbering by
+    phfem_face_lookup; every triangle must be a boundary face.  face_of=True also returns each
+    triangle's face id."""
     dev = conn["faces"].device
-    f2t = conn["face2tet"][1]
-    bnd = torch.nonzero(f2t < 0).flatten()
-    key = {tuple(sorted(t)): int(f) for f, t in zip(bnd.tolist(), conn["faces"][:, bnd].t().tolist())}
-    tris = tris.cpu().numpy() if hasattr(tris, "cpu") else np.asarray(tris)
-    nm = np.zeros(conn["nF"], np.uint8)
-    for j in range(tris.shape[1]):
-        k = tuple(sorted(int(v) for v in tris[:, j]))
-        if k not in key:
-            raise B.PhfemError(B.EINVAL, f"Neumann triangle {k} is not a boundary face")
-        nm[key[k]] = 1
-    return torch.tensor(nm, device=dev)
+    tris = torch.as_tensor(tris, dtype=I32).to(dev).contiguous()
+    n = tris.shape[1]
+    nF = conn["nF"]
+    flags = torch.empty(nF, dtype=torch.uint8, device=dev)
+    fo = torch.empty(max(n, 1), dtype=I32, device=dev)
+    wb = B.lib().phfem_face_lookup_workspace(n)
+    work = B.workspace(wb, dev) if wb else None
+    nC = conn["nC"]
+    B.phfem_face_lookup(nC, nF, conn["faces"].contiguous(), conn["face2tet"].contiguous(), n, tris if n else None,
+                        work, flags, fo if n else None)
+    return (flags, fo[:n]) if face_of else flags
 
 
 def refine_connected(coord, tetra, conn, status=None):
@@ -204,7 +207,7 @@ def condense_batch(coord, tetra, conn, kappas, prm, pattern=None):
     val = torch.empty((nk, nnz), dtype=F64, device=dev)
     diag = torch.empty((nk, nF), dtype=F64, device=dev)
     rhs = torch.empty((nk, nF), dtype=F64, device=dev)
-    B.phfem_condense_batch(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"],
+    B.phfem_condense_batch(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"], conn["nbr"],
                            conn["face2tet"], nk, kappas, prm, work, rp, cl, val, diag, rhs)
     return [dict(rowptr=rowptr, col=col, val=val[j], diag=diag[j], rhs=rhs[j], nnz=nnz) for j in range(nk)]
 
@@ -242,18 +245,24 @@ def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, 
 
 
 def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.9,
-         max_iter=200000, want_coord=True):
-    """Adjoint gradient (a10): (dJ/dlog kappa [nE], dJ/dX [3, nC], stats)."""
+         max_iter=200000, want_coord=True, allow_noconv=False):
+    """Adjoint gradient (a10): (dJ/dlog kappa [nE], dJ/dX [3, nC], stats).  With allow_noconv an
+    adjoint solve that stopped above tol (ENOCONV: the last iterate) still returns its
+    gradient; stats["converged"] says which."""
     dev = coord.device
     nC, nE, nF = coord.shape[1], tetra.shape[1], conn["nF"]
     work = B.workspace(B.lib().phfem_grad_workspace(nE, nF, mode), dev)
     dlogk = torch.empty(nE, dtype=F64, device=dev)
     dX = torch.empty((3, nC), dtype=F64, device=dev) if want_coord else None
     st = SolveStats()
-    B.phfem_grad(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"], conn["face2tet"],
-                 conn["nbr"], kappa, prm, sysm["rowptr"], sysm["col"], sysm["val"], sysm["diag"], U, lam,
-                 dJdU.contiguous(), mode, tol, inner_tol, max_iter, work, dlogk, dX, st)
-    return dlogk, dX, st.as_dict()
+    rc = B.phfem_grad(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"], conn["face2tet"],
+                      conn["nbr"], kappa, prm, sysm["rowptr"], sysm["col"], sysm["val"], sysm["diag"], U, lam,
+                      dJdU.contiguous(), mode, tol, inner_tol, max_iter, work, dlogk, dX, st, check=False)
+    stats = st.as_dict()
+    stats["converged"] = rc == OK
+    if rc != OK and not (rc == ENOCONV and allow_noconv):
+        raise PhfemError(rc, B.lib().phfem_last_error().decode())
+    return dlogk, dX, stats
 
 
 def errors(coord, tetra, conn, kappa, prm, U, lam, u_kind, u_par, h, nq=8):

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(B.EXPORTS)
-    assert L.phfem_abi_version() == 1
+    assert L.phfem_abi_version() == 2
 
 
 def test_workspace_queries():
@@ -43,6 +43,8 @@ def test_workspace_queries():
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 2) > L.phfem_refine_connected_workspace(72, 114)
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 0) == 0
     assert L.phfem_errors_workspace(0) == 0 and L.phfem_errors_workspace(1000) >= 3 * 8 * 4
+    assert L.phfem_refine_workspace(0, 0) == 0 and L.phfem_refine_workspace(3, 0) > 0
+    assert L.phfem_face_lookup_workspace(0) == 0 and L.phfem_face_lookup_workspace(100) >= 4 * (256 + 100)
     assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 1) == L.phfem_condense_workspace(20, 50, 100, 1)
     assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 3) == L.phfem_condense_workspace(20, 50, 100, 1)
     assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 0) == 0
@@ -71,7 +73,15 @@ def test_validation_errors_on_host():
     rc = L.phfem_solve(8, 16, 6, 16, 18, *([16] * 4), None, C.addressof(p), *([16] * 5), 5, 1e-10, 1e-4, 10, 16, 0,
                        16, 16, C.addressof(st), None)
     assert rc == B.EINVAL  # bad mode
-    rc = L.phfem_refine(8, 16, 6, 16, 0, *([16] * 3), None, None, None, 0, None, 0, None, 16, 16, None, None, None)
+    rc = L.phfem_refine(8, 16, 6, 16, 0, *([16] * 3), None, None, None, 0, None, 0, None, None, 0, 16, 16, None, None,
+                        None)
+    assert rc == B.EINVAL
+    # boundary faces need the refine workspace (its error word); triangles the lookup's
+    rc = L.phfem_refine(8, 16, 6, 16, 19, *([16] * 3), 16, 16, 16, 2, 16, 0, None, None, 0, 16, 16, 16, None, None)
+    assert rc == B.EWORKSPACE
+    rc = L.phfem_face_lookup(8, 18, 16, 16, 3, 16, 16, 0, 16, None, None)
+    assert rc == B.EWORKSPACE
+    rc = L.phfem_face_lookup(8, 18, 16, 16, -1, 16, 16, 1 << 20, 16, None, None)
     assert rc == B.EINVAL
     par, out = (C.c_double * 4)(), (C.c_double * 3)()
     for nq, h in ((0, 0.5), (13, 0.5), (4, 0.0)):  # rule size / mesh size checked before any GPU work
@@ -93,14 +103,14 @@ def test_size_limits_on_host():
     rc = L.phfem_refine_connected(4 * nE, 16, nE, 16, 2 * nE, 2 * nE, *([16] * 5), 16, 1 << 40, *([16] * 11),
                                   counts.ctypes.data, None, None)
     assert rc == B.EINVAL and b"index ranges" in L.phfem_last_error()
-    rc = L.phfem_refine(1 << 30, 16, nE * 16, 16, nE, *([16] * 3), None, None, None, 0, None, 0, None, 16, 16, None,
-                        None, None)
+    rc = L.phfem_refine(1 << 30, 16, nE * 16, 16, nE, *([16] * 3), None, None, None, 0, None, 0, None, None, 0, 16, 16,
+                        None, None, None)
     assert rc == B.EINVAL and b"int32" in L.phfem_last_error()
     p = B.params(c=1.0)
     nF = (1 << 31) // 6 + 1  # 6 nF >= 2^31
     rc = L.phfem_condense(8, 16, 6, 16, nF, *([16] * 6), C.addressof(p), 16, 1 << 40, *([16] * 5), None)
     assert rc == B.EINVAL and b"int32" in L.phfem_last_error()
-    rc = L.phfem_condense_batch(8, 16, 6, 16, 18, *([16] * 4), 0, 16, C.addressof(p), 16, 1 << 40, None, None, 16,
+    rc = L.phfem_condense_batch(8, 16, 6, 16, 18, *([16] * 5), 0, 16, C.addressof(p), 16, 1 << 40, None, None, 16,
                                 16, 16, None)
     assert rc == B.EINVAL  # nk < 1
     rc = L.phfem_refine_connected_levels(8, 16, 6, 16, 19, 18, *([16] * 5), 17, 16, 1 << 40, *([16] * 11),

@@ -106,7 +106,7 @@ def test_batch_input_check():
     rhs = torch.empty((2, nF), dtype=torch.float64, device=DEV)
     col = torch.empty(6 * nF, dtype=torch.int32, device=DEV)
     ks = torch.ones((2, nE), dtype=torch.float64, device=DEV)
-    args = (8, Xd, nE, Td, nF, gc["faces"], gc["tet2face"], gc["sigma"], gc["face2tet"])
+    args = (8, Xd, nE, Td, nF, gc["faces"], gc["tet2face"], gc["sigma"], gc["nbr"], gc["face2tet"])
     with pytest.raises(B.PhfemError):  # kappa required for nk > 1
         B.phfem_condense_batch(*args, 2, None, gp, work, None, None, val, diag, rhs)
     with pytest.raises(B.PhfemError):  # nk >= 1

@@ -6,9 +6,7 @@ any size (the oracle cannot solve these meshes in seconds).
   J = 1/2 |U - u_target|^2: forward solve and adjoint in FP64 and in mixed precision, both
   to a true (matrix-free FP64) relative residual of 1e-12 (the FP64 mode needs a
   correction solve for it: its recurrence alone levels off near 3.5e-11 on this mesh);
-  mixed u_h within 5e-10 of FP64 (both near their attainable accuracy, about 6e-13 in the
-  residual; a residual difference reaches u_h amplified about 200-fold on this mesh, so
-  measured differences are 1-2e-10); mixed gradients within 1e-6 of FP64 (relative to the
+  mixed u_h within 1e-10 of FP64; mixed gradients within 1e-6 of FP64 (relative to the
   largest entry); the FP64 gradients against
   central differences of J along smooth directions of log kappa and of the coordinates
   (1e-6; smooth, so that the directional derivative is not a cancelling sum of per-tet
@@ -16,8 +14,10 @@ any size (the oracle cannot solve these meshes in seconds).
 * Fichera domain, 5 levels (10,450,944 tets), f = 1, zero Dirichlet data, lognormal kappa
   (sigma 0.5): exhaustive connectivity properties, sampled condensed rows against the
   oracle (FP64 1e-12, mixed 1e-5), the mixed solve (true FP64 residual 1e-11) with local
-  conservation on sampled tets, and the mixed adjoint against a central difference of J
-  along a smooth log-kappa direction (1e-5).
+  conservation on sampled tets, and the mixed adjoint against the FP64 mode's and against a
+  central difference of J along a smooth log-kappa direction (both 1e-6).
+* Kuhn cube, 6 levels (17,915,904 tets): mixed and FP64 face solves to a true relative
+  residual of 1e-11, u_h within 1e-10 of each other.
 """
 import numpy as np
 import pytest
@@ -42,6 +42,7 @@ SIN3 = (O.FUN_SIN3, (M.SIN3_AMPLITUDE,))
 def J_of(X, T, c, kappa, prm, mode, Ut, tol, stats=None):
     sysm = P.condense(X, T, c, kappa, prm)
     lam, U, st = P.solve(X, T, c, sysm, kappa, prm, mode=mode, tol=tol)
+    print(f"  solve mode {mode}: iters={st['iters']} true rel. residual={st['rel_res']:.2e}", flush=True)
     assert st["converged"]
     if stats is not None:
         stats.update(st)
@@ -88,7 +89,7 @@ def test_gradient_workload_mixed_vs_fp64(jittered5):
     J32, U32, _, g32, x32 = out[1]
     du = float((U32 - U64).abs().max()) / float(U64.abs().max())
     print(f"u_h mixed vs FP64: {du:.2e}", flush=True)
-    assert du <= 5e-10
+    assert du <= 1e-10
     assert float((g32 - g64).abs().max()) <= 1e-6 * float(g64.abs().max())
     assert float((x32 - x64).abs().max()) <= 1e-6 * float(x64.abs().max())
     oprm = O.params(c=1.0, f=SIN3)
@@ -139,21 +140,65 @@ def test_fichera_condense_rows(fichera5, precision, tol):
     check_rows(X, T, c, sysm, kap, O.params(c=1.0, kappa=1.0, f=f1), tol, np.random.default_rng(50 + precision))
 
 
+@pytest.mark.timeout(1500)
 def test_fichera_mixed_solve_adjoint(fichera5):
+    """The mixed adjoint gradient w.r.t. log kappa on the Fichera workload against the FP64
+    mode's gradient and against a central difference of J along a smooth direction, both to
+    1e-6 (J from FP64 solves at a true residual of 1e-12, step 2.5e-4: truncation ~1e-8)."""
     X, T, c, kap = fichera5
     f1 = (O.FUN_CONST, (1.0,))
-    prm = P.params(c=1.0, f=f1, precision=1)
-    J, sysm, lam, U = J_of(X, T, c, kap, prm, 1, 0.0, 1e-11)
+    p32 = P.params(c=1.0, f=f1, precision=1)
+    p64 = P.params(c=1.0, f=f1, precision=0)
+    J32, sysm, lam, U = J_of(X, T, c, kap, p32, 1, 0.0, 1e-11)
     check_conservation(X, T, c, kap, O.params(c=1.0, kappa=1.0, f=f1), U, lam, np.random.default_rng(51))
-    dlogk, _, st = P.grad(X, T, c, sysm, kap, prm, U, lam, U.contiguous(), mode=1, tol=1e-11, want_coord=False)
-    print(f"J={J:.10e} adjoint iters={st['iters']}", flush=True)
+    g32, _, st = P.grad(X, T, c, sysm, kap, p32, U, lam, U.contiguous(), mode=1, tol=1e-11, want_coord=False)
+    del sysm
+    J64, sysm, lam, U = J_of(X, T, c, kap, p64, 0, 0.0, 1e-12)
+    g64, _, st64 = P.grad(X, T, c, sysm, kap, p64, U, lam, U.contiguous(), mode=0, tol=1e-12, want_coord=False)
+    del sysm
+    dg = float((g32 - g64).abs().max()) / float(g64.abs().max())
+    print(f"J mixed={J32:.10e} FP64={J64:.10e}; adjoint iters mixed={st['iters']} FP64={st64['iters']}; "
+          f"gradient mixed vs FP64 {dg:.2e}", flush=True)
+    assert dg <= 1e-6
     d = smooth_tet_field(X, T)
-    eps = 1e-3
-    Jp = J_of(X, T, c, kap * torch.exp(eps * d), prm, 1, 0.0, 1e-11)[0]
-    Jm = J_of(X, T, c, kap * torch.exp(-eps * d), prm, 1, 0.0, 1e-11)[0]
-    fd, an = (Jp - Jm) / (2 * eps), float((dlogk * d).sum())
-    print(f"log kappa: fd={fd:.10e} adjoint={an:.10e}", flush=True)
-    assert abs(fd - an) <= 1e-5 * abs(an)
+    eps = 2.5e-4
+    Jp = J_of(X, T, c, kap * torch.exp(eps * d), p64, 0, 0.0, 1e-12)[0]
+    Jm = J_of(X, T, c, kap * torch.exp(-eps * d), p64, 0, 0.0, 1e-12)[0]
+    fd = (Jp - Jm) / (2 * eps)
+    a32, a64 = float((g32 * d).sum()), float((g64 * d).sum())
+    print(f"log kappa: fd={fd:.10e} adjoint mixed={a32:.10e} FP64={a64:.10e}", flush=True)
+    assert abs(fd - a64) <= 1e-6 * abs(a64)
+    assert abs(fd - a32) <= 1e-6 * abs(a32)
+
+
+@pytest.mark.timeout(1200)
+def test_kuhn_L6_mixed_vs_fp64_solve():
+    """Kuhn cube, 6 levels (17,915,904 tets, 35,856,384 faces): the face solve in mixed
+    precision (FP32 PCG corrections, FP64 refinement on the matrix-free residual) and in FP64,
+    both to a true relative residual of 1e-11; u_h agree within 1e-10 (relative to the largest
+    |u_h|).  Both times at that equal accuracy are printed."""
+    import time
+
+    X0, T0 = M.kuhn_cube()
+    X, T, c = P.refine_connected_levels(torch.tensor(X0, device=DEV), torch.tensor(T0, device=DEV), 6)
+    assert T.shape[1] == 17915904 and c["nF"] == 35856384
+    Us = {}
+    for prec, mode in ((1, 1), (0, 0)):
+        prm = P.params(c=1.0, kappa=1.0, f=SIN3, precision=prec)
+        sysm = P.condense(X, T, c, None, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, U, st = P.solve(X, T, c, sysm, None, prm, mode=mode, tol=1e-11, max_iter=600000)
+        torch.cuda.synchronize()
+        print(f"mode {mode}: {time.perf_counter() - t0:.1f} s, iters={st['iters']} ir_steps={st['ir_steps']} "
+              f"true rel. residual={st['rel_res']:.2e}", flush=True)
+        assert st["converged"] and st["rel_res"] <= 1e-11
+        Us[mode] = U
+        del sysm, lam
+        torch.cuda.empty_cache()
+    du = float((Us[1] - Us[0]).abs().max()) / float(Us[0].abs().max())
+    print(f"u_h mixed vs FP64: {du:.2e}", flush=True)
+    assert du <= 1e-10
 
 
 def test_mixed_solve_stagnation_reported(jittered5):

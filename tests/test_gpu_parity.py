@@ -310,8 +310,8 @@ def test_solve_parity(make, L, kind, mode, precision):
     kap = None if pb["kappa"] is None else dev(pb["kappa"])
     Xd, Td = dev(X), dev(T)
     sysm = P.condense(Xd, Td, gc, kap, gp)
-    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=0.7)
-    assert st["rel_res"] <= 1e-11, st
+    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=0.7, allow_noconv=True)
+    assert st["rel_res"] <= 1e-12, st
     assert np.abs(host(U) - oU).max() <= 1e-10 * np.abs(oU).max(), st
     assert np.abs(host(lam) - olam).max() <= 1e-9 * np.abs(olam).max(), st
 
@@ -341,8 +341,10 @@ def test_grad_parity(mode, precision):
     Xd, Td, kap = dev(X), dev(T), dev(pb["kappa"])
     gc = P.connect(Td, X.shape[1])
     sysm = P.condense(Xd, Td, gc, kap, gp)
-    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=0.7)
-    dlogk, dX, st2 = P.grad(Xd, Td, gc, sysm, kap, gp, U, lam, U - dev(Ut), mode=mode, tol=1e-13, inner_tol=0.7)
+    lam, U, st = P.solve(Xd, Td, gc, sysm, kap, gp, mode=mode, tol=1e-13, inner_tol=0.7, allow_noconv=True)
+    dlogk, dX, st2 = P.grad(Xd, Td, gc, sysm, kap, gp, U, lam, U - dev(Ut), mode=mode, tol=1e-13, inner_tol=0.7,
+                            allow_noconv=True)
+    assert st["rel_res"] <= 1e-12 and st2["rel_res"] <= 1e-12, (st, st2)
     assert np.abs(host(dlogk) - og["dlogk"]).max() <= 1e-6 * np.abs(og["dlogk"]).max()
     assert np.abs(host(dX) - og["dX"]).max() <= 1e-6 * np.abs(og["dX"]).max()
 
@@ -356,7 +358,7 @@ def test_autograd_function():
     gp = P.params(c=1.0, f=(O.FUN_SIN3, (M.SIN3_AMPLITUDE,)))
     logk = dev(np.log(kap)).requires_grad_(True)
     Xr = Xd.clone().requires_grad_(True)
-    U = P.PrimalHybridSolve.apply(logk, Xr, Td, gc, gp, 0, 1e-13)
+    U = P.PrimalHybridSolve.apply(logk, Xr, Td, gc, gp, 0, 1e-12)
     Ut = torch.zeros_like(U)
     J = 0.5 * ((U - Ut) ** 2).sum()
     J.backward()
@@ -533,7 +535,8 @@ def test_neumann_solve_parity(mode, precision):
     gc = P.connect(dev(T), X.shape[1])
     gp = P.params(**EXAMPLE, precision=precision, neumann=P.neumann_flags(gc, dev(Nb)))
     sysm = P.condense(dev(X), dev(T), gc, None, gp)
-    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=mode, tol=1e-13)
+    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=mode, tol=1e-13, allow_noconv=True)
+    assert st["rel_res"] <= 1e-12, st
     assert np.abs(host(gU) - U).max() <= 1e-10 * np.abs(U).max()
     gl = host(glam)
     assert np.abs(gl - lam)[nm == 0].max() <= 1e-9 * np.abs(lam).max()
@@ -551,7 +554,7 @@ def test_neumann_linear_exact_gpu():
     gc = P.connect(dev(T), X.shape[1])
     gp = P.params(**par, neumann=P.neumann_flags(gc, dev(Nb)))
     sysm = P.condense(dev(X), dev(T), gc, None, gp)
-    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=0, tol=1e-14)
+    glam, gU, st = P.solve(dev(X), dev(T), gc, sysm, None, gp, mode=0, tol=1e-14, allow_noconv=True)
     u = a[0] + a[1] * X[0] + a[2] * X[1] + a[3] * X[2]
     assert np.abs(host(gU) - u[T]).max() <= 1e-12
 
