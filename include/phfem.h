@@ -299,10 +299,12 @@ int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE, const int3
 enum { PHFEM_SOLVE_FP64_PCG = 0, PHFEM_SOLVE_FP32_PCG_FP64_IR = 1 };
 
 typedef struct {
-  int32_t iters;    /* PCG iterations (all inner iterations in IR mode) */
-  int32_t ir_steps; /* residual replacements (IR mode) / true-residual corrections (FP64 mode) */
-  double rel_res;   /* final ||b_D - C U(lambda)|| / ||r+||, evaluated in FP64 matrix-free */
-  double rhs_norm;  /* ||r+|| */
+  int32_t iters;        /* PCG iterations, all of them (FP32 and FP64 in IR mode) */
+  int32_t ir_steps;     /* residual replacements (IR mode) / true-residual corrections (FP64 mode) */
+  double rel_res;       /* final ||b_D - C U(lambda)|| / ||r+||, evaluated in FP64 matrix-free */
+  double rhs_norm;      /* ||r+|| */
+  int32_t polish_steps; /* IR mode: FP64 correction solves after the FP32 refinement */
+  int32_t polish_iters; /* IR mode: their PCG iterations (included in iters) */
 } phfem_solve_stats;
 
 size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
@@ -330,11 +332,17 @@ size_t phfem_solve_workspace(int64_t nE, int64_t nF, int32_t mode);
  *    0.9, measured best: rarer replacements let the FP32 recurrence drift from the true
  *    residual, which costs iterations as the condition number grows -- Kuhn L6 to 1e-10:
  *    63.6K iterations at 0.9 against 83.4K at 0.7) since the last replacement; the FP32
- *    iterate, scaled back by D^-1/2, is then added to
- *    the FP64 solution and the search direction kept.  Stops when the true residual meets
- *    tol, or with ENOCONV when 6 replacements in a row gain less than 10 % (tol below the
- *    attainable accuracy, about 6e-13 relative at Kuhn L5).  stats.ir_steps counts the
- *    replacements.
+ *    iterate, scaled back by D^-1/2, is then added to the FP64 solution and the search
+ *    direction kept.  The FP32 phase ends when the true residual meets tol or 6
+ *    replacements in a row gain less than 10 % (a replacement is also forced after 2048
+ *    iterations without that gain).  Then an FP64 polish: 1 to 3 correction solves on the
+ *    Jacobi-scaled FP64 stored system, each from the true residual to a relative 0.1
+ *    (continuing while tol is unmet and each halves the true residual): the
+ *    FP32 corrections barely resolve the smoothest error modes (cond x eps32 near 1 there),
+ *    which leaves the FP32-phase iterate's error about ten times the FP64 solve's at an
+ *    equal residual; the polish removes it.  ENOCONV when the true residual is still above
+ *    tol (attainable accuracy reached, or max_iter).  stats.ir_steps counts the
+ *    replacements, stats.polish_steps / polish_iters the FP64 corrections.
  * The true residual is summed per face from the per-tet terms, owner's first, so the
  * whole solve is bitwise reproducible run to run.
  * Outputs: lambda[nF], U[4][nE] (float64).  Synchronizes (residual checks every few

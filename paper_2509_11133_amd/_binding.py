@@ -56,10 +56,12 @@ class Params(C.Structure):
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("rel_res", C.c_double), ("rhs_norm", C.c_double)]
+    _fields_ = [("iters", C.c_int32), ("ir_steps", C.c_int32), ("rel_res", C.c_double), ("rhs_norm", C.c_double),
+                ("polish_steps", C.c_int32), ("polish_iters", C.c_int32)]
 
     def as_dict(self):
-        return dict(iters=self.iters, ir_steps=self.ir_steps, rel_res=self.rel_res, rhs_norm=self.rhs_norm)
+        return dict(iters=self.iters, ir_steps=self.ir_steps, rel_res=self.rel_res, rhs_norm=self.rhs_norm,
+                    polish_steps=self.polish_steps, polish_iters=self.polish_iters)
 
 
 def params(c=1.0, kappa=1.0, f=(FUN_ZERO, ()), ud=(FUN_ZERO, ()), quad=QUAD_FACE_CENTROID, precision=FP64,

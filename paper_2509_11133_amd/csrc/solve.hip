@@ -26,6 +26,10 @@ constexpr int ST = 256;
 constexpr int MAXG = 1024;
 constexpr int CHECK = 16;
 constexpr int REFRESH = 256;  // iterations between exact products q = A p (fused recurrence)
+constexpr int FORCE = 2048;  // iterations after which a residual replacement is forced
+constexpr int POLISH_MIN = 1;      // FP64 correction solves after the mixed refinement (at least)
+constexpr int POLISH_MAX = 3;      // (at most; each must halve the true residual to continue)
+constexpr double POLISH_TOL = 0.1;  // relative tolerance of each FP64 correction solve
 
 static unsigned pcg_grid(int64_t n) {
   int64_t g = (n + ST - 1) / ST;
@@ -375,7 +379,7 @@ static void pcg_layout(Arena& a, int64_t n, PcgWS& w) {
 }
 
 struct SolveWS {
-  PcgWS pcg;
+  PcgWS pcg, pcg64;  // pcg64: FP64 vectors of the mixed mode's FP64 polish
   double *bD, *r64, *e64, *val64s, *cu;
   float *val32, *x32;
   int* flags;
@@ -388,12 +392,14 @@ static void solve_layout(Arena& a, int64_t nE, int64_t nF, int32_t mode, SolveWS
     pcg_layout<double>(a, nF, w.pcg);
   w.bD = a.take<double>(nF);
   w.r64 = a.take<double>(nF);
-  w.e64 = mode == PHFEM_SOLVE_FP32_PCG_FP64_IR ? nullptr : a.take<double>(nF);
-  w.val64s = mode == PHFEM_SOLVE_FP32_PCG_FP64_IR ? nullptr : a.take<double>(6 * nF);
+  w.e64 = a.take<double>(nF);
+  w.val64s = a.take<double>(6 * nF);
   if (mode == PHFEM_SOLVE_FP32_PCG_FP64_IR) {
+    pcg_layout<double>(a, nF, w.pcg64);
     w.val32 = a.take<float>(6 * nF);
     w.x32 = a.take<float>(nF);
   } else {
+    w.pcg64 = w.pcg;
     w.val32 = w.x32 = nullptr;
   }
   w.cu = a.take<double>(4 * nE);
@@ -533,7 +539,7 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
     if (hf[1]) return err(PHFEM_EINVAL, "face system is not the 6-slot layout of phfem_condense (rowptr[F] = 6 F, "
                                         "column ids in [0, nF))");
   }
-  phfem_solve_stats loc = {0, 0, 0.0, 0.0};
+  phfem_solve_stats loc = {0, 0, 0.0, 0.0, 0, 0};
   if (mode == PHFEM_SOLVE_FP64_PCG) {
     // PCG on the stored system stops on its recurrence residual; the stored system differs
     // from the matrix-free FP64 operator by assembly rounding, so the true residual can level
@@ -613,20 +619,12 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
   if (rc) return rc;
   ref = std::sqrt(ref);
   double rel = 1.0, best = r0;
-  int slot = 0, it = 0, steps = 0, stall = 0;
+  int slot = 0, it = 0, steps = 0, stall = 0, last = 0;
   bool replace = false, done = false, exact = false;
   while (!done) {
     // below the attainable accuracy the true residual stops falling: 6 replacements in a row
     // without a 10 % gain end the solve early (as max_iter would, with the same error)
-    if (it >= maxit || stall >= 6) {
-      loc.iters = it;
-      loc.ir_steps = steps;
-      loc.rel_res = rel;
-      *st = loc;
-      return err(PHFEM_ENOCONV, stall >= 6 ? "mixed refinement stagnated above tolerance (attainable accuracy "
-                                             "reached; stats.rel_res holds it)"
-                                           : "mixed refinement reached max_iter above tolerance");
-    }
+    if (it >= maxit || stall >= 6) break;
     // direction step (exact product after a replacement and every REFRESH iterations)
     rc = pcg_direction<float, true>(nF, col, w.val32, nullptr, pw, slot, it == 0, exact || (it > 0 && it % REFRESH == 0),
                                     s);
@@ -662,6 +660,7 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
         exact = true;
       }
       replace = false;
+      last = it;
     }
     slot ^= 1;
     ++it;
@@ -669,13 +668,47 @@ static int face_solve(const MeshOp& m, const int32_t* rowptr, const int32_t* col
       double rr = 0;
       rc = read_scalar(pw.scal + 2, &rr, s);
       if (rc) return rc;
-      if (!(std::sqrt(rr) > REPLACE * ref) || !(rr == rr)) replace = true;
+      // replace when the recurrence has gained the factor, and also after FORCE iterations
+      // without that gain (a recurrence that has stopped descending, near the attainable
+      // accuracy, would otherwise never reach the stagnation test)
+      if (!(std::sqrt(rr) > REPLACE * ref) || !(rr == rr) || it - last >= FORCE) replace = true;
+    }
+  }
+  // FP64 polish.  The FP32 corrections leave the smoothest error modes (where cond x eps32
+  // approaches 1) barely resolved: at an equal true residual the mixed iterate's error is about
+  // ten times the FP64 solve's.  Correction solves on the stored FP64 system (its Jacobi-scaled
+  // copy) from the true residual remove that part; they start from a small residual and stop
+  // at a modest relative tolerance, so they cost a fraction of the FP32 iterations.
+  if (it < maxit) {
+    PH_LAUNCH("scale_f64", k_scale_f64, pcg_grid(6 * nF), ST, 0, s, nF, col, val, diag, w.val64s);
+    double rn = rel * r0;
+    for (int c = 0; c < POLISH_MAX && it < maxit; ++c) {
+      int pit = 0;
+      double prel = 0;
+      rc = pcg<double, true>(nF, col, w.val64s, diag, w.r64, w.e64, POLISH_TOL, maxit - it, w.pcg64, &pit, &prel, s);
+      if (rc) return rc;
+      it += pit;
+      loc.polish_iters += pit;
+      PH_LAUNCH("add_f64", k_add_f64, G, ST, 0, s, nF, (const double*)w.e64, x);
+      rc = residual(m, x, U, w.cu, w.r64, w.flags, s);
+      if (rc) return rc;
+      const double prev = rn;
+      rc = norm2(nF, w.r64, w.pcg64, &rn, s);
+      if (rc) return rc;
+      ++loc.polish_steps;
+      rel = rn / r0;
+      if (!(rel > tol) && c + 1 >= POLISH_MIN) break;
+      if (!(rn < 0.5 * prev) && c + 1 >= POLISH_MIN) break;
     }
   }
   loc.iters = it;
   loc.ir_steps = steps;
   loc.rel_res = rel;
   *st = loc;
+  if (rel > tol)
+    return err(PHFEM_ENOCONV, it >= maxit ? "mixed refinement reached max_iter above tolerance"
+                                          : "mixed refinement stagnated above tolerance (attainable accuracy "
+                                            "reached; stats.rel_res holds it)");
   return PHFEM_OK;
 }
 

@@ -37,8 +37,10 @@ def test_workspace_queries():
     assert L.phfem_connect_workspace(10 ** 6, 10 ** 6, 1) > 10 ** 6 * 6 * 20
     assert L.phfem_condense_workspace(20, 50, 100, 1) > 0
     assert L.phfem_condense_workspace(20, 50, 100, 0) > L.phfem_condense_workspace(20, 50, 100, 1)
-    # both modes hold a Jacobi-scaled copy of the 6 nF off-diagonal slots: 8 B (FP64) or 4 B each
-    assert L.phfem_solve_workspace(100, 200, 0) - L.phfem_solve_workspace(100, 200, 1) >= 6 * 200 * 4
+    # FP64 mode: a Jacobi-scaled FP64 copy of the 6 nF off-diagonal slots; the mixed mode holds an
+    # FP32 copy besides (its FP64 polish iterates on the FP64 one) and the polish's FP64 vectors
+    assert L.phfem_solve_workspace(100, 200, 0) >= 6 * 200 * 8
+    assert L.phfem_solve_workspace(100, 200, 1) - L.phfem_solve_workspace(100, 200, 0) >= 6 * 200 * 4
     assert L.phfem_grad_workspace(100, 200, 0) > L.phfem_solve_workspace(100, 200, 0)
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 2) > L.phfem_refine_connected_workspace(72, 114)
     assert L.phfem_refine_connected_levels_workspace(8, 6, 19, 18, 0) == 0
