@@ -399,6 +399,20 @@ int phfem_errors(int64_t nC, const double* coord, int64_t nE, const int32_t* tet
                  const double* lambda, int32_t u_kind, const double* u_par, double h, int32_t nq, void* work,
                  size_t work_bytes, double* out, phfem_stream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc and caller workspaces): phfem_errors without the
+ * workspace argument.  Its scratch (per-block partial sums, totals, the index-check word;
+ * 2 MiB) is a fixed device array of the library, one copy per GPU the library runs on,
+ * held until the process ends; the call allocates nothing.  Same inputs, outputs, kernels
+ * and results (bit for bit) as phfem_errors.  Limit: nE <= PHFEM_ERRORS_NOALLOC_MAX_TETS
+ * (EINVAL beyond it).  Calls that overlap in time on one GPU share that array and race:
+ * serialize them (one stream, or host-side ordering).  Synchronizes. */
+#define PHFEM_ERRORS_NOALLOC_MAX_TETS 22364160
+int phfem_errors_noalloc(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                         const int32_t* tet2face, const int8_t* sigma, const double* kappa, const phfem_params* p,
+                         const double* U, const double* lambda, int32_t u_kind, const double* u_par, double h,
+                         int32_t nq, double* out, phfem_stream_t stream);
+
 /* ---------------------------------------------------------------- profiling --------- */
 /* When enabled, every kernel launch of the library is bracketed by HIP events on its
  * stream.  phfem_profile_query synchronizes those events and returns, for the kernel

@@ -29,8 +29,9 @@ EXPORTS = [
     "phfem_profile_names", "phfem_refine_connected_workspace", "phfem_refine_connected", "phfem_refined_sizes",
     "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels", "phfem_errors_workspace",
     "phfem_errors", "phfem_condense_batch_workspace", "phfem_condense_batch", "phfem_refine_workspace",
-    "phfem_face_lookup_workspace", "phfem_face_lookup",
+    "phfem_face_lookup_workspace", "phfem_face_lookup", "phfem_errors_noalloc",
 ]
+ERRORS_NOALLOC_MAX_TETS = 22364160
 
 
 class PhfemError(RuntimeError):
@@ -128,6 +129,7 @@ def lib():
         L.phfem_condense_batch_workspace.argtypes = [I64, I64, I64, I32, I32]
         L.phfem_condense_batch.argtypes = [I64, VP, I64, VP, I64] + [VP] * 5 + [I32, VP, VP, VP, SZ] + [VP] * 5 + [VP]
         L.phfem_errors.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, SZ, VP, VP]
+        L.phfem_errors_noalloc.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, VP]
         L.phfem_profile_enable.argtypes = [I32]
         L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
         L.phfem_profile_names.argtypes = [C.c_char_p, SZ]
@@ -257,6 +259,16 @@ def phfem_errors(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, prm, U, lam, 
     _chk(lib().phfem_errors(nC, _p(coord), nE, _p(tetra), nF, _p(tet2face), _p(sigma), _p(kappa), C.addressof(prm),
                             _p(U), _p(lam), u_kind, C.addressof(par), h, nq, _p(work), work.numel(),
                             C.addressof(out), _stream()))
+    return out[0], out[1], out[2]
+
+
+def phfem_errors_noalloc(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, prm, U, lam, u_kind, u_par, h, nq):
+    """phfem_errors with the library's fixed scratch (no workspace): the same three sums."""
+    par = (C.c_double * 4)(*([float(v) for v in u_par] + [0.0] * (4 - len(u_par))))
+    out = (C.c_double * 3)()
+    _chk(lib().phfem_errors_noalloc(nC, _p(coord), nE, _p(tetra), nF, _p(tet2face), _p(sigma), _p(kappa),
+                                    C.addressof(prm), _p(U), _p(lam), u_kind, C.addressof(par), h, nq,
+                                    C.addressof(out), _stream()))
     return out[0], out[1], out[2]
 
 

@@ -11,6 +11,7 @@
 // the Legendre three-term recurrence.  One thread per tet, per-block partial sums reduced in
 // a fixed order (deterministic).
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -198,6 +199,32 @@ __global__ __launch_bounds__(ERT) void k_errors_sum(int64_t nb, const double* __
 
 __global__ void k_errors_clear(uint32_t* __restrict__ bad) { *bad = 0u; }
 
+// Scratch of phfem_errors_noalloc: the per-block partial sums, the three totals and the
+// index-check word, in a fixed device array (no allocation and no caller workspace).  Every
+// GPU that runs the library holds one copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr size_t NOALLOC_BYTES = size_t(2) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_BYTES / sizeof(double)];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[MAX_DEVICES];
+
+// the current device's address of `scratch`, looked up once per device
+static int scratch_address(void** out) {
+  int d = 0;
+  PH_HIP(hipGetDevice(&d));
+  if (d < 0 || d >= MAX_DEVICES) return err(PHFEM_EINVAL, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[d]) {
+    void* p = nullptr;
+    PH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch[d] = p;
+  }
+  *out = g_scratch[d];
+  return PHFEM_OK;
+}
+
 static size_t errors_scratch_bytes(int64_t nE) {
   Arena a;
   a.take<double>(3 * ((nE + ERT - 1) / ERT));
@@ -266,4 +293,20 @@ extern "C" int phfem_errors(int64_t nC, const double* coord, int64_t nE, const i
   if (!work || work_bytes < phfem_errors_workspace(nE)) return err(PHFEM_EWORKSPACE, "errors workspace too small");
   return errors_run(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, p, U, lambda, u_kind, u_par, h, nq, work,
                     work_bytes, out, (hipStream_t)stream_);
+}
+
+extern "C" int phfem_errors_noalloc(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                                    const int32_t* tet2face, const int8_t* sigma, const double* kappa,
+                                    const phfem_params* p, const double* U, const double* lambda, int32_t u_kind,
+                                    const double* u_par, double h, int32_t nq, double* out, phfem_stream_t stream_) {
+  clear_error();
+  int rc = errors_args_ok(nC, coord, nE, tetra, nF, tet2face, sigma, p, U, lambda, u_kind, u_par, h, nq, out);
+  if (rc) return rc;
+  if (nE > PHFEM_ERRORS_NOALLOC_MAX_TETS || errors_scratch_bytes(nE) > NOALLOC_BYTES)
+    return err(PHFEM_EINVAL, "phfem_errors_noalloc: nE exceeds PHFEM_ERRORS_NOALLOC_MAX_TETS (use phfem_errors)");
+  void* base = nullptr;
+  rc = scratch_address(&base);
+  if (rc) return rc;
+  return errors_run(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, p, U, lambda, u_kind, u_par, h, nq, base,
+                    NOALLOC_BYTES, out, (hipStream_t)stream_);
 }
