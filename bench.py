@@ -36,21 +36,47 @@ def kuhn_counts(L):
     return nE, nC, nEd, nF, nB
 
 
-def compulsory_bytes(L):
-    """Algorithmic bytes of the whole pipeline (every array read once and written once):
-    per level l < L edge connectivity of level l and refinement to l+1; at level L full
-    connectivity and the condensed assembly (FP64 face system)."""
-    tot = 0.0
-    for l in range(L):
-        nE, nC, nEd, nF, nB = kuhn_counts(l)
-        tot += 16 * nE + 8 * nEd + 24 * nE + 4 * nEd + 4 * nE              # connect edges: tets -> U, tet2edge, first, prefix
-        tot += 16 * nE + 28 * nE + 4 * nEd + 24 * nC + 192 * nE + 24 * (nE + nEd)  # refine
+def section8d_rows(L):
+    """Compulsory bytes of the pipeline by stage, each input read once and each output written
+    once, with the arrays' own sizes (the per-tet figures of the hot-path measurement plan,
+    evaluated with the exact counts of the Kuhn cube at level L; kappa constant, so no kappa
+    array is read).  Returns {stage: bytes}."""
     nE, nC, nEd, nF, nB = kuhn_counts(L)
-    tot += 16 * nE + 8 * nEd + 24 * nE + 4 * nEd + 4 * nE
-    tot += 12 * nF + 16 * nE + 4 * nE + 8 * nF + 16 * nE                      # faces, tet2face, sigma, face2tet, nbr
-    nnz = 6 * nF - 3 * nB
-    tot += 52 * nE + 24 * nC + 4 * nF + 12 * nnz + 16 * nF                    # condense
-    return tot
+    cE, cC, cEd, cF, cB = kuhn_counts(L - 1)
+    rows = {}
+    # refinement of level L-1 to L: coarse tets, tet->edge, coordinates, edge/tet prefix in;
+    # refined tets and the new coordinates out
+    rows["refine"] = 16 * cE + 24 * cE + 24 * cC + 4 * cEd + 4 * cE + 16 * nE + 24 * (cEd + cE)
+    # connectivity of level L: tets in; edges, tet->edge, tet->face + sigma (4 bits), faces,
+    # face->tet out
+    rows["connect"] = 16 * nE + 8 * nEd + 24 * nE + 16.5 * nE + 12 * nF + 8 * nF
+    # edge connectivity of the levels below L (tets in, edges and tet->edge out)
+    rows["connect_lower"] = sum(16 * e + 24 * e + 8 * ed for e, _, ed, _, _ in (kuhn_counts(l) for l in range(L)))
+    # assembly + condensation: tets, coordinates, tet->face + sigma in; the face system out
+    # (values and column ids of nnz = 7 nI + 4 nB entries with the diagonal, row pointers, rhs)
+    nnz = 7 * (nF - nB) + 4 * nB
+    rows["condense"] = 16 * nE + 24 * nC + 16.5 * nE + 8 * nnz + 4 * nnz + 4 * (nF + 1) + 8 * nF
+    return rows
+
+
+def compulsory_bytes(L):
+    return sum(section8d_rows(L).values())
+
+
+# The dominant kernels' share of those compulsory bytes per launch at the final level: the
+# tile pass of the condensation reads the mesh and writes the whole face system (the
+# "condense" row); the second refinement-connectivity pass writes the refined mesh's
+# connectivity (the "connect" row less its tet reads, which the derived path does not make).
+def kernel_8d_bytes(name, L):
+    rows = section8d_rows(L)
+    nE = kuhn_counts(L)[0]
+    if name.startswith("cond_tile"):
+        return rows["condense"]
+    if name == "refconn_pass2":
+        return rows["connect"] - 16 * nE
+    if name == "refine":
+        return rows["refine"]
+    return None
 
 
 def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False, status=None):
@@ -139,20 +165,30 @@ def pipeline_traffic(kern, steps):
     return tot
 
 
-def roofline(kern, steps):
+def roofline(kern, steps, L):
+    """The dominant kernel (largest summed HIP-event time in the profiled pass) against HBM
+    peak: achieved = its compulsory bytes per launch at the final level (kernel_8d_bytes) / its
+    average launch time (of the final-level launches: the kernels that run once per step)."""
     name, k = max(kern.items(), key=lambda kv: kv[1]["ms"])
-    if k["bytes"] <= 0:  # fall back to the heaviest kernel with a byte count
-        name, k = max(((n, v) for n, v in kern.items() if v["bytes"] > 0), key=lambda kv: kv[1]["ms"])
-    gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    b8 = kernel_8d_bytes(name, L)
+    per_step = k["launches"] // max(steps, 1)
+    avg = k["ms"] / max(k["launches"], 1)
+    if b8 is None or per_step != 1:
+        return name, None
+    gbs = b8 / (avg * 1e-3) / 1e9
     return name, dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(name), kernel=name,
-                      launches_per_step=k["launches"] // max(steps, 1),
-                      avg_launch_ms=round(k["ms"] / max(k["launches"], 1), 5),
-                      algorithmic_bytes_per_step=k["bytes"] / max(steps, 1))
+                      launches_per_step=per_step, avg_launch_ms=round(avg, 5), algorithmic_bytes_per_launch=b8,
+                      kernel_bytes_per_launch=k["bytes"] / max(k["launches"], 1),
+                      note="algorithmic bytes: the compulsory reads and writes of what the kernel produces "
+                           "(mesh in, face system out); kernel_bytes_per_launch adds its own intermediates; "
+                           "traffic: rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by the "
+                           "library's calibration streams")
 
 
-def cpu_baseline(levels):
-    """The oracle (single-threaded FP64 C++) on the same pipeline at a smaller level."""
+def cpu_baseline(levels, runs=3):
+    """The oracle (single-threaded FP64 C++) on the same pipeline at a smaller level: the median
+    of `runs` runs."""
     import numpy as np
 
     import oracle as O
@@ -167,17 +203,23 @@ def cpu_baseline(levels):
     core = min(aff) if aff else None
     if aff:
         os.sched_setaffinity(0, {core})
+    X0, T0, db0 = X, T, db
+    times = []
     try:
-        t0 = time.perf_counter()
-        for _ in range(levels):
-            O.edges(X.shape[1], T)
-            X, T, db, _ = O.refine(X, T, db)
-        conn = O.connect(X.shape[1], T)
-        O.condense(X, T, conn, None, prm)
-        dt = time.perf_counter() - t0
+        for _ in range(runs):
+            X, T, db = X0, T0, db0
+            t0 = time.perf_counter()
+            for _ in range(levels):
+                O.edges(X.shape[1], T)
+                X, T, db, _ = O.refine(X, T, db)
+            conn = O.connect(X.shape[1], T)
+            O.condense(X, T, conn, None, prm)
+            times.append(time.perf_counter() - t0)
+            del conn
     finally:
         if aff:
             os.sched_setaffinity(0, aff)
+    dt = sorted(times)[len(times) // 2]
     nE = T.shape[1]
     del np
     cpu = "unknown"
@@ -190,8 +232,9 @@ def cpu_baseline(levels):
         pass
     return dict(value=round(nE / dt, 1), unit="tets/s", cores=1, kind="oracle",
                 host_cpu=cpu, host_cores=os.cpu_count(), pinned_core=core,
+                runs_s=[round(t, 3) for t in times],
                 sample=f"Kuhn cube, {levels} levels ({nE} tets): edges+refine per level, full connectivity, "
-                       f"condensed assembly; FP64, 1 thread pinned to one core; {dt:.2f} s")
+                       f"condensed assembly; FP64, 1 thread pinned to one core; median of {runs} runs {dt:.2f} s")
 
 
 def solve_block(torch, P, B, M, Ls):
@@ -313,18 +356,27 @@ def main():
     ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
     ap.add_argument("--no-reassembly", action="store_true", help="skip the pattern-reuse / batched-kappa timings")
     ap.add_argument("--no-paper-mesh", action="store_true", help="skip the paper's 5-tet cube timings")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only copy 1 GiB device-to-device 3 times (the reference kernel that scales the "
-                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run the library's calibration streams (1 GiB read, 1 GiB write, 1 GiB copy, "
+                         "2^25 scattered 32-byte records gathered from a 2 GiB array), each twice, and exit: "
+                         "profiled with FETCH_SIZE / WRITE_SIZE they give the counters' scale")
     args = ap.parse_args()
-    if args.calibrate_copy:
+    if args.calibrate:
         import torch
-        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
+
+        from paper_2509_11133_amd import _binding as B
+        n = 1 << 27  # doubles: 1 GiB
+        a = torch.ones(2 * n, dtype=torch.float64, device="cuda")  # 2 GiB (2^26 records of 32 B)
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        part = torch.empty(4096, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            B.phfem_profile_stream(0, a, part, n)
+            B.phfem_profile_stream(1, None, b, n)
+            B.phfem_profile_stream(2, a, b, n)
+            B.phfem_profile_stream(3, a, part, 1 << 25, 1 << 26)
         torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 3}))
+        print(json.dumps({"cal_read": 8 * n, "cal_write": 8 * n, "cal_copy_read": 8 * n, "cal_copy_write": 8 * n,
+                          "cal_gather_requested": 32 << 25, "repeats": 2}))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -394,8 +446,9 @@ def main():
             "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4)
                                     for k, v in sorted(ms_["kern"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
     if mixed["kern"]:
-        name, rl = roofline(mixed["kern"], args.steps)
+        name, rl = roofline(mixed["kern"], args.steps, L)
         line["roofline"] = rl
+        line["compulsory_bytes_by_stage"] = {k: round(v) for k, v in section8d_rows(L).items()}
         pt = pipeline_traffic(mixed["kern"], args.steps)
         line["achieved_hbm_frac"] = None if pt is None else round(pt / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
         line["measured_bytes_per_step"] = None if pt is None else round(pt)

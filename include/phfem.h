@@ -422,6 +422,13 @@ int phfem_errors_noalloc(int64_t nC, const double* coord, int64_t nE, const int3
  * writes the names seen, comma separated.  Host-side bookkeeping only; not thread safe
  * against concurrent launches from several threads. */
 void phfem_profile_enable(int32_t on);
+/* Streams of known size that scale the HBM traffic counters of a profiler run (reads counted by
+ * FETCH_SIZE, writes by WRITE_SIZE): op 0 reads n doubles of src (16-byte loads) and writes one
+ * partial sum per workgroup to dst[0..4095]; op 1 writes n doubles to dst; op 2 copies n
+ * doubles from src to dst; op 3 gathers n 32-byte records of src[m][4] (m a power of two) at
+ * the positions (j * 2654435761) mod m, partial sums to dst[0..4095].  n even for ops 0-2;
+ * src 32-byte and dst 16-byte aligned.  Asynchronous.  Errors: EINVAL. */
+int phfem_profile_stream(int32_t op, const double* src, double* dst, int64_t n, int64_t m, phfem_stream_t stream);
 void phfem_profile_reset(void);
 int phfem_profile_query(const char* name, int64_t* launches, double* total_ms, double* total_bytes);
 int phfem_profile_names(char* buf, size_t buf_bytes);

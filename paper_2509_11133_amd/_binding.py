@@ -30,6 +30,7 @@ EXPORTS = [
     "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels", "phfem_errors_workspace",
     "phfem_errors", "phfem_condense_batch_workspace", "phfem_condense_batch", "phfem_refine_workspace",
     "phfem_face_lookup_workspace", "phfem_face_lookup", "phfem_errors_noalloc",
+    "phfem_profile_stream",
 ]
 ERRORS_NOALLOC_MAX_TETS = 22364160
 
@@ -131,6 +132,7 @@ def lib():
         L.phfem_errors.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, SZ, VP, VP]
         L.phfem_errors_noalloc.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, VP]
         L.phfem_profile_enable.argtypes = [I32]
+        L.phfem_profile_stream.argtypes = [I32, VP, VP, I64, I64, VP]
         L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
         L.phfem_profile_names.argtypes = [C.c_char_p, SZ]
         _lib = L
@@ -274,6 +276,11 @@ def phfem_errors_noalloc(nC, coord, nE, tetra, nF, tet2face, sigma, kappa, prm, 
 
 def phfem_profile_enable(on):
     lib().phfem_profile_enable(1 if on else 0)
+
+
+def phfem_profile_stream(op, src, dst, n, m=0):
+    """Calibration stream of known size: 0 read, 1 write, 2 copy, 3 gather of 32-byte records."""
+    _chk(lib().phfem_profile_stream(op, _p(src), _p(dst), n, m, _stream()))
 
 
 def phfem_profile_reset():

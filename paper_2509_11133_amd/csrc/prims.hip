@@ -314,6 +314,55 @@ int radix_sort(uint64_t* keysA, int32_t* valsA, uint64_t* keysB, int32_t* valsB,
   return PHFEM_OK;
 }
 
+// ------------------------------------------------------------------ counter calibration
+// Streams of known size for scaling the HBM traffic counters (FETCH_SIZE, WRITE_SIZE):
+// read n doubles (16-byte loads, one partial sum per workgroup written), write n doubles,
+// copy n doubles, or gather n 32-byte records at scattered positions of an array of m.
+constexpr int CALT = 256;
+
+__global__ __launch_bounds__(CALT) void k_cal_read(int64_t n2, const double2* __restrict__ src,
+                                                   double* __restrict__ part) {
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * CALT + threadIdx.x; i < n2; i += (int64_t)gridDim.x * CALT) {
+    const double2 v = src[i];
+    a += v.x + v.y;
+  }
+  __shared__ double l[CALT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+  if ((threadIdx.x & 63) == 0) l[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (l[0] + l[1]) + (l[2] + l[3]);
+}
+
+__global__ __launch_bounds__(CALT) void k_cal_write(int64_t n2, double2* __restrict__ dst, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * CALT + threadIdx.x; i < n2; i += (int64_t)gridDim.x * CALT)
+    dst[i] = make_double2(v, v + 1.0);
+}
+
+__global__ __launch_bounds__(CALT) void k_cal_copy(int64_t n2, const double2* __restrict__ src,
+                                                   double2* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * CALT + threadIdx.x; i < n2; i += (int64_t)gridDim.x * CALT) dst[i] = src[i];
+}
+
+// record j of the gather: (j * 2654435761) mod m, an odd multiplier over a power-of-two m
+// (a permutation of the records); each 32-byte record read with two 16-byte loads
+__global__ __launch_bounds__(CALT) void k_cal_gather(int64_t n, int64_t m, const double4* __restrict__ src,
+                                                     double* __restrict__ part) {
+  double a = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * CALT + threadIdx.x; j < n; j += (int64_t)gridDim.x * CALT) {
+    const uint64_t q = ((uint64_t)j * 2654435761ull) & (uint64_t)(m - 1);
+    const double4 v = src[q];
+    a += (v.x + v.y) + (v.z + v.w);
+  }
+  __shared__ double l[CALT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+  if ((threadIdx.x & 63) == 0) l[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (l[0] + l[1]) + (l[2] + l[3]);
+}
+
 }  // namespace ph
 
 // ------------------------------------------------------------------ C-ABI: errors, profiler
@@ -323,6 +372,36 @@ const char* phfem_last_error(void) { return ph::g_error.c_str(); }
 int phfem_abi_version(void) { return 2; }
 
 void phfem_profile_enable(int32_t on) { ph::g_prof = on != 0; }
+
+int phfem_profile_stream(int32_t op, const double* src, double* dst, int64_t n, int64_t m, phfem_stream_t stream_) {
+  using namespace ph;
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  const unsigned G = 4096;  // grid-stride: partial sums of the read kernels fit dst[G]
+  if (n <= 0 || (op != 3 && (n & 1))) return err(PHFEM_EINVAL, "n must be positive (and even for streams)");
+  if (reinterpret_cast<uintptr_t>(src) & 31 || reinterpret_cast<uintptr_t>(dst) & 15)
+    return err(PHFEM_EINVAL, "src 32-byte and dst 16-byte aligned");
+  switch (op) {
+    case 0:
+      if (!src || !dst) return err(PHFEM_EINVAL, "null src/dst");
+      PH_LAUNCH_B("cal_read", 8.0 * n, k_cal_read, G, CALT, 0, s, n / 2, (const double2*)src, dst);
+      return PHFEM_OK;
+    case 1:
+      if (!dst) return err(PHFEM_EINVAL, "null dst");
+      PH_LAUNCH_B("cal_write", 8.0 * n, k_cal_write, G, CALT, 0, s, n / 2, (double2*)dst, 1.0);
+      return PHFEM_OK;
+    case 2:
+      if (!src || !dst) return err(PHFEM_EINVAL, "null src/dst");
+      PH_LAUNCH_B("cal_copy", 16.0 * n, k_cal_copy, G, CALT, 0, s, n / 2, (const double2*)src, (double2*)dst);
+      return PHFEM_OK;
+    case 3:
+      if (!src || !dst || m <= 0 || (m & (m - 1))) return err(PHFEM_EINVAL, "gather: m must be a power of two");
+      PH_LAUNCH_B("cal_gather", 32.0 * n, k_cal_gather, G, CALT, 0, s, n, m, (const double4*)src, dst);
+      return PHFEM_OK;
+    default:
+      return err(PHFEM_EINVAL, "op must be 0 (read), 1 (write), 2 (copy) or 3 (gather)");
+  }
+}
 
 void phfem_profile_reset(void) {
   std::lock_guard<std::mutex> lk(ph::g_prof_mu);
