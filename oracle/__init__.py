@@ -25,10 +25,19 @@ FUN_ZERO, FUN_CONST, FUN_SIN3, FUN_LINEAR, FUN_X2Y2Z2, FUN_X2Y2Z2_LOAD = 0, 1, 2
 QUAD_FACE_CENTROID, QUAD_P1_INTERP = 0, 1
 
 
+# PHFEM_ORACLE_SANITIZE=1: an AddressSanitizer + UndefinedBehaviorSanitizer build (its own file),
+# for a process started with gcc's libasan preloaded (tests/test_sanitizers.py)
+_SAN = os.environ.get("PHFEM_ORACLE_SANITIZE") == "1"
+if _SAN:
+    _LIB = os.path.join(_HERE, "liboracle_san.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with g++ (single-threaded, -O2, no fast-math)."""
+    """Compile liboracle.so with g++ (single-threaded, -O2, no fast-math), or the sanitizer build."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", _SRC, "-o", _LIB])
+        opt = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer"] if _SAN else ["-O2"])
+        subprocess.check_call(["g++", *opt, "-std=c++17", "-fPIC", "-shared", _SRC, "-o", _LIB])
     return _LIB
 
 

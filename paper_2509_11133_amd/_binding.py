@@ -13,7 +13,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libphfem.so")
+# PHFEM_LIB names another build of the same library (a sanitizer build of the host code, in the
+# sanitizer tests); default: the in-tree build
+LIB_PATH = os.environ.get("PHFEM_LIB") or os.path.join(HERE, "libphfem.so")
 
 OK, EINVAL, EORIENT, EDEGEN, ESINGULAR, ENOCONV, EWORKSPACE, EHIP = range(8)
 FUN_ZERO, FUN_CONST, FUN_SIN3, FUN_LINEAR, FUN_X2Y2Z2, FUN_X2Y2Z2_LOAD = range(6)

@@ -778,7 +778,7 @@ static void rc_layout(Arena& a, int64_t nE, int64_t nEd, RCWS& w) {
   w.ntiles = (nE + RCW - 1) / RCW;
   const int64_t sw = scan_status_words(4 * w.ntiles);
   w.z = a.take<uint32_t>(4 + 2 * sw);
-  w.st = reinterpret_cast<uint64_t*>(w.z + 4);
+  w.st = w.z ? reinterpret_cast<uint64_t*>(w.z + 4) : nullptr;  // (a size query lays out from null)
   w.nz = 4 + 2 * sw;
   w.tagg = a.take<uint32_t>(4 * w.ntiles);
   w.tpre = a.take<uint32_t>(4 * w.ntiles + 2);
