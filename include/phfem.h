@@ -357,6 +357,30 @@ int phfem_solve(int64_t nC, const double* coord, int64_t nE, const int32_t* tetr
                 int32_t max_iter, void* work, size_t work_bytes, double* lambda, double* U,
                 phfem_solve_stats* stats, phfem_stream_t stream);
 
+/* Several loads on one face system (Algorithm 1: the condensed S serves every load; the loads
+ * differ in f, u_D and g, not in kappa or c): nk (1..8) right-hand sides solved together.
+ * p[nk]: one params struct per load, all with the same c, kappa_const, precision and
+ * neumann == NULL (EINVAL otherwise; the Dirichlet boundary of the paper's system); kappa is
+ * shared.  (rowptr, col, val, diag): the 6-slot system of phfem_condense (either precision;
+ * checked once per call).  rhs[nk][nF] (may be NULL): the r+ of each load as phfem_condense
+ * writes it; NULL: r+ = b_D - C A^-1 B evaluated per tet in FP64 (the true residual at
+ * lambda = 0).  FP64 Jacobi-PCG for all loads in lockstep on the Jacobi-scaled FP64 copy of
+ * the system: each iteration reads the matrix once for all loads (interleaved vectors; 72 B
+ * per face of matrix plus 40 B per face and load, against 72 + 40 B per face for every load
+ * solved alone), with each load's own alpha and beta, a load frozen once its recurrence
+ * residual meets tol; then, as phfem_solve's FP64 mode, correction solves on the true
+ * residuals (matrix-free FP64) of the loads still above tol, in lockstep again.
+ * Outputs: lambda[nk][nF], U[nk][4][nE], stats[nk] (host; iters = lockstep iterations while
+ * that load was active).  Synchronizes.  Errors: EINVAL, EDEGEN, ENOCONV (a load stopped
+ * above tol; all outputs and stats are still written), EWORKSPACE. */
+size_t phfem_solve_multi_workspace(int64_t nE, int64_t nF, int32_t nk);
+int phfem_solve_multi(int64_t nC, const double* coord, int64_t nE, const int32_t* tetra, int64_t nF,
+                      const int32_t* faces, const int32_t* tet2face, const int8_t* sigma, const int32_t* face2tet,
+                      const double* kappa, int32_t nk, const phfem_params* p, const int32_t* rowptr,
+                      const int32_t* col, const double* val, const double* diag, const double* rhs, double tol,
+                      int32_t max_iter, void* work, size_t work_bytes, double* lambda, double* U,
+                      phfem_solve_stats* stats, phfem_stream_t stream);
+
 /* ---------------------------------------------------------------- grad (a10) -------- */
 size_t phfem_grad_workspace(int64_t nE, int64_t nF, int32_t mode);
 

@@ -32,7 +32,7 @@ EXPORTS = [
     "phfem_refine_connected_levels_workspace", "phfem_refine_connected_levels", "phfem_errors_workspace",
     "phfem_errors", "phfem_condense_batch_workspace", "phfem_condense_batch", "phfem_refine_workspace",
     "phfem_face_lookup_workspace", "phfem_face_lookup", "phfem_errors_noalloc",
-    "phfem_profile_stream",
+    "phfem_profile_stream", "phfem_solve_multi_workspace", "phfem_solve_multi",
 ]
 ERRORS_NOALLOC_MAX_TETS = 22364160
 
@@ -104,7 +104,8 @@ def lib():
         for n in ("phfem_connect_workspace", "phfem_condense_workspace", "phfem_solve_workspace",
                   "phfem_grad_workspace", "phfem_refine_connected_workspace",
                   "phfem_refine_connected_levels_workspace", "phfem_errors_workspace",
-                  "phfem_condense_batch_workspace", "phfem_refine_workspace", "phfem_face_lookup_workspace"):
+                  "phfem_condense_batch_workspace", "phfem_refine_workspace", "phfem_face_lookup_workspace",
+                  "phfem_solve_multi_workspace"):
             getattr(L, n).restype = SZ
         L.phfem_connect_workspace.argtypes = [I64, I64, I32]
         L.phfem_condense_workspace.argtypes = [I64, I64, I64, I32]
@@ -133,6 +134,9 @@ def lib():
         L.phfem_condense_batch.argtypes = [I64, VP, I64, VP, I64] + [VP] * 5 + [I32, VP, VP, VP, SZ] + [VP] * 5 + [VP]
         L.phfem_errors.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, SZ, VP, VP]
         L.phfem_errors_noalloc.argtypes = [I64, VP, I64, VP, I64] + [VP] * 4 + [VP] * 2 + [I32, VP, DBL, I32, VP, VP]
+        L.phfem_solve_multi_workspace.argtypes = [I64, I64, I32]
+        L.phfem_solve_multi.argtypes = ([I64, VP, I64, VP, I64] + [VP] * 5 + [I32, VP] + [VP] * 5
+                                        + [DBL, I32, VP, SZ, VP, VP, VP, VP])
         L.phfem_profile_enable.argtypes = [I32]
         L.phfem_profile_stream.argtypes = [I32, VP, VP, I64, I64, VP]
         L.phfem_profile_query.argtypes = [C.c_char_p, VP, VP, VP]
@@ -240,6 +244,19 @@ def phfem_solve(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, kapp
     rc = lib().phfem_solve(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(face2tet),
                            _p(kappa), C.addressof(prm), _p(rowptr), _p(col), _p(val), _p(diag), _p(rhs), mode, tol,
                            inner_tol, max_iter, _p(work), work.numel(), _p(lam), _p(U), C.addressof(stats), _stream())
+    if check:
+        _chk(rc)
+    return rc
+
+
+def phfem_solve_multi(nC, coord, nE, tetra, nF, faces, tet2face, sigma, face2tet, kappa, prms, rowptr, col, val, diag,
+                      rhs, tol, max_iter, work, lam, U, stats, check=True):
+    """prms: a sequence of Params (one per load); stats: a ctypes array of SolveStats of that length."""
+    arr = (Params * len(prms))(*prms)
+    rc = lib().phfem_solve_multi(nC, _p(coord), nE, _p(tetra), nF, _p(faces), _p(tet2face), _p(sigma), _p(face2tet),
+                                 _p(kappa), len(prms), C.addressof(arr), _p(rowptr), _p(col), _p(val), _p(diag),
+                                 _p(rhs), tol, max_iter, _p(work), work.numel(), _p(lam), _p(U), C.addressof(stats),
+                                 _stream())
     if check:
         _chk(rc)
     return rc

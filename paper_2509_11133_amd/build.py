@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphfem.so")
-SOURCES = ["prims.hip", "connect.hip", "refine.hip", "refconn.hip", "fe.hip", "solve.hip", "errors.hip", "facelookup.hip"]
+SOURCES = ["prims.hip", "connect.hip", "refine.hip", "refconn.hip", "fe.hip", "solve.hip", "msolve.hip", "errors.hip", "facelookup.hip"]
 ARCH = os.environ.get("PHFEM_ARCH", "gfx950")
 
 FLAGS = [

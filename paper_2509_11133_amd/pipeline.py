@@ -244,6 +244,28 @@ def solve(coord, tetra, conn, sysm, kappa, prm, mode=SOLVE_FP64_PCG, tol=1e-10, 
     return lam, U, stats
 
 
+def solve_multi(coord, tetra, conn, sysm, kappa, prms, rhs=None, tol=1e-10, max_iter=200000, allow_noconv=False):
+    """Several loads on one face system (FP64 lockstep PCG): prms = one params per load (same c
+    and kappa), rhs = [nk, nF] tensor or None (formed matrix-free).  Returns (lambda [nk, nF],
+    U [nk, 4, nE], list of stats)."""
+    dev = coord.device
+    nC, nE, nF = coord.shape[1], tetra.shape[1], conn["nF"]
+    nk = len(prms)
+    work = B.workspace(B.lib().phfem_solve_multi_workspace(nE, nF, nk), dev)
+    lam = torch.empty((nk, nF), dtype=F64, device=dev)
+    U = torch.empty((nk, 4, nE), dtype=F64, device=dev)
+    st = (SolveStats * nk)()
+    rc = B.phfem_solve_multi(nC, coord, nE, tetra, nF, conn["faces"], conn["tet2face"], conn["sigma"],
+                             conn["face2tet"], kappa, prms, sysm["rowptr"], sysm["col"], sysm["val"], sysm["diag"],
+                             None if rhs is None else rhs.contiguous(), tol, max_iter, work, lam, U, st, check=False)
+    stats = [s_.as_dict() for s_ in st]
+    for s_ in stats:
+        s_["converged"] = rc == OK and s_["rel_res"] <= tol
+    if rc != OK and not (rc == ENOCONV and allow_noconv):
+        raise PhfemError(rc, B.lib().phfem_last_error().decode())
+    return lam, U, stats
+
+
 def grad(coord, tetra, conn, sysm, kappa, prm, U, lam, dJdU, mode=SOLVE_FP64_PCG, tol=1e-10, inner_tol=0.9,
          max_iter=200000, want_coord=True, allow_noconv=False):
     """Adjoint gradient (a10): (dJ/dlog kappa [nE], dJ/dX [3, nC], stats).  With allow_noconv an
