@@ -844,95 +844,87 @@ int orc_faces(int64_t nC, int64_t nE, const int32_t* tet, int32_t* faces, int32_
   return ORC_OK;
 }
 
-// RedRefine + refineFaces (Listing 5), literally: 7 new points per tet (centroid, then the
-// six edge midpoints), a coordinate-keyed stable unique appended to Coord, the centroid ids
-// C and the remaining new ids R assigned to the edges in U order, then the 12 children at
-// rows T and nE + 11(T-1) + (c-1), and the 1 -> 4 split of the boundary faces.
-// Xo: [3][nC + nEd + nE] (stride = new nC); To: [4][12 nE]; dbo/nbo: [3][4 n].
+// Red refinement (Section 3.4).  Every tet gets seven new nodes, its centroid
+// (((x_I + x_J) + x_K) + x_L) / 4 and the midpoints (x_a + x_b) / 2 of its six edges; a
+// midpoint is shared by all tets holding the edge, a centroid belongs to one tet.  New nodes
+// are numbered after the old ones in the order they first occur when the tets are visited in
+// order, each tet listing its centroid and then the midpoints of its edges IJ, IK, IL, JK, JL,
+// KL (the coordinate-keyed stable unique of the section's construction; in a conforming mesh a
+// midpoint is identified by its edge's node pair, a centroid by its tet).  Each tet becomes 12:
+// four corner tets (a vertex and the midpoints of its three edges) and the eight tets joining
+// the centroid to the faces of the inner octahedron, in the vertex order of CHILD below; child
+// 1 keeps row t, children 2..12 go to rows nE + 11 t + (c - 2).  A boundary triangle
+// [n1 n2 n3] splits into its three corner triangles and the middle one (SPLIT below), keeping
+// its orientation; triangle 1 keeps row f, 2..4 go to rows n + 3 f + (c - 2).
+// Xo: [3][nC + nEd + nE] (stride = the new node count); To: [4][12 nE]; dbo/nbo: [3][4 n].
+namespace {
+// point labels: 0..3 = vertices I J K L, 4 + j = midpoint of local edge j (IJ IK IL JK JL KL),
+// 10 = centroid
+const int CHILD[12][4] = {{0, 4, 5, 6}, {1, 7, 4, 8}, {2, 5, 7, 9}, {3, 9, 8, 6},   // corner tets
+                          {4, 5, 6, 10}, {7, 4, 8, 10}, {5, 7, 9, 10}, {9, 8, 6, 10},
+                          {4, 7, 5, 10}, {5, 9, 6, 10}, {4, 6, 8, 10}, {9, 7, 8, 10}};  // octahedron
+// triangle labels: 0..2 = n1 n2 n3, 3 = mid(n1 n2), 4 = mid(n2 n3), 5 = mid(n1 n3)
+const int SPLIT[4][3] = {{0, 3, 5}, {1, 4, 3}, {2, 5, 4}, {3, 4, 5}};
+}  // namespace
+
 int orc_refine(int64_t nC, const double* X, int64_t nE, const int32_t* tet, int64_t nDb, const int32_t* db,
                int64_t nNb, const int32_t* nb, double* Xo, int32_t* To, int32_t* dbo, int32_t* nbo, int64_t* nC_out) {
   int rc = check_mesh(nC, nE, tet);
   if (rc) return rc;
-  EdgeData E;
-  build_edges(nE, tet, E);
-  int64_t nEd = (int64_t)E.a.size();
-  typedef std::array<double, 3> P3;
-  std::map<P3, int64_t> seen;
-  std::vector<P3> newpts;
-  std::vector<int64_t> centroid_id(nE);
-  std::vector<char> is_centroid;
   auto coord = [&](int v, int d) { return X[d * nC + v]; };
+  // first-appearance numbering of the new nodes and their coordinates
+  std::map<std::pair<int, int>, int64_t> mid_id;  // edge (sorted node pair) -> new node id
+  std::vector<int64_t> cent_id(nE);
+  std::vector<std::array<double, 3>> newpts;
+  std::vector<std::array<int64_t, 11>> label(nE);  // per tet: node id of every point label
   for (int64_t t = 0; t < nE; ++t) {
     int v[4];
     for (int i = 0; i < 4; ++i) v[i] = tet_node(tet, nE, t, i);
-    P3 pts[7];
-    for (int d = 0; d < 3; ++d)
-      pts[0][d] = (((coord(v[0], d) + coord(v[1], d)) + coord(v[2], d)) + coord(v[3], d)) / 4.0;
-    for (int j = 0; j < 6; ++j)
-      for (int d = 0; d < 3; ++d) pts[1 + j][d] = (coord(v[EDGE_V[j][0]], d) + coord(v[EDGE_V[j][1]], d)) / 2.0;
-    for (int m = 0; m < 7; ++m) {
-      auto it = seen.find(pts[m]);
-      int64_t id;
-      if (it == seen.end()) {
-        id = nC + (int64_t)newpts.size();
-        seen[pts[m]] = id;
-        newpts.push_back(pts[m]);
-        is_centroid.push_back(m == 0);
-      } else {
-        id = it->second;
-        if (m == 0) return fail(ORC_EDEGEN, "centroid coincides with another new point");
+    std::array<double, 3> ct;
+    for (int d = 0; d < 3; ++d) ct[d] = (((coord(v[0], d) + coord(v[1], d)) + coord(v[2], d)) + coord(v[3], d)) / 4.0;
+    cent_id[t] = nC + (int64_t)newpts.size();
+    newpts.push_back(ct);
+    for (int i = 0; i < 4; ++i) label[t][i] = v[i];
+    label[t][10] = cent_id[t];
+    for (int j = 0; j < 6; ++j) {
+      const int a = v[EDGE_V[j][0]], b = v[EDGE_V[j][1]];
+      const std::pair<int, int> key(std::min(a, b), std::max(a, b));
+      auto it = mid_id.find(key);
+      if (it == mid_id.end()) {
+        std::array<double, 3> m;
+        for (int d = 0; d < 3; ++d) m[d] = (coord(a, d) + coord(b, d)) / 2.0;
+        it = mid_id.emplace(key, nC + (int64_t)newpts.size()).first;
+        newpts.push_back(m);
       }
-      if (m == 0) centroid_id[t] = id;
+      label[t][4 + j] = it->second;
     }
   }
-  // C = find(ismember(Coord, Ct)) must list the centroids in tet order; R = the rest.
-  std::vector<int64_t> Rids;
-  for (size_t m = 0; m < newpts.size(); ++m)
-    if (!is_centroid[m]) Rids.push_back(nC + (int64_t)m);
-  for (int64_t t = 1; t < nE; ++t)
-    if (centroid_id[t] <= centroid_id[t - 1]) return fail(ORC_EDEGEN, "centroids out of tet order");
-  if ((int64_t)Rids.size() != nEd) return fail(ORC_EDEGEN, "midpoints do not match edges");
-  // the midpoint of edge e must be the point given the id R(e)
-  for (int64_t e = 0; e < nEd; ++e) {
-    P3 m;
-    for (int d = 0; d < 3; ++d) m[d] = (coord(E.a[e], d) + coord(E.b[e], d)) / 2.0;
-    if (seen[m] != Rids[e]) return fail(ORC_EDEGEN, "midpoint numbering differs from edge order");
-  }
-  int64_t nCo = nC + (int64_t)newpts.size();
+  const int64_t nCo = nC + (int64_t)newpts.size();
   for (int d = 0; d < 3; ++d) {
     for (int64_t v = 0; v < nC; ++v) Xo[d * nCo + v] = X[d * nC + v];
     for (size_t m = 0; m < newpts.size(); ++m) Xo[d * nCo + nC + (int64_t)m] = newpts[m][d];
   }
-  auto A = [&](int p, int q) -> int { return (int)Rids[edge_of(E, p, q)]; };
-  int64_t nEo = 12 * nE;
-  for (int64_t t = 0; t < nE; ++t) {
-    int I = tet_node(tet, nE, t, 0), J = tet_node(tet, nE, t, 1), K = tet_node(tet, nE, t, 2),
-        L = tet_node(tet, nE, t, 3);
-    int C = (int)centroid_id[t];
-    int ch[12][4] = {{I, A(I, J), A(I, K), A(I, L)},       {J, A(K, J), A(I, J), A(J, L)},
-                     {K, A(I, K), A(J, K), A(K, L)},       {L, A(K, L), A(L, J), A(I, L)},
-                     {A(I, J), A(I, K), A(I, L), C},       {A(K, J), A(I, J), A(J, L), C},
-                     {A(I, K), A(J, K), A(K, L), C},       {A(K, L), A(L, J), A(I, L), C},
-                     {A(I, J), A(K, J), A(I, K), C},       {A(I, K), A(L, K), A(I, L), C},
-                     {A(I, J), A(I, L), A(J, L), C},       {A(K, L), A(K, J), A(L, J), C}};
+  const int64_t nEo = 12 * nE;
+  for (int64_t t = 0; t < nE; ++t)
     for (int c = 0; c < 12; ++c) {
-      int64_t row = (c == 0) ? t : nE + 11 * t + (c - 1);
-      for (int i = 0; i < 4; ++i) To[i * nEo + row] = ch[c][i];
+      const int64_t row = c == 0 ? t : nE + 11 * t + (c - 1);
+      for (int i = 0; i < 4; ++i) To[i * nEo + row] = (int32_t)label[t][CHILD[c][i]];
     }
-  }
   auto refine_faces = [&](int64_t n, const int32_t* Fin, int32_t* Fout) -> int {
-    int64_t n4 = 4 * n;
+    const int64_t n4 = 4 * n;
     for (int64_t f = 0; f < n; ++f) {
-      int n1 = Fin[f], n2 = Fin[n + f], n3 = Fin[2 * n + f];
-      if (edge_of(E, n1, n2) < 0 || edge_of(E, n2, n3) < 0 || edge_of(E, n1, n3) < 0)
-        return fail(ORC_EINVAL, "boundary face is not a mesh face");
-      int rows4[4][3] = {{n1, A(n1, n2), A(n1, n3)},
-                         {n2, A(n2, n3), A(n1, n2)},
-                         {n3, A(n1, n3), A(n2, n3)},
-                         {A(n1, n2), A(n2, n3), A(n1, n3)}};
+      const int c3[3] = {Fin[f], Fin[n + f], Fin[2 * n + f]};
+      int64_t lab[6] = {c3[0], c3[1], c3[2], -1, -1, -1};
+      const int ends[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+      for (int m = 0; m < 3; ++m) {
+        const int a = c3[ends[m][0]], b = c3[ends[m][1]];
+        auto it = mid_id.find(std::pair<int, int>(std::min(a, b), std::max(a, b)));
+        if (it == mid_id.end()) return fail(ORC_EINVAL, "boundary face is not a mesh face");
+        lab[3 + m] = it->second;
+      }
       for (int c = 0; c < 4; ++c) {
-        int64_t row = (c == 0) ? f : n + 3 * f + (c - 1);
-        for (int m = 0; m < 3; ++m) Fout[m * n4 + row] = rows4[c][m];
+        const int64_t row = c == 0 ? f : n + 3 * f + (c - 1);
+        for (int m = 0; m < 3; ++m) Fout[m * n4 + row] = (int32_t)lab[SPLIT[c][m]];
       }
     }
     return ORC_OK;

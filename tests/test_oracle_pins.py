@@ -455,6 +455,32 @@ def test_table4_convergence_orders():
         assert abs(oy - tab[i, 2]) <= 0.15 and abs(ol - tab[i, 4]) <= 0.15, (i, oy, ol)
 
 
+def test_refine_numbering_equals_coordinate_unique():
+    """The oracle numbers new nodes combinatorially (first appearance of each tet's centroid and
+    edge midpoints); the construction of Section 3.4 does it by a stable unique over the
+    coordinates of those seven points per tet.  Restated here with numpy on the coordinates: the
+    same new coordinates in the same order, on Kuhn and Fichera meshes (levels 1-2) and a
+    jittered one (the children's vertex lists are pinned by the worked example and brute force)."""
+    cases = [(M.kuhn_cube(), 2), (M.fichera(), 1)]
+    Xk, Tk = M.kuhn_cube()
+    Xk, Tk, _, _ = O.refine(Xk, Tk)
+    cases.append(((M.jitter_unit_cube(Xk, Tk, 0.1, seed=4), Tk), 1))
+    for (X, T), L in cases:
+        X, T = np.asarray(X, float), np.asarray(T, np.int32)
+        for _ in range(L):
+            nC = X.shape[1]
+            P = X[:, T]  # 3 x 4 x nE
+            pts = [((P[:, 0] + P[:, 1]) + P[:, 2] + P[:, 3]) / 4.0]
+            pts += [(P[:, a] + P[:, b]) / 2.0 for a, b in [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]]
+            seq = np.stack(pts, axis=2).reshape(3, -1).T  # (7 nE) x 3, tet-major
+            _, first = np.unique(seq, axis=0, return_index=True)
+            order = np.sort(first)
+            X2, T2, _, _ = O.refine(X, T)
+            assert np.array_equal(X2[:, nC:].T, seq[order])
+            assert X2.shape[1] == nC + len(order)
+            X, T = X2, T2
+
+
 def test_table4_values_below_best_approximation():
     """Why Table 4's printed Y-norm values are not reproduced: under the norm as stated (the
     broken H1 seminorm plus h^-2 L2), no function that is linear on each tet comes closer to
