@@ -103,7 +103,8 @@ typedef struct {
 enum {
   PHFEM_CONNECT_EDGES = 1,      /* Nodes-to-Edge numbering (NumEdges, Listing 2) */
   PHFEM_CONNECT_FACES = 2,      /* Edges-to-Tet neighbours + Faces (Listings 3-4, fullFaces) */
-  PHFEM_CONNECT_NODES2EDGE = 4  /* also export Nodes2Edge (upper triangle) as CSR */
+  PHFEM_CONNECT_NODES2EDGE = 4, /* also export Nodes2Edge (upper triangle) as CSR */
+  PHFEM_CONNECT_RADIX = 8       /* take the radix-sort path (same outputs; for comparison) */
 };
 
 size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags);
@@ -128,9 +129,12 @@ size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags);
  *   face2tet[2][nF]      slot 4t+k of the owner, slot of the neighbour or -1; capacity 8 nE
  *   nbr[4][nE]           tet across local face k, -1 on the boundary (may be NULL)
  * counts (host int64[3]): nEd, nF, nB (boundary faces).  Face outputs may be NULL without
- * the FACES flag.  Synchronizes `stream` (counts are read back).  Numbering is by a stable
- * sort of the occurrence keys; a mesh of at most 256 tets without NODES2EDGE is connected in
- * one workgroup (each occurrence compared with the earlier ones), with identical outputs.
+ * the FACES flag.  Synchronizes `stream` (counts are read back).  Three paths, identical
+ * outputs: a mesh of at most 256 tets without NODES2EDGE is connected in one workgroup (each
+ * occurrence compared with the earlier ones); larger meshes bucket the occurrences by their
+ * lowest node (counting sort) and resolve each bucket in LDS, falling back by themselves to
+ * a stable radix sort of the occurrence keys when a node is the lowest node of more than
+ * 8192 occurrences (or always, with PHFEM_CONNECT_RADIX).
  * Errors: EINVAL (nC, nE <= 0 or > 2^28 / 2^26, node out of range, repeated node in a tet),
  * EORIENT (a face held by two tets in the same orientation or by more than two tets). */
 int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, void* work, size_t work_bytes,

@@ -21,7 +21,7 @@ OK, EINVAL, EORIENT, EDEGEN, ESINGULAR, ENOCONV, EWORKSPACE, EHIP = range(8)
 FUN_ZERO, FUN_CONST, FUN_SIN3, FUN_LINEAR, FUN_X2Y2Z2, FUN_X2Y2Z2_LOAD = range(6)
 QUAD_FACE_CENTROID, QUAD_P1_INTERP = 0, 1
 FP64, MIXED = 0, 1
-CONNECT_EDGES, CONNECT_FACES, CONNECT_NODES2EDGE = 1, 2, 4
+CONNECT_EDGES, CONNECT_FACES, CONNECT_NODES2EDGE, CONNECT_RADIX = 1, 2, 4, 8
 SOLVE_FP64_PCG, SOLVE_FP32_PCG_FP64_IR = 0, 1
 
 EXPORTS = [

@@ -391,8 +391,413 @@ __global__ __launch_bounds__(SMT) void k_connect_small(int nC, int nE, const int
   }
 }
 
-// ---------------------------------------------------------------- workspace layout
-struct ConnWS {
+// ---------------------------------------------------------------- node buckets
+// The general path for meshes above SMALL_NE tets.  Equal keys share their lowest node (an
+// edge's smaller node, a face's smallest node), so the occurrences are bucketed by that node
+// with a counting sort (each workgroup aggregates its occurrences per node in an LDS hash
+// table, then takes one global atomic per distinct node), and each bucket -- a few dozen
+// occurrences in a mesh of bounded vertex degree -- is resolved in LDS by comparing every
+// occurrence with the rest of its bucket:
+//   edges: the first appearance is the least position among the bucket's occurrences with
+//          the same other node;
+//   faces: the first appearance is the least slot among the occurrences with the same edge
+//          opposite the lowest node; the other one is the neighbour.
+// The head flags then give per-tet counts, a scan gives the ids, and every output is written
+// in position order (tet-major, coalesced) instead of in a sort order.  The order of the
+// entries inside a bucket depends on atomics, but nothing read from a bucket does (minima,
+// counts, ranks), so the outputs are deterministic.  A bucket above BK_BIG occurrences (a
+// node in thousands of tets) sends the call to the radix-sort path below.
+constexpr int BK_T = 256;            // threads per workgroup
+constexpr int BK_LOGHS = 11;         // LDS hash slots per workgroup: 2048 > 6 BK_T occurrences
+constexpr int BK_HS = 1 << BK_LOGHS;
+constexpr uint32_t BK_EMPTY = 0xffffffffu;
+constexpr int BK_BPW = 32;           // buckets per workgroup in the resolve pass
+constexpr int BK_CAP = 4096;         // occurrences of those buckets staged in LDS
+constexpr int BK_BIG = 8192;         // largest bucket resolved here
+enum : int { DEV_BUCKET = 16 };      // internal: a bucket above BK_BIG occurrences
+static_assert(BK_HS > 6 * BK_T, "every probe sequence finds a free slot");
+static_assert(BK_BPW <= 255, "bucket index fits a byte");
+
+__device__ __forceinline__ bool tet_ok(const int v[4], int64_t nC) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ok &= v[i] >= 0 && v[i] < nC;
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) ok &= v[i] != v[j];
+  }
+  return ok;
+}
+
+// occurrence o of tet t: bucket node and entry.
+//   edges (o = j):  entry = other node << 32 | position 6t+j
+//   faces (o = k):  entry = opposite edge << 32 | (slot 4t+k) << 1 | parity of the tuple's node order
+template <bool FACES>
+__device__ __forceinline__ void bk_occ(int o, const int v[4], const int e[6], int64_t t, uint32_t& lo,
+                                       uint64_t& ent) {
+  if (!FACES) {
+    const uint32_t a = (uint32_t)v[ev0(o)], b = (uint32_t)v[ev1(o)];
+    lo = a < b ? a : b;
+    ent = ((uint64_t)(a < b ? b : a) << 32) | (uint32_t)(6 * t + o);
+  } else {
+    const int na = v[fv(o, 0)], nb_ = v[fv(o, 1)], nc = v[fv(o, 2)];
+    int oe;
+    if (na < nb_ && na < nc) {
+      lo = (uint32_t)na;
+      oe = e[eidx(fv(o, 1), fv(o, 2))];
+    } else if (nb_ < nc) {
+      lo = (uint32_t)nb_;
+      oe = e[eidx(fv(o, 0), fv(o, 2))];
+    } else {
+      lo = (uint32_t)nc;
+      oe = e[eidx(fv(o, 0), fv(o, 1))];
+    }
+    const uint32_t par = (uint32_t)(((na > nb_) + (na > nc) + (nb_ > nc)) & 1);
+    ent = ((uint64_t)(uint32_t)oe << 32) | ((uint32_t)(4 * t + o) << 1) | par;
+  }
+}
+
+// LDS hash slot of node `key` (linear probing; the table never fills)
+__device__ __forceinline__ int bk_slot(uint32_t* hk, uint32_t key) {
+  uint32_t h = (key * 2654435761u) >> (32 - BK_LOGHS);
+  for (;;) {
+    const uint32_t prev = atomicCAS(&hk[h], BK_EMPTY, key);
+    if (prev == BK_EMPTY || prev == key) return (int)h;
+    h = (h + 1) & (BK_HS - 1);
+  }
+}
+
+// bcnt[node] += occurrences in the node's bucket (tets with a bad node id are left out and
+// flagged)
+template <bool FACES>
+__global__ __launch_bounds__(BK_T) void k_bk_count(int64_t nE, int64_t nC, const int32_t* __restrict__ tet,
+                                                   uint32_t* __restrict__ bcnt, int* __restrict__ flags) {
+  constexpr int N = FACES ? 4 : 6;
+  __shared__ uint32_t hk[BK_HS], hc[BK_HS];
+  for (int i = threadIdx.x; i < BK_HS; i += BK_T) {
+    hk[i] = BK_EMPTY;
+    hc[i] = 0;
+  }
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  if (t < nE) {
+    int v[4], e[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+    if (tet_ok(v, nC)) {
+#pragma unroll
+      for (int o = 0; o < N; ++o) {
+        uint32_t lo;
+        uint64_t ent;
+        bk_occ<FACES>(o, v, e, t, lo, ent);
+        atomicAdd(&hc[bk_slot(hk, lo)], 1u);
+      }
+    } else {
+      atomicOr(flags, DEV_BADNODE);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < BK_HS; i += BK_T)
+    if (hk[i] != BK_EMPTY) atomicAdd(&bcnt[hk[i]], hc[i]);
+}
+
+// Entries into their buckets: bucket b spans [boff[b], boff[b+1]); each workgroup claims a
+// run per node it holds by decrementing bcnt (which ends at zero again).  A tet with a bad
+// node id has no entries; its positions are marked as their own heads so that the later
+// passes stay in bounds (the call then fails with the flag set by the count pass).
+template <bool FACES>
+__global__ __launch_bounds__(BK_T) void k_bk_fill(int64_t nE, int64_t nC, const int32_t* __restrict__ tet,
+                                                  const int32_t* __restrict__ t2e, const uint32_t* __restrict__ boff,
+                                                  uint32_t* __restrict__ bcnt, uint64_t* __restrict__ bent,
+                                                  int32_t* __restrict__ hp, int32_t* __restrict__ pp) {
+  constexpr int N = FACES ? 4 : 6;
+  __shared__ uint32_t hk[BK_HS], hc[BK_HS];
+  for (int i = threadIdx.x; i < BK_HS; i += BK_T) {
+    hk[i] = BK_EMPTY;
+    hc[i] = 0;
+  }
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  int slot[N];
+  uint32_t rk[N];
+  uint64_t ent[N];
+  bool ok = false;
+  if (t < nE) {
+    int v[4], e[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+    ok = tet_ok(v, nC);
+    if (ok) {
+      if (FACES) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) e[j] = t2e[j * nE + t];
+      }
+#pragma unroll
+      for (int o = 0; o < N; ++o) {
+        uint32_t lo;
+        bk_occ<FACES>(o, v, e, t, lo, ent[o]);
+        slot[o] = bk_slot(hk, lo);
+        rk[o] = atomicAdd(&hc[slot[o]], 1u);
+      }
+    } else {
+#pragma unroll
+      for (int o = 0; o < N; ++o) {
+        hp[N * t + o] = (int32_t)(N * t + o);
+        if (FACES) pp[N * t + o] = -1;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < BK_HS; i += BK_T) {
+    const uint32_t key = hk[i];
+    if (key != BK_EMPTY) {
+      const uint32_t c = hc[i];
+      const uint32_t old = atomicSub(&bcnt[key], c);
+      hc[i] = boff[key] + old - c;
+    }
+  }
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int o = 0; o < N; ++o) bent[hc[slot[o]] + rk[o]] = ent[o];
+  }
+}
+
+// One entry against its bucket B[0, m) (LDS or global), written at global bucket start g.
+//   edges: hp[pos] = least position with the same other node; SORTED also writes the
+//          bucket in ascending (other node, position) order to bsort and the head flags in
+//          that order to dfl (Nodes2Edge).
+//   faces: hp[slot] = least slot with the same opposite edge, pp[slot] = the other slot or
+//          -1; three occurrences, or two with the same parity, are flagged.
+template <bool FACES, bool SORTED>
+__device__ __forceinline__ void bk_resolve_one(uint64_t mine, const uint64_t* B, int m, int64_t g,
+                                               int32_t* __restrict__ hp, int32_t* __restrict__ pp,
+                                               uint64_t* __restrict__ bsort, uint32_t* __restrict__ dfl,
+                                               int* __restrict__ flags) {
+  const uint32_t key = (uint32_t)(mine >> 32), w = (uint32_t)mine;
+  if (!FACES) {
+    uint32_t hmin = w, rank = 0;
+#pragma unroll 4
+    for (int j = 0; j < m; ++j) {
+      const uint64_t o = B[j];
+      if ((uint32_t)(o >> 32) == key) hmin = min(hmin, (uint32_t)o);
+      if (SORTED) rank += o < mine ? 1u : 0u;
+    }
+    hp[w] = (int32_t)hmin;
+    if (SORTED) {
+      bsort[g + rank] = mine;
+      dfl[g + rank] = hmin == w ? 1u : 0u;
+    }
+  } else {
+    uint32_t hmin = w >> 1, cnt = 0, pw = BK_EMPTY;
+#pragma unroll 4
+    for (int j = 0; j < m; ++j) {
+      const uint64_t o = B[j];
+      if ((uint32_t)(o >> 32) == key) {
+        const uint32_t ow = (uint32_t)o;
+        ++cnt;
+        hmin = min(hmin, ow >> 1);
+        if (ow != w) pw = ow;
+      }
+    }
+    hp[w >> 1] = (int32_t)hmin;
+    pp[w >> 1] = cnt == 2 ? (int32_t)(pw >> 1) : -1;
+    if (cnt > 2 || (cnt == 2 && (pw & 1u) == (w & 1u))) atomicOr(flags, DEV_ORIENT);
+  }
+}
+
+// Buckets [b0, b0 + BK_BPW) per workgroup: staged in LDS when their entries fit BK_CAP, else
+// one bucket at a time from global memory; a bucket above BK_BIG is flagged DEV_BUCKET and
+// its entries are given in-bounds placeholders (own head, no partner, no Nodes2Edge entry).
+template <bool FACES, bool SORTED>
+__global__ __launch_bounds__(BK_T) void k_bk_resolve(int64_t nB, const uint32_t* __restrict__ boff,
+                                                     const uint64_t* __restrict__ bent, int32_t* __restrict__ hp,
+                                                     int32_t* __restrict__ pp, uint64_t* __restrict__ bsort,
+                                                     uint32_t* __restrict__ dfl, int* __restrict__ flags) {
+  __shared__ uint64_t E[BK_CAP];
+  __shared__ uint32_t bs[BK_BPW + 1];
+  __shared__ uint8_t lb[BK_CAP];
+  const int64_t b0 = (int64_t)blockIdx.x * BK_BPW;
+  const int nb = (int)min((int64_t)BK_BPW, nB - b0);
+  const uint32_t s0 = boff[b0], total = boff[b0 + nb] - s0;
+  if (total <= (uint32_t)BK_CAP) {
+    for (int i = threadIdx.x; i <= nb; i += BK_T) bs[i] = boff[b0 + i] - s0;
+    for (uint32_t e = threadIdx.x; e < total; e += BK_T) E[e] = bent[s0 + e];
+    __syncthreads();
+    if ((int)threadIdx.x < nb)
+      for (uint32_t e = bs[threadIdx.x]; e < bs[threadIdx.x + 1]; ++e) lb[e] = (uint8_t)threadIdx.x;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < total; e += BK_T) {
+      const int k = lb[e];
+      const uint32_t j0 = bs[k];
+      bk_resolve_one<FACES, SORTED>(E[e], E + j0, (int)(bs[k + 1] - j0), (int64_t)s0 + j0, hp, pp, bsort, dfl,
+                                    flags);
+    }
+  } else {
+    for (int k = 0; k < nb; ++k) {
+      const uint32_t j0 = boff[b0 + k];
+      const int m = (int)(boff[b0 + k + 1] - j0);
+      if (m > BK_BIG) {
+        if (threadIdx.x == 0) atomicOr(flags, DEV_BUCKET);
+        for (int e = threadIdx.x; e < m; e += BK_T) {
+          const uint64_t mine = bent[j0 + e];
+          const uint32_t w = (uint32_t)mine;
+          if (!FACES) {
+            hp[w] = (int32_t)w;
+            if (SORTED) {
+              bsort[j0 + e] = mine;
+              dfl[j0 + e] = 0u;
+            }
+          } else {
+            hp[w >> 1] = (int32_t)(w >> 1);
+            pp[w >> 1] = -1;
+          }
+        }
+        continue;
+      }
+      for (int e = threadIdx.x; e < m; e += BK_T)
+        bk_resolve_one<FACES, SORTED>(bent[j0 + e], bent + j0, m, (int64_t)j0, hp, pp, bsort, dfl, flags);
+    }
+  }
+}
+
+// cnt[t] = first appearances among the N positions of tet t (cnt[nE] = 0)
+template <int N>
+__global__ __launch_bounds__(BK_T) void k_bk_heads(int64_t nE, const int32_t* __restrict__ hp,
+                                                   uint32_t* __restrict__ cnt) {
+  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  if (t > nE) return;
+  uint32_t c = 0;
+  if (t < nE) {
+#pragma unroll
+    for (int o = 0; o < N; ++o) c += hp[N * t + o] == (int32_t)(N * t + o) ? 1u : 0u;
+  }
+  cnt[t] = c;
+}
+
+// id of the first appearance at position h = N th + oh: prefix of th + heads of th before oh
+template <int N>
+__device__ __forceinline__ int32_t bk_head_id(int32_t h, const int32_t* __restrict__ hp,
+                                              const uint32_t* __restrict__ pre) {
+  const int64_t th = h / N;
+  const int oh = (int)(h - N * th);
+  uint32_t id = pre[th];
+  for (int i = 0; i < oh; ++i) id += hp[N * th + i] == (int32_t)(N * th + i) ? 1u : 0u;
+  return (int32_t)id;
+}
+
+// edge outputs in tet order; pre = exclusive scan of k_bk_heads<6>, *nEdp its total
+__global__ __launch_bounds__(BK_T) void k_bk_edge_assign(int64_t nE, const int32_t* __restrict__ tet,
+                                                         const int32_t* __restrict__ hp,
+                                                         const uint32_t* __restrict__ pre,
+                                                         const uint32_t* __restrict__ nEdp,
+                                                         int32_t* __restrict__ tet2edge, int32_t* __restrict__ edges,
+                                                         int32_t* __restrict__ eft,
+                                                         int32_t* __restrict__ tet_edge_prefix) {
+  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  if (t >= nE) return;
+  const int64_t nEd = *nEdp;
+  int v[4], h[6];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+  const int2* h2 = reinterpret_cast<const int2*>(hp + 6 * t);  // 24 t bytes: 8-byte aligned
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int2 x = h2[i];
+    h[2 * i] = x.x;
+    h[2 * i + 1] = x.y;
+  }
+  const uint32_t pt = pre[t];
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int32_t p = (int32_t)(6 * t + j);
+    int32_t id;
+    if (h[j] == p) {
+      id = (int32_t)(pt + r++);
+      const int a = v[ev0(j)], b = v[ev1(j)];
+      edges[id] = a < b ? a : b;
+      edges[nEd + id] = a < b ? b : a;
+      eft[id] = (int32_t)t;
+    } else {
+      id = bk_head_id<6>(h[j], hp, pre);
+    }
+    tet2edge[j * nE + t] = id;
+  }
+  tet_edge_prefix[t] = (int32_t)pt;
+}
+
+// face outputs in tet order; pre = exclusive scan of k_bk_heads<4>, *nFp its total
+__global__ __launch_bounds__(BK_T) void k_bk_face_assign(int64_t nE, const int32_t* __restrict__ tet,
+                                                         const int32_t* __restrict__ hp,
+                                                         const int32_t* __restrict__ pp,
+                                                         const uint32_t* __restrict__ pre,
+                                                         const uint32_t* __restrict__ nFp,
+                                                         int32_t* __restrict__ faces, int32_t* __restrict__ tet2face,
+                                                         int8_t* __restrict__ sigma, int32_t* __restrict__ face2tet,
+                                                         int32_t* __restrict__ nbr) {
+  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  if (t >= nE) return;
+  const int64_t nF = *nFp;
+  int v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+  const int4 h4 = reinterpret_cast<const int4*>(hp)[t], p4 = reinterpret_cast<const int4*>(pp)[t];
+  const int h[4] = {h4.x, h4.y, h4.z, h4.w}, pr[4] = {p4.x, p4.y, p4.z, p4.w};
+  const uint32_t pt = pre[t];
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int32_t q = (int32_t)(4 * t + k);
+    if (h[k] == q) {
+      const int32_t id = (int32_t)(pt + r++);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) faces[m * nF + id] = v[fv(k, m)];
+      face2tet[id] = q;
+      face2tet[nF + id] = pr[k];
+      tet2face[k * nE + t] = id;
+      sigma[k * nE + t] = 1;
+      if (nbr) nbr[k * nE + t] = pr[k] >= 0 ? (pr[k] >> 2) : -1;
+    } else {
+      tet2face[k * nE + t] = bk_head_id<4>(h[k], hp, pre);
+      sigma[k * nE + t] = -1;
+      if (nbr) nbr[k * nE + t] = h[k] >> 2;
+    }
+  }
+}
+
+// Nodes2Edge from the sorted buckets: u = exclusive scan of the head flags in sorted order
+// (the rank of the node pair among all distinct pairs, i.e. the CSR slot); *nup its total.
+__global__ __launch_bounds__(BK_T) void k_bk_n2e_fill(int64_t n, int64_t nE, const uint64_t* __restrict__ bsort,
+                                                      const uint32_t* __restrict__ u,
+                                                      const uint32_t* __restrict__ nup,
+                                                      const int32_t* __restrict__ tet2edge, int32_t* __restrict__ col,
+                                                      int32_t* __restrict__ eid) {
+  const int64_t s = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t us = u[s], un = s + 1 < n ? u[s + 1] : *nup;
+  if (un == us) return;
+  const uint64_t ent = bsort[s];
+  const uint32_t pos = (uint32_t)ent;
+  const int64_t t = pos / 6;
+  const int j = (int)(pos - 6 * t);
+  col[us] = (int32_t)(ent >> 32);
+  eid[us] = tet2edge[j * nE + t];
+}
+
+// row pointers: the CSR slot of each node's first entry (its bucket start), total at nC
+__global__ __launch_bounds__(BK_T) void k_bk_n2e_rows(int64_t nC, int64_t n, const uint32_t* __restrict__ boff,
+                                                      const uint32_t* __restrict__ u,
+                                                      const uint32_t* __restrict__ nup,
+                                                      int32_t* __restrict__ rowptr) {
+  const int64_t b = (int64_t)blockIdx.x * BK_T + threadIdx.x;
+  if (b > nC) return;
+  const uint32_t s = boff[b];
+  rowptr[b] = (int32_t)(s < n ? u[s] : *nup);
+}
+
+// ---------------------------------------------------------------- workspace layouts
+struct ConnWS {  // radix-sort path
   uint64_t *kA, *kB;
   int32_t *vA, *vB;
   uint8_t* first;
@@ -419,12 +824,7 @@ static void conn_layout(Arena& a, int64_t nC, int64_t nE, int32_t flags, ConnWS&
   w.sub = a.size();
 }
 
-}  // namespace ph
-
-using namespace ph;
-
-extern "C" size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags) {
-  if (nC <= 0 || nE <= 0) return 0;
+static size_t radix_workspace(int64_t nC, int64_t nE, int32_t flags) {
   Arena a;
   ConnWS w;
   conn_layout(a, nC, nE, flags, w);
@@ -434,41 +834,147 @@ extern "C" size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags)
   return w.sub + extra;
 }
 
-extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, void* work,
-                             size_t work_bytes, int32_t* edges, int32_t* tet2edge, int32_t* edge_first_tet,
-                             int32_t* tet_edge_prefix, int32_t* n2e_rowptr, int32_t* n2e_col, int32_t* n2e_edge,
-                             int32_t* faces, int32_t* tet2face, int8_t* sigma, int32_t* face2tet, int32_t* nbr,
-                             int64_t* counts, phfem_stream_t stream_) {
-  clear_error();
-  hipStream_t s = (hipStream_t)stream_;
-  if (nC <= 0 || nE <= 0) return err(PHFEM_EINVAL, "nC and nE must be positive");
-  if (nE > (int64_t(1) << 26) || nC > (int64_t(1) << 28)) return err(PHFEM_EINVAL, "mesh too large for int32 ids");
-  if (!tetra || !edges || !tet2edge || !edge_first_tet || !tet_edge_prefix || !counts)
-    return err(PHFEM_EINVAL, "null edge output");
-  const bool want_faces = flags & PHFEM_CONNECT_FACES, want_n2e = flags & PHFEM_CONNECT_NODES2EDGE;
-  if (want_faces && (!faces || !tet2face || !sigma || !face2tet)) return err(PHFEM_EINVAL, "null face output");
-  if (want_n2e && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "null Nodes2Edge output");
-  if (!work || work_bytes < phfem_connect_workspace(nC, nE, flags))
-    return err(PHFEM_EWORKSPACE, "connect workspace too small");
+struct BkWS {  // node-bucket path
+  uint32_t *bcnt, *boff;  // nC + 1 each
+  uint64_t* bent;         // bucket entries, 6 nE
+  uint64_t* bsort;        // sorted buckets (Nodes2Edge only)
+  uint32_t* dfl;          // head flags in sorted order, then CSR slots (Nodes2Edge only)
+  int32_t *hp, *pp;       // head position per position (6 nE); partner slot per face slot (4 nE)
+  uint32_t* cnt;          // nE + 1
+  int* dflags;
+  uint32_t* total;        // [0] nEd, [1] nF, [2] distinct node pairs
+  size_t sub;
+};
 
-  Arena a(work, work_bytes);
+static void bk_layout(Arena& a, int64_t nC, int64_t nE, int32_t flags, BkWS& w) {
+  const int64_t n = 6 * nE;
+  const bool n2e = flags & PHFEM_CONNECT_NODES2EDGE, faces = flags & PHFEM_CONNECT_FACES;
+  w.bcnt = a.take<uint32_t>(nC + 1);
+  w.boff = a.take<uint32_t>(nC + 1);
+  w.bent = a.take<uint64_t>(n);
+  w.bsort = n2e ? a.take<uint64_t>(n) : nullptr;
+  w.dfl = n2e ? a.take<uint32_t>(n) : nullptr;
+  w.hp = a.take<int32_t>(n);
+  w.pp = faces ? a.take<int32_t>(4 * nE) : nullptr;
+  w.cnt = a.take<uint32_t>(nE + 1);
+  w.dflags = a.take<int>(16);
+  w.total = a.take<uint32_t>(16);
+  w.sub = a.size();
+}
+
+static size_t bucket_workspace(int64_t nC, int64_t nE, int32_t flags) {
+  Arena a;
+  BkWS w;
+  bk_layout(a, nC, nE, flags, w);
+  size_t extra = scan_workspace(nC + 1);
+  extra = std::max(extra, scan_workspace(nE + 1));
+  if (flags & PHFEM_CONNECT_NODES2EDGE) extra = std::max(extra, scan_workspace(6 * nE));
+  return w.sub + extra;
+}
+
+// counts[0..2] from the device totals and flags; one readback.  *redo: a bucket was too large
+// for the bucket path (nothing else went wrong), so the caller runs the radix path instead.
+static int bk_finish(const BkWS& w, int64_t nE, bool faces, int64_t* counts, bool* redo, hipStream_t s) {
+  uint32_t tot[2] = {0, 0};
+  int hf = 0;
+  PH_HIP(hipMemcpyAsync(tot, w.total, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipMemcpyAsync(&hf, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+  PH_HIP(hipStreamSynchronize(s));
+  if (hf & ~DEV_BUCKET) return dev_flags_to_status(hf & ~DEV_BUCKET);
+  if (hf & DEV_BUCKET) {
+    *redo = true;
+    return PHFEM_OK;
+  }
+  counts[0] = tot[0];
+  counts[1] = faces ? tot[1] : 0;
+  counts[2] = faces ? 2 * (int64_t)tot[1] - 4 * nE : 0;  // 4 nE = 2 nI + nB and nF = nI + nB
+  return PHFEM_OK;
+}
+
+static int connect_bucket(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, Arena& a, int32_t* edges,
+                          int32_t* tet2edge, int32_t* edge_first_tet, int32_t* tet_edge_prefix, int32_t* n2e_rowptr,
+                          int32_t* n2e_col, int32_t* n2e_edge, int32_t* faces, int32_t* tet2face, int8_t* sigma,
+                          int32_t* face2tet, int32_t* nbr, int64_t* counts, bool* redo, hipStream_t s) {
+  const bool want_faces = flags & PHFEM_CONNECT_FACES, want_n2e = flags & PHFEM_CONNECT_NODES2EDGE;
+  BkWS w;
+  bk_layout(a, nC, nE, flags, w);
+  const size_t sub = w.sub;
+  const int64_t n6 = 6 * nE, n4 = 4 * nE;
+  const unsigned gt = grid_for(nE, BK_T), gb = grid_for(nC, BK_BPW);
+  PH_HIP(hipMemsetAsync(w.dflags, 0, sizeof(int), s));
+  PH_HIP(hipMemsetAsync(w.bcnt, 0, sizeof(uint32_t) * (nC + 1), s));
+
+  // ---- edges, bucketed by their smaller node
+  PH_LAUNCH_B("bk_count", 16.0 * nE, k_bk_count<false>, gt, BK_T, 0, s, nE, nC, tetra, w.bcnt, w.dflags);
+  if (want_n2e) {  // Nodes2Edge indexes rows by node id: stop before any pass that would
+    int hf = 0;
+    PH_HIP(hipMemcpyAsync(&hf, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (hf) return dev_flags_to_status(hf);
+  }
+  a.off = sub;
+  int rc = scan_exclusive(w.bcnt, w.boff, nC + 1, nullptr, a, s);
+  if (rc) return rc;
+  PH_LAUNCH_B("bk_fill", 16.0 * nE + 8.0 * n6, k_bk_fill<false>, gt, BK_T, 0, s, nE, nC, tetra, nullptr,
+              (const uint32_t*)w.boff, w.bcnt, w.bent, w.hp, nullptr);
+  if (want_n2e)
+    PH_LAUNCH_B("bk_resolve", 24.0 * n6, (k_bk_resolve<false, true>), gb, BK_T, 0, s, nC, (const uint32_t*)w.boff,
+                (const uint64_t*)w.bent, w.hp, nullptr, w.bsort, w.dfl, w.dflags);
+  else
+    PH_LAUNCH_B("bk_resolve", 12.0 * n6, (k_bk_resolve<false, false>), gb, BK_T, 0, s, nC, (const uint32_t*)w.boff,
+                (const uint64_t*)w.bent, w.hp, nullptr, nullptr, nullptr, w.dflags);
+  PH_LAUNCH_B("bk_heads", 4.0 * n6 + 4.0 * nE, k_bk_heads<6>, grid_for(nE + 1, BK_T), BK_T, 0, s, nE,
+              (const int32_t*)w.hp, w.cnt);
+  a.off = sub;
+  rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total, a, s);
+  if (rc) return rc;
+  // unique edges ~ 1.2 nE on a tet mesh: 12 bytes each (node pair, first tet)
+  PH_LAUNCH_B("edge_assign", 16.0 * nE + 4.0 * n6 + 4.0 * nE + 4.0 * n6 + 4.0 * nE + 12.0 * 1.2 * nE,
+              k_bk_edge_assign, gt, BK_T, 0, s, nE, tetra, (const int32_t*)w.hp, (const uint32_t*)w.cnt,
+              (const uint32_t*)w.total, tet2edge, edges, edge_first_tet, tet_edge_prefix);
+  if (want_n2e) {
+    a.off = sub;
+    rc = scan_exclusive(w.dfl, w.dfl, n6, w.total + 2, a, s);  // in place: head flag -> CSR slot
+    if (rc) return rc;
+    PH_LAUNCH("n2e_fill", k_bk_n2e_fill, grid_for(n6, BK_T), BK_T, 0, s, n6, nE, (const uint64_t*)w.bsort,
+              (const uint32_t*)w.dfl, (const uint32_t*)(w.total + 2), (const int32_t*)tet2edge, n2e_col, n2e_edge);
+    PH_LAUNCH("n2e_rows", k_bk_n2e_rows, grid_for(nC + 1, BK_T), BK_T, 0, s, nC, n6, (const uint32_t*)w.boff,
+              (const uint32_t*)w.dfl, (const uint32_t*)(w.total + 2), n2e_rowptr);
+  }
+  if (!want_faces) return bk_finish(w, nE, false, counts, redo, s);
+
+  // ---- faces, bucketed by their smallest node (bcnt is back at zero after the fill)
+  PH_LAUNCH_B("bk_count", 16.0 * nE, k_bk_count<true>, gt, BK_T, 0, s, nE, nC, tetra, w.bcnt, w.dflags);
+  a.off = sub;
+  rc = scan_exclusive(w.bcnt, w.boff, nC + 1, nullptr, a, s);
+  if (rc) return rc;
+  PH_LAUNCH_B("bk_fill", 40.0 * nE + 8.0 * n4, k_bk_fill<true>, gt, BK_T, 0, s, nE, nC, tetra,
+              (const int32_t*)tet2edge, (const uint32_t*)w.boff, w.bcnt, w.bent, w.hp, w.pp);
+  PH_LAUNCH_B("bk_resolve", 16.0 * n4, (k_bk_resolve<true, false>), gb, BK_T, 0, s, nC, (const uint32_t*)w.boff,
+              (const uint64_t*)w.bent, w.hp, w.pp, nullptr, nullptr, w.dflags);
+  PH_LAUNCH_B("bk_heads", 4.0 * n4 + 4.0 * nE, k_bk_heads<4>, grid_for(nE + 1, BK_T), BK_T, 0, s, nE,
+              (const int32_t*)w.hp, w.cnt);
+  a.off = sub;
+  rc = scan_exclusive(w.cnt, w.cnt, nE + 1, w.total + 1, a, s);
+  if (rc) return rc;
+  // unique faces ~ 2 nE: 20 bytes each (node triple, two slots)
+  PH_LAUNCH_B("face_assign", 16.0 * nE + 8.0 * n4 + 4.0 * nE + 9.0 * n4 + 20.0 * 2 * nE, k_bk_face_assign, gt, BK_T,
+              0, s, nE, tetra, (const int32_t*)w.hp, (const int32_t*)w.pp, (const uint32_t*)w.cnt,
+              (const uint32_t*)(w.total + 1), faces, tet2face, sigma, face2tet, nbr);
+  return bk_finish(w, nE, true, counts, redo, s);
+}
+
+// The radix-sort path: stable LSD sort of the occurrence keys (node pair; lowest node and
+// opposite edge), segment heads, per-tet counts and a scan give the same numbering.
+static int connect_radix(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, Arena& a, int32_t* edges,
+                         int32_t* tet2edge, int32_t* edge_first_tet, int32_t* tet_edge_prefix, int32_t* n2e_rowptr,
+                         int32_t* n2e_col, int32_t* n2e_edge, int32_t* faces, int32_t* tet2face, int8_t* sigma,
+                         int32_t* face2tet, int32_t* nbr, int64_t* counts, hipStream_t s) {
+  const bool want_faces = flags & PHFEM_CONNECT_FACES, want_n2e = flags & PHFEM_CONNECT_NODES2EDGE;
   ConnWS w;
   conn_layout(a, nC, nE, flags, w);
   const size_t sub = w.sub;
   const int64_t n6 = 6 * nE, n4 = 4 * nE;
-  if (nE <= SMALL_NE && !want_n2e) {
-    PH_LAUNCH_B("connect_small", 16.0 * nE + 36.0 * nE + 3.6 * nE * 4 + (want_faces ? 26.0 * n4 : 0.0), k_connect_small,
-                1, SMT, 0, s, (int)nC, (int)nE, tetra, want_faces ? 1 : 0, edges, tet2edge, edge_first_tet,
-                tet_edge_prefix, faces, tet2face, sigma, face2tet, nbr, w.total);
-    uint32_t h3[3] = {0, 0, 0};
-    PH_HIP(hipMemcpyAsync(h3, w.total, sizeof(h3), hipMemcpyDeviceToHost, s));
-    PH_HIP(hipStreamSynchronize(s));
-    if (h3[2]) return dev_flags_to_status((int)h3[2]);
-    counts[0] = h3[0];
-    counts[1] = want_faces ? h3[1] : 0;
-    counts[2] = want_faces ? 2 * (int64_t)h3[1] - 4 * nE : 0;
-    return PHFEM_OK;
-  }
   const int nb = bits_for(nC);
   PH_HIP(hipMemsetAsync(w.dflags, 0, sizeof(int), s));
 
@@ -565,4 +1071,58 @@ extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32
   counts[1] = nF;
   counts[2] = 2 * nF - 4 * nE;  // 4 nE = 2 nI + nB and nF = nI + nB
   return PHFEM_OK;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" size_t phfem_connect_workspace(int64_t nC, int64_t nE, int32_t flags) {
+  if (nC <= 0 || nE <= 0) return 0;
+  return std::max(radix_workspace(nC, nE, flags), bucket_workspace(nC, nE, flags));
+}
+
+extern "C" int phfem_connect(int64_t nC, int64_t nE, const int32_t* tetra, int32_t flags, void* work,
+                             size_t work_bytes, int32_t* edges, int32_t* tet2edge, int32_t* edge_first_tet,
+                             int32_t* tet_edge_prefix, int32_t* n2e_rowptr, int32_t* n2e_col, int32_t* n2e_edge,
+                             int32_t* faces, int32_t* tet2face, int8_t* sigma, int32_t* face2tet, int32_t* nbr,
+                             int64_t* counts, phfem_stream_t stream_) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream_;
+  if (nC <= 0 || nE <= 0) return err(PHFEM_EINVAL, "nC and nE must be positive");
+  if (nE > (int64_t(1) << 26) || nC > (int64_t(1) << 28)) return err(PHFEM_EINVAL, "mesh too large for int32 ids");
+  if (!tetra || !edges || !tet2edge || !edge_first_tet || !tet_edge_prefix || !counts)
+    return err(PHFEM_EINVAL, "null edge output");
+  const bool want_faces = flags & PHFEM_CONNECT_FACES, want_n2e = flags & PHFEM_CONNECT_NODES2EDGE;
+  if (want_faces && (!faces || !tet2face || !sigma || !face2tet)) return err(PHFEM_EINVAL, "null face output");
+  if (want_n2e && (!n2e_rowptr || !n2e_col || !n2e_edge)) return err(PHFEM_EINVAL, "null Nodes2Edge output");
+  if (!work || work_bytes < phfem_connect_workspace(nC, nE, flags))
+    return err(PHFEM_EWORKSPACE, "connect workspace too small");
+
+  Arena a(work, work_bytes);
+  if (nE <= SMALL_NE && !want_n2e) {
+    ConnWS w;
+    conn_layout(a, nC, nE, flags, w);
+    PH_LAUNCH_B("connect_small", 16.0 * nE + 36.0 * nE + 3.6 * nE * 4 + (want_faces ? 26.0 * 4 * nE : 0.0),
+                k_connect_small, 1, SMT, 0, s, (int)nC, (int)nE, tetra, want_faces ? 1 : 0, edges, tet2edge,
+                edge_first_tet, tet_edge_prefix, faces, tet2face, sigma, face2tet, nbr, w.total);
+    uint32_t h3[3] = {0, 0, 0};
+    PH_HIP(hipMemcpyAsync(h3, w.total, sizeof(h3), hipMemcpyDeviceToHost, s));
+    PH_HIP(hipStreamSynchronize(s));
+    if (h3[2]) return dev_flags_to_status((int)h3[2]);
+    counts[0] = h3[0];
+    counts[1] = want_faces ? h3[1] : 0;
+    counts[2] = want_faces ? 2 * (int64_t)h3[1] - 4 * nE : 0;
+    return PHFEM_OK;
+  }
+  if (!(flags & PHFEM_CONNECT_RADIX)) {
+    bool redo = false;
+    const int rc = connect_bucket(nC, nE, tetra, flags, a, edges, tet2edge, edge_first_tet, tet_edge_prefix,
+                                  n2e_rowptr, n2e_col, n2e_edge, faces, tet2face, sigma, face2tet, nbr, counts,
+                                  &redo, s);
+    if (rc || !redo) return rc;
+    a.off = 0;
+  }
+  return connect_radix(nC, nE, tetra, flags, a, edges, tet2edge, edge_first_tet, tet_edge_prefix, n2e_rowptr,
+                       n2e_col, n2e_edge, faces, tet2face, sigma, face2tet, nbr, counts, s);
 }

@@ -10,17 +10,19 @@ import numpy as np
 import torch
 
 from . import _binding as B
-from ._binding import (CONNECT_EDGES, CONNECT_FACES, CONNECT_NODES2EDGE, ENOCONV, FP64, MIXED, OK,
-                       SOLVE_FP32_PCG_FP64_IR, SOLVE_FP64_PCG, PhfemError, SolveStats, params)
+from ._binding import (CONNECT_EDGES, CONNECT_FACES, CONNECT_NODES2EDGE, CONNECT_RADIX, ENOCONV, FP64, MIXED,
+                       OK, SOLVE_FP32_PCG_FP64_IR, SOLVE_FP64_PCG, PhfemError, SolveStats, params)
 
 I32, F64 = torch.int32, torch.float64
 
 
-def connect(tetra, nC, faces=True, n2e=False):
-    """Edges (+ Nodes2Edge CSR) and, with faces=True, the face numbering (a1-a3)."""
+def connect(tetra, nC, faces=True, n2e=False, radix=False):
+    """Edges (+ Nodes2Edge CSR) and, with faces=True, the face numbering (a1-a3).
+    radix=True takes the library's radix-sort path (same outputs)."""
     dev = tetra.device
     nE = tetra.shape[1]
-    flags = CONNECT_EDGES | (CONNECT_FACES if faces else 0) | (CONNECT_NODES2EDGE if n2e else 0)
+    flags = (CONNECT_EDGES | (CONNECT_FACES if faces else 0) | (CONNECT_NODES2EDGE if n2e else 0)
+             | (CONNECT_RADIX if radix else 0))
     work = B.workspace(B.lib().phfem_connect_workspace(nC, nE, flags), dev)
     e = torch.empty(12 * nE, dtype=I32, device=dev)
     t2e = torch.empty((6, nE), dtype=I32, device=dev)
