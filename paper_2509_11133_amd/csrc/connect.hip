@@ -412,7 +412,7 @@ constexpr int BK_LOGHS = 11;         // LDS hash slots per workgroup: 2048 > 6 B
 constexpr int BK_HS = 1 << BK_LOGHS;
 constexpr uint32_t BK_EMPTY = 0xffffffffu;
 constexpr int BK_BPW = 32;           // buckets per workgroup in the resolve pass
-constexpr int BK_CAP = 4096;         // occurrences of those buckets staged in LDS
+constexpr int BK_CAP = 2048;         // occurrences of those buckets staged in LDS
 constexpr int BK_BIG = 8192;         // largest bucket resolved here
 enum : int { DEV_BUCKET = 16 };      // internal: a bucket above BK_BIG occurrences
 static_assert(BK_HS > 6 * BK_T, "every probe sequence finds a free slot");
@@ -906,7 +906,7 @@ static int connect_bucket(int64_t nC, int64_t nE, const int32_t* tetra, int32_t 
 
   // ---- edges, bucketed by their smaller node
   PH_LAUNCH_B("bk_count", 16.0 * nE, k_bk_count<false>, gt, BK_T, 0, s, nE, nC, tetra, w.bcnt, w.dflags);
-  if (want_n2e) {  // Nodes2Edge indexes rows by node id: stop before any pass that would
+  if (want_n2e) {  // Nodes2Edge writes rows by node id: a bad id stops the call here
     int hf = 0;
     PH_HIP(hipMemcpyAsync(&hf, w.dflags, sizeof(int), hipMemcpyDeviceToHost, s));
     PH_HIP(hipStreamSynchronize(s));
