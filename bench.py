@@ -301,6 +301,33 @@ def reassembly_block(torch, P, B, M, X0d, T0d, L, reps=5, nk=4):
     return out
 
 
+def general_connect_block(torch, P, X0d, T0d, L, reps=3):
+    """phfem_connect (edges + faces) on the final mesh, which the benchmark step connects in
+    closed form instead: ms per call through the node buckets and through the radix sort
+    (HIP events, mean of reps after one untimed call); both outputs checked against the
+    derived connectivity."""
+    X, T, conn = P.refine_connected_levels(X0d, T0d, L)
+    nC, nE = X.shape[1], T.shape[1]
+    out = {"workload": f"Kuhn cube, {L} levels ({nE} tets), edges + faces"}
+    for radix in (False, True):
+        g = P.connect(T, nC, faces=True, radix=radix)
+        for k in ("edges", "tet2edge", "faces", "tet2face", "sigma", "face2tet", "nbr"):
+            assert torch.equal(g[k], conn[k]), k
+        del g
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.connect(T, nC, faces=True, radix=radix)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out["radix_ms" if radix else "bucket_ms"] = round(ms, 4)
+        if not radix:
+            out["bucket_tets_per_s"] = round(nE / (ms * 1e-3), 1)
+    log("general connect", out)
+    return out
+
+
 # The paper's own timings (MATLAB R2025a, vectorized, FP64, on an Intel Core i5-10210U), level
 # 5 of its 5-tet cube (1,244,160 tets): Table 1 (connectivity and refinement) and Table 2
 # (local matrices), in seconds.  Another machine and another program: context, not a target.
@@ -353,7 +380,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=5)
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (per-kernel HIP events)")
-    ap.add_argument("--no-sort-variant", action="store_true", help="skip the all-sort-connect comparison pipeline")
+    ap.add_argument("--no-sort-variant", action="store_true",
+                    help="skip the general-connect comparisons (pipeline with phfem_connect at every level, "
+                         "connect of the final mesh)")
     ap.add_argument("--no-reassembly", action="store_true", help="skip the pattern-reuse / batched-kappa timings")
     ap.add_argument("--no-paper-mesh", action="store_true", help="skip the paper's 5-tet cube timings")
     ap.add_argument("--calibrate", action="store_true",
@@ -442,7 +471,8 @@ def main():
         ms_ = res["mixed_sort"]
         line["sort_connect_pipeline"] = {
             "value": round(nE / (ms_["ms"] * 1e-3), 1), "ms_per_step": round(ms_["ms"], 4),
-            "note": "same workload with sort-based connect at every level (general phfem_connect path)",
+            "note": "same workload with the general connect (phfem_connect) at every level instead of the "
+                    "derived connectivity",
             "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4)
                                     for k, v in sorted(ms_["kern"].items(), key=lambda kv: -kv[1]["ms"])[:8]}}
     if mixed["kern"]:
@@ -456,6 +486,9 @@ def main():
                                        for k, v in sorted(mixed["kern"].items(), key=lambda kv: -kv[1]["ms"])}
         line["fp64"]["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
                                                for k, v in sorted(fp64["kern"].items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_sort_variant:
+        line["general_connect"] = general_connect_block(torch, P, X0d, T0d, L)
+        torch.cuda.empty_cache()
     if not args.no_reassembly:
         line["reassembly"] = reassembly_block(torch, P, B, M, X0d, T0d, L)
         torch.cuda.empty_cache()
