@@ -190,11 +190,6 @@ __device__ __forceinline__ void load_vec(const double x[4][3], double vol, const
 
 // AoS copy of the coordinates, one 32-byte (x, y, z, 0) record per node: a tet's gather
 // then touches 4 cache lines instead of 12
-__global__ __launch_bounds__(FT) void k_coords_aos(int64_t nC, const double* __restrict__ X, double4* __restrict__ XA) {
-  const int64_t v = (int64_t)blockIdx.x * FT + threadIdx.x;
-  if (v >= nC) return;
-  XA[v] = make_double4(X[v], X[nC + v], X[2 * nC + v], 0.0);
-}
 
 __device__ __forceinline__ void gather_xa(const double4* __restrict__ XA, const int v[4], double x[4][3]) {
 #pragma unroll
@@ -488,6 +483,12 @@ __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __
   }
 }
 
+__global__ __launch_bounds__(FT) void k_coords_aos(int64_t nC, const double* __restrict__ X, double4* __restrict__ XA) {
+  const int64_t v = (int64_t)blockIdx.x * FT + threadIdx.x;
+  if (v >= nC) return;
+  XA[v] = make_double4(X[v], X[nC + v], X[2 * nC + v], 0.0);
+}
+
 // rank of each of the 6 columns (ties by position; pads last)
 __device__ __forceinline__ void col_ranks(const int (&cf)[6], int (&rk)[6]) {
 #pragma unroll
@@ -519,8 +520,12 @@ __device__ __forceinline__ double face_bD(int64_t nF, int64_t nC, const double* 
                                (xx[0][1] + xx[1][1] + xx[2][1]) / 3.0, (xx[0][2] + xx[1][2] + xx[2][2]) / 3.0);
 }
 
-// Rows of the faces owned by tile blockIdx.x.  PATTERN: also rowptr and col (values-only
-// re-assembly leaves them to an earlier call).
+// Rows of the faces owned by tile blockIdx.x.  Faces are numbered in owner order, so the tile
+// owns one id range, found from its tets' owned faces right after their first loads; the
+// face-to-tet slots of the first NPF chunks of CT faces of that range, and the records of
+// their cross-tile second tets, are then requested before the element arithmetic, so that
+// their latency overlaps it instead of following it.  PATTERN: also rowptr and col
+// (values-only re-assembly leaves them to an earlier call).
 template <class R, bool PATTERN>
 __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __restrict__ XA,
                                                   const double* __restrict__ X, int64_t nE,
@@ -531,6 +536,7 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
                                                   const SlotRec<R>* __restrict__ recs, int32_t* __restrict__ rowptr,
                                                   int32_t* __restrict__ col, double* __restrict__ val,
                                                   double* __restrict__ diag, double* __restrict__ rhs) {
+  constexpr int NPF = sizeof(R) == 4 ? 2 : 1;
   __shared__ R lS[10][CT];
   __shared__ R lr[4][CT];
   __shared__ int32_t lF[4][CT];
@@ -544,33 +550,33 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
     lrange[0] = INT_MAX;
     lrange[1] = -1;
   }
-  __syncthreads();
+  const int64_t t = T0 + o;
+  int v[4], sig[4], F[4];
+  double kap = P.kc;
   int fmin = INT_MAX, fmax = -1;
   if (o < nb) {
-    const int64_t t = T0 + o;
-    int sig[4], F[4];
-    double x[4][3];
-    elem_inputs(nC, XA, nE, t, tet, t2f, sigma, sig, F, x);
-    R su[10], r[4];
-    elem_block<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, su, r);
 #pragma unroll
-    for (int j = 0; j < 10; ++j) lS[j][o] = su[j];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      lr[k][o] = r[k];
-      lF[k][o] = F[k];
-      if (sig[k] > 0) {
-        fmin = min(fmin, F[k]);
-        fmax = max(fmax, F[k]);
+    for (int i = 0; i < 4; ++i) {
+      v[i] = tet[i * nE + t];
+      if ((uint32_t)v[i] >= (uint64_t)nC) v[i] = 0;  // invalid input: no read out of range
+      sig[i] = sigma[i * nE + t];
+      F[i] = t2f[i * nE + t];
+      if (sig[i] > 0) {
+        fmin = min(fmin, F[i]);
+        fmax = max(fmax, F[i]);
       }
     }
+    if (kappa) kap = kappa[t];
   }
-  // the tile's owned face range (faces are numbered in owner order)
+  double x[4][3];
+  if (o < nb) gather_xa(XA, v, x);
+  // the tile's owned face range
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     fmin = min(fmin, __shfl_xor(fmin, d, 64));
     fmax = max(fmax, __shfl_xor(fmax, d, 64));
   }
+  __syncthreads();
   if ((o & 63) == 0) {
     atomicMin(&lrange[0], fmin);
     atomicMax(&lrange[1], fmax);
@@ -580,12 +586,44 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
   int64_t F1 = (int64_t)lrange[1] + 1;
   if (F1 > nF) F1 = nF;                    // invalid input: stay in range
   if (F1 - F0 > 4 * CT) F1 = F0 + 4 * CT;  // (a tile owns at most 4 CT faces)
-  // rows in chunks of CT faces: built into LDS, then stored as contiguous ranges
-  for (int64_t base = F0; base < F1; base += CT) {
+  // the slot of the second tet of a face is a record when that tet lies outside the tile
+  auto cross_slot = [&](int q1) {
+    const int o2 = (q1 >> 2) - (int)T0;
+    return q1 >= 0 && (uint64_t)q1 < (uint64_t)(4 * nE) && !(o2 >= 0 && o2 < nb);
+  };
+  int pq0[NPF], pq1[NPF];
+#pragma unroll
+  for (int c = 0; c < NPF; ++c) {
+    const int64_t f = F0 + c * CT + o;
+    pq0[c] = f < F1 ? face2tet[f] : -1;
+    pq1[c] = f < F1 ? face2tet[nF + f] : -1;
+  }
+  SlotRec<R> prec[NPF];
+#pragma unroll
+  for (int c = 0; c < NPF; ++c)
+    if (cross_slot(pq1[c])) prec[c] = recs[pq1[c]];
+  if (o < nb) {
+    R su[10], r[4];
+    elem_block<R>(x, sig, F, kap, P, nF, su, r);
+#pragma unroll
+    for (int j = 0; j < 10; ++j) lS[j][o] = su[j];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lr[k][o] = r[k];
+      lF[k][o] = F[k];
+    }
+  }
+  __syncthreads();
+  // one chunk of CT faces from `base`: rows built into LDS, then stored as contiguous ranges.
+  // pre: q0, q1 (and the record, for a cross-tile second tet) were loaded above.
+  auto chunk = [&](int64_t base, bool pre, int q0, int q1, SlotRec<R> rec) __attribute__((always_inline)) {
     const int nloc = F1 - base < CT ? (int)(F1 - base) : CT;
     const int64_t f = base + o;
     if (o < nloc) {
-      const int q0 = face2tet[f], q1 = face2tet[nF + f];
+      if (!pre) {
+        q0 = face2tet[f];
+        q1 = face2tet[nF + f];
+      }
       const int oo = (q0 >> 2) - (int)T0, k = q0 & 3;
       int cf[6], rk[6];
       double cv[6];
@@ -622,7 +660,7 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
             ++n;
           }
         } else {  // its record
-          const SlotRec<R> b = recs[q1];
+          const SlotRec<R> b = pre ? rec : recs[q1];
           dg += (double)b.d;
           rh -= (double)b.r;
 #pragma unroll
@@ -657,7 +695,15 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
       if (PATTERN) st_nt(col + 6 * base + i, lcol[i]);
     }
     __syncthreads();
-  }
+  };
+  int64_t base = F0;
+#pragma unroll
+  for (int c = 0; c < NPF; ++c)
+    if (base < F1) {
+      chunk(base, true, pq0[c], pq1[c], prec[c]);
+      base += CT;
+    }
+  for (; base < F1; base += CT) chunk(base, false, -1, -1, prec[0]);
 }
 
 // ---------------------------------------------------------------- recovery / residual (FP64)
@@ -1053,27 +1099,31 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
     int32_t* rp = j == 0 ? rowptr : nullptr;
     int32_t* cl = j == 0 ? col : nullptr;
     double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
-    const double tb = tbv + (cl ? tbp : 0.0);
+    const double tby = tbv + (cl ? tbp : 0.0);
     if (mixed) {
       auto* rc32 = (SlotRec<float>*)recs;
       PH_LAUNCH_B("cond_cross_f32", cb, k_cond_cross<float>, gx, CT, 0, s, nC, XA, nE, tetra, tet2face, sigma, nbr, kj,
                   P, nF, rc32);
       if (cl)
-        PH_LAUNCH_B("cond_tile_f32", tb, (k_cond_tile<float, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra, tet2face,
-                    sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl, vj, dj, rj);
+        PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra, tet2face,
+                    sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl, vj, dj,
+                    rj);
       else
-        PH_LAUNCH_B("cond_tile_f32", tb, (k_cond_tile<float, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl, vj, dj, rj);
+        PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl,
+                    vj, dj, rj);
     } else {
       auto* rc64 = (SlotRec<double>*)recs;
       PH_LAUNCH_B("cond_cross_f64", cb, k_cond_cross<double>, gx, CT, 0, s, nC, XA, nE, tetra, tet2face, sigma, nbr,
                   kj, P, nF, rc64);
       if (cl)
-        PH_LAUNCH_B("cond_tile_f64", tb, (k_cond_tile<double, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp, cl, vj, dj, rj);
+        PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp,
+                    cl, vj, dj, rj);
       else
-        PH_LAUNCH_B("cond_tile_f64", tb, (k_cond_tile<double, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp, cl, vj, dj, rj);
+        PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp,
+                    cl, vj, dj, rj);
     }
   }
   return PHFEM_OK;
