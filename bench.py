@@ -385,6 +385,8 @@ def main():
                          "connect of the final mesh)")
     ap.add_argument("--no-reassembly", action="store_true", help="skip the pattern-reuse / batched-kappa timings")
     ap.add_argument("--no-paper-mesh", action="store_true", help="skip the paper's 5-tet cube timings")
+    ap.add_argument("--connect-only", action="store_true",
+                    help="only the general connect of the final mesh (node buckets, then radix sort); one JSON line")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run the library's calibration streams (1 GiB read, 1 GiB write, 1 GiB copy, "
                          "2^25 scattered 32-byte records gathered from a 2 GiB array), each twice, and exit: "
@@ -425,6 +427,9 @@ def main():
     db0 = M.boundary_faces_box(X0, T0)
     X0d, T0d, db0d = (torch.tensor(a, device=dev) for a in (X0, T0, db0))
     L = args.levels
+    if args.connect_only:
+        print(json.dumps(general_connect_block(torch, P, X0d, T0d, L)), flush=True)
+        return
     nE, nC, nEd, nF, nB = kuhn_counts(L)
     f = (B.FUN_SIN3, (M.SIN3_AMPLITUDE,))
     res = {}
