@@ -100,22 +100,25 @@ def run_pipeline(P, X0, T0, db0, L, prm, kappa=None, sort_connect=False, status=
 
 
 def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort_connect=False):
-    """ms per step (HIP events around `steps` steps, profiler off), host wall ms per step,
-    and -- from a second, separately run set of `steps` steps with the per-launch event
-    profiler on -- per-kernel launches / ms / algorithmic bytes."""
+    """ms per step (HIP events around `steps` steps, profiler off), the median of the steps'
+    own event times, host wall ms per step, and -- from a second, separately run set of
+    `steps` steps with the per-launch event profiler on -- per-kernel launches / ms /
+    algorithmic bytes."""
     st = torch.zeros(1, dtype=torch.int32, device=X0.device)
     for _ in range(warmup):
         run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect, status=st)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         out = run_pipeline(P, X0, T0, db0, L, prm, sort_connect=sort_connect, status=st)
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / steps
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    med = per[len(per) // 2] if steps % 2 else 0.5 * (per[len(per) // 2 - 1] + per[len(per) // 2])
     P.check_status(st)  # every step's refinement input check, read once
     kern = {}
     if profile:
@@ -130,7 +133,17 @@ def time_pipeline(torch, P, B, X0, T0, db0, L, prm, steps, warmup, profile, sort
         for name in B.phfem_profile_names():
             n, tms, by = B.phfem_profile_query(name)
             kern[name] = dict(launches=n, ms=tms, bytes=by)
-    return ms, wall / steps * 1e3, kern, out
+    return ms, med, wall / steps * 1e3, kern, out
+
+
+def stages(kern, steps):
+    """Per-stage ms per step from the profiled kernels: the condensation (AoS coordinates and
+    both condensation passes) and everything before it (refinement, connectivity, scans)."""
+    out = {"refine_connect": 0.0, "assemble_condense": 0.0}
+    for k, v in kern.items():
+        key = "assemble_condense" if k.startswith("cond_") or k == "coords_aos" else "refine_connect"
+        out[key] += v["ms"] / steps
+    return {k: round(v, 4) for k, v in out.items()}
 
 
 def measured_traffic(kernel):
@@ -372,7 +385,7 @@ def paper_mesh_block(torch, P, B, M, L=5, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--solve-levels", type=int, default=5)
@@ -437,10 +450,10 @@ def main():
         if sortc and args.no_sort_variant:
             continue
         prm = P.params(c=1.0, kappa=1.0, f=f, precision=prec)
-        ms, wall_ms, kern, out = time_pipeline(torch, P, B, X0d, T0d, db0d, L, prm, args.steps, args.warmup,
-                                               not args.no_profile, sort_connect=sortc)
+        ms, med, wall_ms, kern, out = time_pipeline(torch, P, B, X0d, T0d, db0d, L, prm, args.steps, args.warmup,
+                                                    not args.no_profile, sort_connect=sortc)
         assert out[1].shape[1] == nE and out[2]["nF"] == nF
-        res[label] = dict(ms=ms, wall_ms=wall_ms, kern=kern)
+        res[label] = dict(ms=ms, med=med, wall_ms=wall_ms, kern=kern)
         log(f"{label}: {ms:.3f} ms/step, {nE / ms * 1e3:.4g} tets/s")
         del out
         torch.cuda.empty_cache()
@@ -456,19 +469,20 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(mixed["ms"], 4),
+        "ms_per_step_median": round(mixed["med"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"Kuhn cube (6 tets) refined {L} times by the 12-subtet split -> {nE} tets, "
-                               f"{nF} faces; sort-based connect of level 0, refine with derived connectivity per "
+                               f"{nF} faces; general connect of level 0 (one workgroup), refine with derived connectivity per "
                                f"level, assemble + condense at the last level; mixed precision (FP32 local/Schur, "
                                f"FP64 dets and face system)",
                    "levels": L, "nE": nE, "nC": nC, "nEd": nEd, "nF": nF, "nnz_offdiag": 6 * nF - 3 * nB,
                    "stored_offdiag": 6 * nF},
         "fp64": {"value": round(nE / (fp64["ms"] * 1e-3), 1), "ms_per_step": round(fp64["ms"], 4),
-                 "mixed_speedup": round(fp64["ms"] / mixed["ms"], 3)},
+                 "ms_per_step_median": round(fp64["med"], 4), "mixed_speedup": round(fp64["ms"] / mixed["ms"], 3)},
         "useful_hbm_frac": round(comp / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "compulsory_bytes_per_step": comp,
     }
@@ -476,6 +490,7 @@ def main():
         ms_ = res["mixed_sort"]
         line["sort_connect_pipeline"] = {
             "value": round(nE / (ms_["ms"] * 1e-3), 1), "ms_per_step": round(ms_["ms"], 4),
+            "ms_per_step_median": round(ms_["med"], 4),
             "note": "same workload with the general connect (phfem_connect) at every level instead of the "
                     "derived connectivity",
             "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4)
@@ -487,6 +502,8 @@ def main():
         pt = pipeline_traffic(mixed["kern"], args.steps)
         line["achieved_hbm_frac"] = None if pt is None else round(pt / (mixed["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
         line["measured_bytes_per_step"] = None if pt is None else round(pt)
+        line["stages_ms_per_step"] = stages(mixed["kern"], args.steps)
+        line["fp64"]["stages_ms_per_step"] = stages(fp64["kern"], args.steps)
         line["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
                                        for k, v in sorted(mixed["kern"].items(), key=lambda kv: -kv[1]["ms"])}
         line["fp64"]["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
