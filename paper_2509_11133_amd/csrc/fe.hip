@@ -399,6 +399,16 @@ __device__ __forceinline__ void elem_block(const double (&x)[4][3], const int (&
   }
 }
 
+// An empty register barrier on the coordinates: the element arithmetic of one field cannot be
+// hoisted out of a loop over fields (holding its geometric intermediates in registers across
+// the loop would cost more, in occupancy, than recomputing them).
+__device__ __forceinline__ void opaque_coords(double (&x)[4][3]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) asm volatile("" : "+v"(x[i][e]));
+}
+
 // the tet's vertex ids (clamped into range: invalid input gives garbage, never a read out of
 // range), sigma, face ids and coordinates
 __device__ __forceinline__ void elem_inputs(int64_t nC, const double4* __restrict__ XA, int64_t nE, int64_t t,
@@ -426,7 +436,7 @@ template <class R>
 __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __restrict__ XA, int64_t nE,
                                                    const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                                    const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
-                                                   const double* __restrict__ kappa, DevParams P, int64_t nF,
+                                                   int nk, const double* __restrict__ kappa, DevParams P, int64_t nF,
                                                    SlotRec<R>* __restrict__ recs) {
   __shared__ int32_t lt[CX];
   __shared__ int32_t lcnt;
@@ -462,23 +472,26 @@ __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __
     int sig[4], F[4];
     double x[4][3];
     elem_inputs(nC, XA, nE, t, tet, t2f, sigma, sig, F, x);
-    R su[10], r[4];
-    elem_block<R>(x, sig, F, kappa ? kappa[t] : P.kc, P, nF, su, r);
+    for (int j = 0; j < nk; ++j) {  // field j of the group: kappa + j nE, records at recs + j 4 nE
+      opaque_coords(x);
+      R su[10], r[4];
+      elem_block<R>(x, sig, F, kappa ? kappa[j * nE + t] : P.kc, P, nF, su, r);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (!(cross & (1 << k))) continue;
-      SlotRec<R> q;
-      q.d = su[uidx(k, k)];
-      q.r = r[k];
-      int m = 0;
+      for (int k = 0; k < 4; ++k) {
+        if (!(cross & (1 << k))) continue;
+        SlotRec<R> q;
+        q.d = su[uidx(k, k)];
+        q.r = r[k];
+        int m = 0;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        if (l == k) continue;
-        q.o[m] = su[uidx(k, l)];
-        q.c[m] = F[l];
-        ++m;
+        for (int l = 0; l < 4; ++l) {
+          if (l == k) continue;
+          q.o[m] = su[uidx(k, l)];
+          q.c[m] = F[l];
+          ++m;
+        }
+        store_rec(recs + (int64_t)j * 4 * nE + 4 * t + k, q);
       }
-      store_rec(recs + 4 * t + k, q);
     }
   }
 }
@@ -1042,16 +1055,20 @@ extern "C" int phfem_assemble(int64_t nC, const double* coord, int64_t nE, const
   return PHFEM_OK;
 }
 
+// fields per cross pass (it loops over them, reading each cross tet's inputs once)
+constexpr int COND_GROUP = 4;
+
 extern "C" size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision,
                                                  int32_t nk) {
   (void)nF;
   if (nk < 1) return 0;
-  Arena a;  // the AoS coordinates and one field's cross-tile records (the fields run in turn)
+  Arena a;  // the AoS coordinates and one group's cross-tile records (the groups run in turn)
   a.take<double4>(nC);
+  const int64_t g = std::min<int64_t>(nk, COND_GROUP);
   if (precision == PHFEM_MIXED)
-    a.take<SlotRec<float>>(4 * nE);
+    a.take<SlotRec<float>>(g * 4 * nE);
   else
-    a.take<SlotRec<double>>(4 * nE);
+    a.take<SlotRec<double>>(g * 4 * nE);
   return a.size();
 }
 
@@ -1082,48 +1099,54 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
   Arena a(work, work_bytes);
   const bool mixed = p->precision == PHFEM_MIXED;
   double4* XA = a.take<double4>(nC);
-  void* recs = mixed ? (void*)a.take<SlotRec<float>>(4 * nE) : (void*)a.take<SlotRec<double>>(4 * nE);
+  const int64_t grp = std::min<int64_t>(nk, COND_GROUP);
+  void* recs = mixed ? (void*)a.take<SlotRec<float>>(grp * 4 * nE) : (void*)a.take<SlotRec<double>>(grp * 4 * nE);
   DevParams P = to_dev(*p);
-  // algorithmic bytes per field.  cross: tets, tet2face, sigma, nbr (+ kappa) once; tile:
-  // tets, tet2face, sigma (+ kappa) once, face2tet once, off-diagonal values, diagonal and rhs
-  // written once, the pattern (col + row pointer) once when written; coordinates once per
-  // pass (the records crossing tiles are left out: an intermediate of this design)
+  // algorithmic bytes per field.  cross: tets, tet2face, sigma, nbr (+ kappa) once (each
+  // further field of its group adds its kappa only); tile: tets, tet2face, sigma (+ kappa)
+  // once, face2tet once, off-diagonal values, diagonal and rhs written once, the pattern (col +
+  // row pointer) once when written; coordinates once per pass (the records crossing tiles are
+  // left out: an intermediate of this design)
   const double kb = kappa ? 8.0 : 0.0;
   const double cb = (52.0 + kb) * nE + 32.0 * nC;
   const double tbv = (36.0 + kb) * nE + 32.0 * nC + 8.0 * nF + (8.0 * 6.0 + 16.0) * nF, tbp = 4.0 * 7.0 * nF;
   const unsigned gt = grid_for(nE, CT), gx = grid_for(nE, CX);
   PH_LAUNCH_B("coords_aos", 56.0 * nC, k_coords_aos, grid_for(nC, FT), FT, 0, s, nC, coord, XA);
-  for (int j = 0; j < nk; ++j) {
-    // field j; the pattern (when asked for) with the first field only
-    const double* kj = kappa ? kappa + j * nE : nullptr;
-    int32_t* rp = j == 0 ? rowptr : nullptr;
-    int32_t* cl = j == 0 ? col : nullptr;
-    double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
-    const double tby = tbv + (cl ? tbp : 0.0);
-    if (mixed) {
-      auto* rc32 = (SlotRec<float>*)recs;
-      PH_LAUNCH_B("cond_cross_f32", cb, k_cond_cross<float>, gx, CT, 0, s, nC, XA, nE, tetra, tet2face, sigma, nbr, kj,
-                  P, nF, rc32);
-      if (cl)
-        PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra, tet2face,
-                    sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl, vj, dj,
-                    rj);
-      else
-        PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<float>*)rc32, rp, cl,
-                    vj, dj, rj);
-    } else {
-      auto* rc64 = (SlotRec<double>*)recs;
-      PH_LAUNCH_B("cond_cross_f64", cb, k_cond_cross<double>, gx, CT, 0, s, nC, XA, nE, tetra, tet2face, sigma, nbr,
-                  kj, P, nF, rc64);
-      if (cl)
-        PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp,
-                    cl, vj, dj, rj);
-      else
-        PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                    tet2face, sigma, kj, P, nF, faces, face2tet, (const SlotRec<double>*)rc64, rp,
-                    cl, vj, dj, rj);
+  for (int j0 = 0; j0 < nk; j0 += COND_GROUP) {
+    // fields j0 .. j0 + g - 1: one cross pass writes their records, then one tile pass per field;
+    // the pattern (when asked for) with the first field only
+    const int g = std::min(COND_GROUP, nk - j0);
+    const double* kg = kappa ? kappa + j0 * nE : nullptr;
+    if (mixed)
+      PH_LAUNCH_B("cond_cross_f32", cb + (g - 1) * kb * nE, k_cond_cross<float>, gx, CT, 0, s, nC, XA, nE, tetra,
+                  tet2face, sigma, nbr, g, kg, P, nF, (SlotRec<float>*)recs);
+    else
+      PH_LAUNCH_B("cond_cross_f64", cb + (g - 1) * kb * nE, k_cond_cross<double>, gx, CT, 0, s, nC, XA, nE, tetra,
+                  tet2face, sigma, nbr, g, kg, P, nF, (SlotRec<double>*)recs);
+    for (int jj = 0; jj < g; ++jj) {
+      const int j = j0 + jj;
+      const double* kj = kappa ? kappa + j * nE : nullptr;
+      int32_t* rp = j == 0 ? rowptr : nullptr;
+      int32_t* cl = j == 0 ? col : nullptr;
+      double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
+      const double tby = tbv + (cl ? tbp : 0.0);
+      if (mixed) {
+        const auto* rc32 = (const SlotRec<float>*)recs + jj * 4 * nE;
+        if (cl)
+          PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc32, rp, cl, vj, dj, rj);
+        else
+          PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc32, rp, cl, vj, dj, rj);
+      } else {
+        const auto* rc64 = (const SlotRec<double>*)recs + jj * 4 * nE;
+        if (cl)
+          PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc64, rp, cl, vj, dj, rj);
+        else
+          PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc64, rp, cl, vj, dj, rj);
+      }
     }
   }
   return PHFEM_OK;
