@@ -286,10 +286,11 @@ int phfem_condense(int64_t nC, const double* coord, int64_t nE, const int32_t* t
  * rowptr[nF+1] and col[6 nF] are written when both are given and left untouched when both are
  * NULL (values-only re-assembly: the pattern phfem_condense wrote for the same connectivity
  * stays valid; it saves the 28 B/face of col and row pointers).  The coordinate copy is built
- * once per call and the fields are condensed in turn (measured faster than one fused pass,
- * whose per-field registers cost occupancy); field j's arrays equal phfem_condense's with
- * kappa + j nE, bit for bit.  Workspace: phfem_condense_batch_workspace (one field's
- * cross-tile records, independent of nk).
+ * once per call; the cross-tile pass runs once per group of up to four fields (reading the
+ * mesh once for the group), the tile pass once per field (a fused pass over several fields
+ * costs occupancy in registers); field j's arrays equal phfem_condense's with kappa + j nE,
+ * bit for bit.  Workspace: phfem_condense_batch_workspace (one group's cross-tile records:
+ * min(nk, 4) fields).
  * Errors: EINVAL (also for only one of rowptr / col), ESINGULAR, EWORKSPACE.  Does not
  * synchronize. */
 size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t nF, int32_t precision, int32_t nk);
