@@ -54,10 +54,11 @@ def test_batch_equals_single(precision, neumann):
     gc = P.connect(dev(T), X.shape[1])
     nm = P.neumann_flags(gc, dev(Nb)) if neumann else None
     gp = P.params(**prm, precision=precision, neumann=nm)
-    ks = dev(fields(T.shape[1], 3))
+    nk = 6  # two groups of the cross pass (4 + 2 fields)
+    ks = dev(fields(T.shape[1], nk))
     Xd, Td = dev(X), dev(T)
     batch = P.condense_batch(Xd, Td, gc, ks, gp)
-    for j in range(3):
+    for j in range(nk):
         one = P.condense(Xd, Td, gc, ks[j].contiguous(), gp)
         for k in ("rowptr", "col", "val", "diag", "rhs"):
             assert torch.equal(batch[j][k], one[k]), (j, k)
@@ -65,9 +66,9 @@ def test_batch_equals_single(precision, neumann):
     rp0, col0 = batch[0]["rowptr"].clone(), batch[0]["col"].clone()
     again = P.condense_batch(Xd, Td, gc, ks.flip(0).contiguous(), gp, pattern=(batch[0]["rowptr"], batch[0]["col"]))
     assert torch.equal(batch[0]["rowptr"], rp0) and torch.equal(batch[0]["col"], col0)
-    for j in range(3):
+    for j in range(nk):
         for k in ("val", "diag", "rhs"):
-            assert torch.equal(again[2 - j][k], batch[j][k]), (j, k)
+            assert torch.equal(again[nk - 1 - j][k], batch[j][k]), (j, k)
 
 
 def full_csr(sysm, nF):
