@@ -341,6 +341,65 @@ def general_connect_block(torch, P, X0d, T0d, L, reps=3):
     return out
 
 
+def rows_block(torch, P, B, M, X0d, T0d, L, reps=3, iters=300):
+    """Each stage of the path on its own at the final level, against HBM peak on its compulsory
+    bytes: the last refinement with derived connectivity (level L-1 -> L), the condensation in
+    both precisions, one PCG iteration of each solver on the L face system (mean over `iters`
+    iterations of its two kernels) and the recovery of u_h.  Per stage: the kernels' HIP-event
+    ms (profiler on), the compulsory bytes and bytes / time / 8 TB/s."""
+    nE, nC, nEd, nF, nB = kuhn_counts(L)
+    rows8 = section8d_rows(L)
+    out = {"workload": f"Kuhn cube, level {L} ({nE} tets, {nF} faces); kernel times from the library's event "
+                       f"profiler, mean of {reps} calls (PCG: of {iters} iterations)"}
+
+    def profiled(fn, n):
+        B.phfem_profile_reset()
+        B.phfem_profile_enable(True)
+        for _ in range(n):
+            r = fn()
+        torch.cuda.synchronize()
+        B.phfem_profile_enable(False)
+        return r, {k: B.phfem_profile_query(k) for k in B.phfem_profile_names()}
+
+    def row(kern, names, nbytes, calls):
+        ms = sum(kern[k][1] for k in kern if k in names) / calls
+        return {"kernels": sorted(k for k in kern if k in names), "ms": round(ms, 4), "compulsory_bytes": round(nbytes),
+                "frac": round(nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+
+    Xc, Tc, cc = P.refine_connected_levels(X0d, T0d, L - 1)
+    (X, T, conn), kern = profiled(lambda: P.refine_connected(Xc, Tc, cc), reps)
+    out["refine_connect"] = row(kern, set(kern), rows8["refine"] + rows8["connect"], reps)
+    out["refine_connect"]["note"] = "refine + connect rows (the derived path reads no refined tets: an upper bound)"
+    del Xc, Tc, cc
+    f = (B.FUN_SIN3, (M.SIN3_AMPLITUDE,))
+    for label, prec, mode, bpf in (("mixed", B.MIXED, B.SOLVE_FP32_PCG_FP64_IR, 92.0),
+                                   ("fp64", B.FP64, B.SOLVE_FP64_PCG, 168.0)):
+        prm = P.params(c=1.0, kappa=1.0, f=f, precision=prec)
+        sysm, kern = profiled(lambda: P.condense(X, T, conn, None, prm), reps)
+        out[f"condense_{label}"] = row(kern, set(kern), rows8["condense"], reps)
+        torch.cuda.synchronize()
+        B.phfem_profile_reset()
+        B.phfem_profile_enable(True)
+        P.solve(X, T, conn, sysm, None, prm, mode=mode, tol=1e-30, max_iter=iters, allow_noconv=True)
+        torch.cuda.synchronize()
+        B.phfem_profile_enable(False)
+        kern = {k: B.phfem_profile_query(k) for k in B.phfem_profile_names()}
+        it = {k: kern[k][1] / kern[k][0] for k in ("spmv_dir", "pcg_update") if k in kern and kern[k][0]}
+        ms = sum(it.values())
+        out[f"pcg_iteration_{label}"] = {"kernels": sorted(it), "ms": round(ms, 4), "bytes_per_face": bpf,
+                                         "compulsory_bytes": round(bpf * nF),
+                                         "frac": round(bpf * nF / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        if label == "fp64" and "recover" in kern:
+            rb = 16 * nE + 16 * nE + 4 * nE + 24 * nC + 8 * nF + 32 * nE  # tets, faces, sigma, coords, lambda in; U out
+            rms = kern["recover"][1] / kern["recover"][0]
+            out["recover"] = {"kernels": ["recover"], "ms": round(rms, 4), "compulsory_bytes": rb,
+                              "frac": round(rb / (rms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        del sysm
+        torch.cuda.empty_cache()
+    log("rows", out)
+    return out
+
+
 # The paper's own timings (MATLAB R2025a, vectorized, FP64, on an Intel Core i5-10210U), level
 # 5 of its 5-tet cube (1,244,160 tets): Table 1 (connectivity and refinement) and Table 2
 # (local matrices), in seconds.  Another machine and another program: context, not a target.
@@ -397,6 +456,7 @@ def main():
                     help="skip the general-connect comparisons (pipeline with phfem_connect at every level, "
                          "connect of the final mesh)")
     ap.add_argument("--no-reassembly", action="store_true", help="skip the pattern-reuse / batched-kappa timings")
+    ap.add_argument("--no-rows", action="store_true", help="skip the per-stage roofline table at the final level")
     ap.add_argument("--no-paper-mesh", action="store_true", help="skip the paper's 5-tet cube timings")
     ap.add_argument("--connect-only", action="store_true",
                     help="only the general connect of the final mesh (node buckets, then radix sort); one JSON line")
@@ -510,6 +570,11 @@ def main():
                                                for k, v in sorted(fp64["kern"].items(), key=lambda kv: -kv[1]["ms"])}
     if not args.no_sort_variant:
         line["general_connect"] = general_connect_block(torch, P, X0d, T0d, L)
+        gc = line["general_connect"]
+        gc["frac"] = round(section8d_rows(L)["connect"] / (gc["bucket_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+        torch.cuda.empty_cache()
+    if not args.no_rows:
+        line["rows_roofline"] = rows_block(torch, P, B, M, X0d, T0d, L)
         torch.cuda.empty_cache()
     if not args.no_reassembly:
         line["reassembly"] = reassembly_block(torch, P, B, M, X0d, T0d, L)
