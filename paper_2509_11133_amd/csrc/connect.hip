@@ -416,7 +416,7 @@ constexpr int BK_CAP = 2048;         // occurrences of those buckets staged in L
 constexpr int BK_BIG = 8192;         // largest bucket resolved here
 enum : int { DEV_BUCKET = 16 };      // internal: a bucket above BK_BIG occurrences
 static_assert(BK_HS > 6 * BK_T, "every probe sequence finds a free slot");
-static_assert(BK_BPW <= 255, "bucket index fits a byte");
+static_assert((BK_BPW & (BK_BPW - 1)) == 0, "bucket search by halving");
 
 __device__ __forceinline__ bool tet_ok(const int v[4], int64_t nC) {
   bool ok = true;
@@ -616,7 +616,6 @@ __global__ __launch_bounds__(BK_T) void k_bk_resolve(int64_t nB, const uint32_t*
                                                      uint32_t* __restrict__ dfl, int* __restrict__ flags) {
   __shared__ uint64_t E[BK_CAP];
   __shared__ uint32_t bs[BK_BPW + 1];
-  __shared__ uint8_t lb[BK_CAP];
   const int64_t b0 = (int64_t)blockIdx.x * BK_BPW;
   const int nb = (int)min((int64_t)BK_BPW, nB - b0);
   const uint32_t s0 = boff[b0], total = boff[b0 + nb] - s0;
@@ -624,11 +623,12 @@ __global__ __launch_bounds__(BK_T) void k_bk_resolve(int64_t nB, const uint32_t*
     for (int i = threadIdx.x; i <= nb; i += BK_T) bs[i] = boff[b0 + i] - s0;
     for (uint32_t e = threadIdx.x; e < total; e += BK_T) E[e] = bent[s0 + e];
     __syncthreads();
-    if ((int)threadIdx.x < nb)
-      for (uint32_t e = bs[threadIdx.x]; e < bs[threadIdx.x + 1]; ++e) lb[e] = (uint8_t)threadIdx.x;
-    __syncthreads();
     for (uint32_t e = threadIdx.x; e < total; e += BK_T) {
-      const int k = lb[e];
+      // the entry's bucket: the last k with bs[k] <= e (binary search over the nb + 1 starts)
+      int k = 0;
+#pragma unroll
+      for (int step = BK_BPW / 2; step > 0; step >>= 1)
+        if (k + step < nb && bs[k + step] <= e) k += step;
       const uint32_t j0 = bs[k];
       bk_resolve_one<FACES, SORTED>(E[e], E + j0, (int)(bs[k + 1] - j0), (int64_t)s0 + j0, hp, pp, bsort, dfl,
                                     flags);
