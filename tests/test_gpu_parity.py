@@ -455,14 +455,23 @@ def test_refine_connected_levels_equals_chained(make, L):
 
 
 def test_refine_connected_matches_sort_connect_L5():
-    """At 1.49M tets (Kuhn, 5 levels): the derived connectivity equals the sort-based
-    phfem_connect of the same refined mesh, bit for bit."""
+    """At 1.49M tets (Kuhn, 5 levels): the derived connectivity equals phfem_connect of the
+    same refined mesh, bit for bit, through the node buckets and through the radix sort (with
+    Nodes2Edge as well: its rows against the derived edges' node pairs)."""
     X, T = M.kuhn_cube()
     Xd, Td, conn = P.refine_connected_levels(dev(X), dev(T), 5)
-    ref = P.connect(Td, Xd.shape[1])
-    for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma", "face2tet",
-              "nbr"):
-        assert torch.equal(conn[k], ref[k]), k
+    for radix in (False, True):
+        ref = P.connect(Td, Xd.shape[1], n2e=True, radix=radix)
+        for k in ("edges", "tet2edge", "edge_first_tet", "tet_edge_prefix", "faces", "tet2face", "sigma",
+                  "face2tet", "nbr"):
+            assert torch.equal(conn[k], ref[k]), (radix, k)
+        e = conn["edges"].cpu().numpy()
+        rp, cl, ed = (ref[k].cpu().numpy() for k in ("n2e_rowptr", "n2e_col", "n2e_edge"))
+        rows = np.repeat(np.arange(Xd.shape[1]), np.diff(rp))
+        assert rp[-1] == conn["nEd"] and np.array_equal(np.sort(ed), np.arange(conn["nEd"])), radix
+        assert np.array_equal(e[0][ed], rows) and np.array_equal(e[1][ed], cl), radix
+        assert np.all(np.diff(cl)[np.diff(rows) == 0] > 0), radix  # ascending within each row
+        del ref
 
 
 # ------------------------------------------------------------------ mixed Dirichlet/Neumann (paper's example)
