@@ -432,14 +432,25 @@ __device__ __forceinline__ void elem_inputs(int64_t nC, const double4* __restric
 constexpr int CXK = 4;
 constexpr int CX = CT * CXK;
 
+// Records are stored densely per workgroup of this pass: workgroup b's region starts at
+// 4 CX b, a tet's records follow each other in local-face order at its offset, the offsets in
+// tet order (an exclusive scan of the cross-face counts); cinfo[t] = offset << 4 | mask of
+// the tet's cross faces, so the tile pass finds the record of slot 4t+k at
+// rec_index(t, k, cinfo[t]).  A field's records take rec_stride(nE) slots.
+__host__ __device__ __forceinline__ int64_t rec_stride(int64_t nE) { return 4 * CX * ((nE + CX - 1) / CX); }
+__device__ __forceinline__ int64_t rec_index(int t, int k, uint32_t ci) {
+  return (int64_t)(t / CX) * 4 * CX + (ci >> 4) + __popc((ci & 15u) & ((1u << k) - 1u));
+}
+
 template <class R>
 __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __restrict__ XA, int64_t nE,
                                                    const int32_t* __restrict__ tet, const int32_t* __restrict__ t2f,
                                                    const int8_t* __restrict__ sigma, const int32_t* __restrict__ nbr,
                                                    int nk, const double* __restrict__ kappa, DevParams P, int64_t nF,
-                                                   SlotRec<R>* __restrict__ recs) {
+                                                   SlotRec<R>* __restrict__ recs, uint16_t* __restrict__ cinfo) {
   __shared__ int32_t lt[CX];
   __shared__ int32_t lcnt;
+  __shared__ uint32_t lw[CT / 64];
   const int64_t T0 = (int64_t)blockIdx.x * CX;
   if (threadIdx.x == 0) lcnt = 0;
   __syncthreads();
@@ -453,26 +464,42 @@ __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __
       sgv[j][k] = t < nE ? sigma[k * nE + t] : 1;
     }
   }
+  int cm[CXK];
 #pragma unroll
   for (int j = 0; j < CXK; ++j) {
     const int64_t t = T0 + j * CT + threadIdx.x;
     const int64_t tile = t / CT;
-    int cross = 0;
+    cm[j] = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (sgv[j][k] < 0 && nbv[j][k] >= 0 && nbv[j][k] / CT != tile) cross |= 1 << k;
-    if (cross) lt[atomicAdd(&lcnt, 1)] = (int32_t)((t - T0) << 4 | cross);
+      if (sgv[j][k] < 0 && nbv[j][k] >= 0 && nbv[j][k] / CT != tile) cm[j] |= 1 << k;
+  }
+  // the tets' record offsets in tet order (j major, then thread)
+  uint32_t run = 0, off[CXK];
+#pragma unroll
+  for (int j = 0; j < CXK; ++j) {
+    uint32_t tot;
+    off[j] = run + block_excl_scan<CT / 64>((uint32_t)__popc(cm[j]), lw, tot);
+    run += tot;
+  }
+#pragma unroll
+  for (int j = 0; j < CXK; ++j) {
+    const int64_t t = T0 + j * CT + threadIdx.x;
+    if (t < nE) cinfo[t] = (uint16_t)(off[j] << 4 | cm[j]);
+    if (cm[j]) lt[atomicAdd(&lcnt, 1)] = (int32_t)(off[j] << 14 | (uint32_t)(t - T0) << 4 | cm[j]);
   }
   __syncthreads();
   const int n = lcnt;
+  const int64_t rs = rec_stride(nE), base = (int64_t)blockIdx.x * 4 * CX;
   for (int i = threadIdx.x; i < n; i += CT) {
     const int w = lt[i];
-    const int64_t t = T0 + (w >> 4);
+    const int64_t t = T0 + ((w >> 4) & (CX - 1));
     const int cross = w & 15;
+    const int64_t tb = base + (w >> 14);
     int sig[4], F[4];
     double x[4][3];
     elem_inputs(nC, XA, nE, t, tet, t2f, sigma, sig, F, x);
-    for (int j = 0; j < nk; ++j) {  // field j of the group: kappa + j nE, records at recs + j 4 nE
+    for (int j = 0; j < nk; ++j) {  // field j of the group: kappa + j nE, records at recs + j rs
       opaque_coords(x);
       R su[10], r[4];
       elem_block<R>(x, sig, F, kappa ? kappa[j * nE + t] : P.kc, P, nF, su, r);
@@ -490,7 +517,7 @@ __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __
           q.c[m] = F[l];
           ++m;
         }
-        store_rec(recs + (int64_t)j * 4 * nE + 4 * t + k, q);
+        store_rec(recs + j * rs + tb + __popc(cross & ((1 << k) - 1)), q);
       }
     }
   }
@@ -546,7 +573,8 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
                                                   const int8_t* __restrict__ sigma, const double* __restrict__ kappa,
                                                   DevParams P, int64_t nF, const int32_t* __restrict__ faces,
                                                   const int32_t* __restrict__ face2tet,
-                                                  const SlotRec<R>* __restrict__ recs, int32_t* __restrict__ rowptr,
+                                                  const SlotRec<R>* __restrict__ recs,
+                                                  const uint16_t* __restrict__ cinfo, int32_t* __restrict__ rowptr,
                                                   int32_t* __restrict__ col, double* __restrict__ val,
                                                   double* __restrict__ diag, double* __restrict__ rhs) {
   constexpr int NPF = sizeof(R) == 4 ? 2 : 1;
@@ -614,7 +642,7 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
   SlotRec<R> prec[NPF];
 #pragma unroll
   for (int c = 0; c < NPF; ++c)
-    if (cross_slot(pq1[c])) prec[c] = recs[pq1[c]];
+    if (cross_slot(pq1[c])) prec[c] = recs[rec_index(pq1[c] >> 2, pq1[c] & 3, cinfo[pq1[c] >> 2])];
   if (o < nb) {
     R su[10], r[4];
     elem_block<R>(x, sig, F, kap, P, nF, su, r);
@@ -673,7 +701,7 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
             ++n;
           }
         } else {  // its record
-          const SlotRec<R> b = pre ? rec : recs[q1];
+          const SlotRec<R> b = pre ? rec : recs[rec_index(q1 >> 2, k2, cinfo[q1 >> 2])];
           dg += (double)b.d;
           rh -= (double)b.r;
 #pragma unroll
@@ -1065,10 +1093,11 @@ extern "C" size_t phfem_condense_batch_workspace(int64_t nC, int64_t nE, int64_t
   Arena a;  // the AoS coordinates and one group's cross-tile records (the groups run in turn)
   a.take<double4>(nC);
   const int64_t g = std::min<int64_t>(nk, COND_GROUP);
+  a.take<uint16_t>(nE);
   if (precision == PHFEM_MIXED)
-    a.take<SlotRec<float>>(g * 4 * nE);
+    a.take<SlotRec<float>>(g * rec_stride(nE) + 4);
   else
-    a.take<SlotRec<double>>(g * 4 * nE);
+    a.take<SlotRec<double>>(g * rec_stride(nE) + 4);
   return a.size();
 }
 
@@ -1099,8 +1128,10 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
   Arena a(work, work_bytes);
   const bool mixed = p->precision == PHFEM_MIXED;
   double4* XA = a.take<double4>(nC);
-  const int64_t grp = std::min<int64_t>(nk, COND_GROUP);
-  void* recs = mixed ? (void*)a.take<SlotRec<float>>(grp * 4 * nE) : (void*)a.take<SlotRec<double>>(grp * 4 * nE);
+  const int64_t grp = std::min<int64_t>(nk, COND_GROUP), rs = rec_stride(nE);
+  uint16_t* cinfo = a.take<uint16_t>(nE);
+  // (4 slots of slack: for invalid input a record index may run 3 past its region)
+  void* recs = mixed ? (void*)a.take<SlotRec<float>>(grp * rs + 4) : (void*)a.take<SlotRec<double>>(grp * rs + 4);
   DevParams P = to_dev(*p);
   // algorithmic bytes per field.  cross: tets, tet2face, sigma, nbr (+ kappa) once (each
   // further field of its group adds its kappa only); tile: tets, tet2face, sigma (+ kappa)
@@ -1119,10 +1150,10 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
     const double* kg = kappa ? kappa + j0 * nE : nullptr;
     if (mixed)
       PH_LAUNCH_B("cond_cross_f32", cb + (g - 1) * kb * nE, k_cond_cross<float>, gx, CT, 0, s, nC, XA, nE, tetra,
-                  tet2face, sigma, nbr, g, kg, P, nF, (SlotRec<float>*)recs);
+                  tet2face, sigma, nbr, g, kg, P, nF, (SlotRec<float>*)recs, cinfo);
     else
       PH_LAUNCH_B("cond_cross_f64", cb + (g - 1) * kb * nE, k_cond_cross<double>, gx, CT, 0, s, nC, XA, nE, tetra,
-                  tet2face, sigma, nbr, g, kg, P, nF, (SlotRec<double>*)recs);
+                  tet2face, sigma, nbr, g, kg, P, nF, (SlotRec<double>*)recs, cinfo);
     for (int jj = 0; jj < g; ++jj) {
       const int j = j0 + jj;
       const double* kj = kappa ? kappa + j * nE : nullptr;
@@ -1131,21 +1162,21 @@ extern "C" int phfem_condense_batch(int64_t nC, const double* coord, int64_t nE,
       double *vj = val + j * 6 * nF, *dj = diag + j * nF, *rj = rhs + j * nF;
       const double tby = tbv + (cl ? tbp : 0.0);
       if (mixed) {
-        const auto* rc32 = (const SlotRec<float>*)recs + jj * 4 * nE;
+        const auto* rc32 = (const SlotRec<float>*)recs + jj * rs;
         if (cl)
           PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                      tet2face, sigma, kj, P, nF, faces, face2tet, rc32, rp, cl, vj, dj, rj);
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc32, cinfo, rp, cl, vj, dj, rj);
         else
           PH_LAUNCH_B("cond_tile_f32", tby, (k_cond_tile<float, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                      tet2face, sigma, kj, P, nF, faces, face2tet, rc32, rp, cl, vj, dj, rj);
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc32, cinfo, rp, cl, vj, dj, rj);
       } else {
-        const auto* rc64 = (const SlotRec<double>*)recs + jj * 4 * nE;
+        const auto* rc64 = (const SlotRec<double>*)recs + jj * rs;
         if (cl)
           PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, true>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                      tet2face, sigma, kj, P, nF, faces, face2tet, rc64, rp, cl, vj, dj, rj);
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc64, cinfo, rp, cl, vj, dj, rj);
         else
           PH_LAUNCH_B("cond_tile_f64", tby, (k_cond_tile<double, false>), gt, CT, 0, s, nC, XA, coord, nE, tetra,
-                      tet2face, sigma, kj, P, nF, faces, face2tet, rc64, rp, cl, vj, dj, rj);
+                      tet2face, sigma, kj, P, nF, faces, face2tet, rc64, cinfo, rp, cl, vj, dj, rj);
       }
     }
   }
