@@ -3,11 +3,15 @@
 // FacesUp / fullFaces.
 //
 // Both numberings are "rank of first appearance" over a position order (edges: 6t + j,
-// faces: 4t + k).  On the GPU: build one key per occurrence, stable radix sort (key,
-// position), mark segment heads (= first appearance, since the sort is stable), count heads
-// per tet and scan -> per-tet prefix, then every occurrence takes the id
-// prefix(t_head) + (heads of t_head before j_head).  Segment heads are found with wave64
-// ballots over the sorted keys.
+// faces: 4t + k): find each occurrence's first appearance (head), count heads per tet and
+// scan -> per-tet prefix, then every occurrence takes the id prefix(t_head) + (heads of
+// t_head before j_head).  Three ways to find the heads, with identical outputs:
+//  * meshes of at most SMALL_NE tets: one workgroup, every occurrence compared with the
+//    earlier ones in LDS;
+//  * the general path: occurrences bucketed by their lowest node (counting sort), each bucket
+//    resolved in LDS (node buckets, below);
+//  * the fallback for a node in thousands of tets (or on request): a stable radix sort of
+//    (key, position), segment heads found with wave64 ballots over the sorted keys.
 #include "common.hpp"
 
 namespace ph {
