@@ -48,7 +48,9 @@ def test_workspace_queries():
     assert L.phfem_refine_workspace(0, 0) == 0 and L.phfem_refine_workspace(3, 0) > 0
     assert L.phfem_face_lookup_workspace(0) == 0 and L.phfem_face_lookup_workspace(100) >= 4 * (256 + 100)
     assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 1) == L.phfem_condense_workspace(20, 50, 100, 1)
-    assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 3) == L.phfem_condense_workspace(20, 50, 100, 1)
+    # the cross pass keeps the records of up to four fields at once
+    assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 3) > L.phfem_condense_workspace(20, 50, 100, 1)
+    assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 9) == L.phfem_condense_batch_workspace(20, 50, 100, 1, 4)
     assert L.phfem_condense_batch_workspace(20, 50, 100, 1, 0) == 0
     # Kuhn cube: 6 tets, 19 edges, 18 faces -> Table-1-style counts by the recurrences
     assert B.phfem_refined_sizes(8, 6, 19, 18, 2) == (8 + 19 + 6 + 2 * 19 + 3 * 18 + 6 * 6 + 72, 864,
