@@ -415,9 +415,12 @@ constexpr int BK_T = 256;            // threads per workgroup
 constexpr int BK_LOGHS = 11;         // LDS hash slots per workgroup: 2048 > 6 BK_T occurrences
 constexpr int BK_HS = 1 << BK_LOGHS;
 constexpr uint32_t BK_EMPTY = 0xffffffffu;
-constexpr int BK_BPW = 32;           // buckets per workgroup in the resolve pass
+constexpr int BK_BPW = 16;           // buckets per workgroup in the resolve pass
 constexpr int BK_CAP = 2048;         // occurrences of those buckets staged in LDS
 constexpr int BK_BIG = 8192;         // largest bucket resolved here
+constexpr int BK_RHS = 1024;         // resolve: LDS hash slots of a workgroup's distinct keys
+constexpr int BK_HCAP = 768;         // resolve: entries of a workgroup resolved by hashing (load <= 3/4)
+constexpr int BK_HE = BK_HCAP / BK_T;  // (entries per thread)
 enum : int { DEV_BUCKET = 16 };      // internal: a bucket above BK_BIG occurrences
 static_assert(BK_HS > 6 * BK_T, "every probe sequence finds a free slot");
 static_assert((BK_BPW & (BK_BPW - 1)) == 0, "bucket search by halving");
@@ -610,20 +613,86 @@ __device__ __forceinline__ void bk_resolve_one(uint64_t mine, const uint64_t* B,
   }
 }
 
-// Buckets [b0, b0 + BK_BPW) per workgroup: staged in LDS when their entries fit BK_CAP, else
-// one bucket at a time from global memory; a bucket above BK_BIG is flagged DEV_BUCKET and
-// its entries are given in-bounds placeholders (own head, no partner, no Nodes2Edge entry).
+// Buckets [b0, b0 + BK_BPW) per workgroup.  Without the sorted output, when their entries fit
+// BK_HCAP: every entry goes into an LDS hash table keyed by (bucket, key part) whose slots keep
+// the least position (edges) or the least slot and one 64-bit sum of (slot, 1 << 32, odd
+// parity << 48) (faces: the other slot of a pair is the sum less this one) -- one insertion per
+// entry instead of a scan of its bucket.  Otherwise the
+// entries are staged in LDS when they fit BK_CAP (each scans its bucket), else one bucket at a
+// time from global memory; a bucket above BK_BIG is flagged DEV_BUCKET and its entries are
+// given in-bounds placeholders (own head, no partner, no Nodes2Edge entry).  Every path
+// writes the same values.
 template <bool FACES, bool SORTED>
 __global__ __launch_bounds__(BK_T) void k_bk_resolve(int64_t nB, const uint32_t* __restrict__ boff,
                                                      const uint64_t* __restrict__ bent, int32_t* __restrict__ hp,
                                                      int32_t* __restrict__ pp, uint64_t* __restrict__ bsort,
                                                      uint32_t* __restrict__ dfl, int* __restrict__ flags) {
-  __shared__ uint64_t E[BK_CAP];
+  constexpr int HS = SORTED ? 1 : BK_RHS, HF = FACES && !SORTED ? BK_RHS : 1;
+  __shared__ uint64_t E[BK_CAP];  // staged entries, or the hash table's keys
+  __shared__ uint32_t hmin[HS];
+  __shared__ uint64_t hsc[HF];
   __shared__ uint32_t bs[BK_BPW + 1];
   const int64_t b0 = (int64_t)blockIdx.x * BK_BPW;
   const int nb = (int)min((int64_t)BK_BPW, nB - b0);
   const uint32_t s0 = boff[b0], total = boff[b0 + nb] - s0;
-  if (total <= (uint32_t)BK_CAP) {
+  static_assert(BK_RHS <= BK_CAP && BK_HCAP < BK_RHS && BK_HCAP % BK_T == 0, "hash table in the staging array");
+  if (!SORTED && total <= (uint32_t)BK_HCAP) {
+    constexpr uint64_t EMPTY64 = ~0ull;
+    for (int i = threadIdx.x; i < BK_RHS; i += BK_T) {
+      E[i] = EMPTY64;
+      hmin[i] = 0xffffffffu;
+      if (FACES) hsc[i] = 0ull;
+    }
+    for (int i = threadIdx.x; i <= nb; i += BK_T) bs[i] = boff[b0 + i] - s0;
+    __syncthreads();
+    int slot[BK_HE];
+    uint32_t wv[BK_HE];
+#pragma unroll
+    for (int u = 0; u < BK_HE; ++u) {
+      const uint32_t e = threadIdx.x + u * BK_T;
+      slot[u] = -1;
+      wv[u] = 0u;
+      if (e < total) {
+        const uint64_t x = bent[s0 + e];
+        int k = 0;
+#pragma unroll
+        for (int step = BK_BPW / 2; step > 0; step >>= 1)
+          if (k + step < nb && bs[k + step] <= e) k += step;
+        const uint64_t key = ((uint64_t)k << 32) | (x >> 32);
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54) & (BK_RHS - 1);  // table never full
+        for (;;) {
+          const uint64_t prev = atomicCAS((unsigned long long*)&E[h], EMPTY64, key);
+          if (prev == EMPTY64 || prev == key) break;
+          h = (h + 1) & (BK_RHS - 1);
+        }
+        slot[u] = (int)h;
+        wv[u] = (uint32_t)x;
+        if (!FACES) {
+          atomicMin(&hmin[h], wv[u]);
+        } else {
+          const uint32_t q = wv[u] >> 1;
+          atomicMin(&hmin[h], q);
+          const uint64_t inc = (uint64_t)q | (1ull << 32) | ((uint64_t)(wv[u] & 1u) << 48);
+          atomicAdd((unsigned long long*)&hsc[h], (unsigned long long)inc);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < BK_HE; ++u) {
+      if (slot[u] < 0) continue;
+      const int h = slot[u];
+      if (!FACES) {
+        hp[wv[u]] = (int32_t)hmin[h];
+      } else {
+        const uint64_t c = hsc[h];
+        const uint32_t q = wv[u] >> 1, mn = hmin[h], n = (uint32_t)(c >> 32) & 0xffffu;
+        hp[q] = (int32_t)mn;
+        pp[q] = n == 2 ? (int32_t)((uint32_t)c - q) : -1;
+        if (n > 2 || (n == 2 && (c >> 48) != 1u)) atomicOr(flags, DEV_ORIENT);
+      }
+    }
+  } else if (total <= (uint32_t)BK_CAP) {
     for (int i = threadIdx.x; i <= nb; i += BK_T) bs[i] = boff[b0 + i] - s0;
     for (uint32_t e = threadIdx.x; e < total; e += BK_T) E[e] = bent[s0 + e];
     __syncthreads();
