@@ -418,8 +418,8 @@ constexpr uint32_t BK_EMPTY = 0xffffffffu;
 constexpr int BK_BPW = 16;           // buckets per workgroup in the resolve pass
 constexpr int BK_CAP = 2048;         // occurrences of those buckets staged in LDS
 constexpr int BK_BIG = 8192;         // largest bucket resolved here
-constexpr int BK_RHS = 1024;         // resolve: LDS hash slots of a workgroup's distinct keys
-constexpr int BK_HCAP = 768;         // resolve: entries of a workgroup resolved by hashing (load <= 3/4)
+constexpr int BK_RHS = 2048;         // resolve: LDS hash slots of a workgroup's distinct keys
+constexpr int BK_HCAP = 1536;        // resolve: entries of a workgroup resolved by hashing (load <= 3/4)
 constexpr int BK_HE = BK_HCAP / BK_T;  // (entries per thread)
 enum : int { DEV_BUCKET = 16 };      // internal: a bucket above BK_BIG occurrences
 static_assert(BK_HS > 6 * BK_T, "every probe sequence finds a free slot");
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(BK_T) void k_bk_resolve(int64_t nB, const uint32_t*
         for (int step = BK_BPW / 2; step > 0; step >>= 1)
           if (k + step < nb && bs[k + step] <= e) k += step;
         const uint64_t key = ((uint64_t)k << 32) | (x >> 32);
-        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 54) & (BK_RHS - 1);  // table never full
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53) & (BK_RHS - 1);  // table never full
         for (;;) {
           const uint64_t prev = atomicCAS((unsigned long long*)&E[h], EMPTY64, key);
           if (prev == EMPTY64 || prev == key) break;

@@ -145,14 +145,18 @@ def test_bucket_and_radix_paths_bitexact(case):
     check_all(X, T)
 
 
-@pytest.mark.parametrize("case", ["uv_last", "uv_first", "ico4_first", "ico3_first"])
+@pytest.mark.parametrize("case", ["uv_last", "uv_first", "uv600_first", "ico4_first", "ico3_first"])
 def test_high_degree_node(case):
     """A node in every tet: numbered last, its buckets stay small on every node but itself as
-    the highest node (LDS path); numbered first, it is the lowest node of 3 occurrences per tet
-    -- 4800 (uv, 1600 tets) and 3840 (ico3, 1280 tets), where its workgroup's buckets exceed
-    LDS and are resolved from global memory, and 15360 (ico4, 5120 tets), above the bucket
-    path's limit, so that the call falls back to the radix sort."""
-    if case.startswith("uv"):
+    the highest node (LDS hash path); numbered first, it is the lowest node of 3 occurrences
+    per tet -- 1800 (uv600, 600 tets: its workgroup's entries exceed the hash table and are
+    staged in LDS, each scanning its bucket), 4800 (uv, 1600 tets) and 3840 (ico3, 1280 tets),
+    where its workgroup's entries exceed LDS and are resolved from global memory, and 15360
+    (ico4, 5120 tets), above the bucket path's limit, so that the call falls back to the radix
+    sort."""
+    if case.startswith("uv600"):
+        X, T = uv_sphere_cone(20, 16, center_first=True)
+    elif case.startswith("uv"):
         X, T = uv_sphere_cone(40, 21, center_first=case.endswith("first"))
     else:
         X, T = icosphere_cone(int(case[3]), center_first=case.endswith("first"))
