@@ -759,7 +759,10 @@ __device__ __forceinline__ int32_t bk_head_id(int32_t h, const int32_t* __restri
   return (int32_t)id;
 }
 
-// edge outputs in tet order; pre = exclusive scan of k_bk_heads<6>, *nEdp its total
+// edge outputs in tet order; pre = exclusive scan of k_bk_heads<6> (nE + 1 entries), *nEdp
+// its total.  The edges first seen in a workgroup's tets have the consecutive ids
+// [pre[t0], pre[t0 + BK_T]): their node pairs and first tets are staged in LDS and stored as
+// contiguous ranges.
 __global__ __launch_bounds__(BK_T) void k_bk_edge_assign(int64_t nE, const int32_t* __restrict__ tet,
                                                          const int32_t* __restrict__ hp,
                                                          const uint32_t* __restrict__ pre,
@@ -767,40 +770,56 @@ __global__ __launch_bounds__(BK_T) void k_bk_edge_assign(int64_t nE, const int32
                                                          int32_t* __restrict__ tet2edge, int32_t* __restrict__ edges,
                                                          int32_t* __restrict__ eft,
                                                          int32_t* __restrict__ tet_edge_prefix) {
-  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
-  if (t >= nE) return;
+  __shared__ int32_t slo[6 * BK_T], shi[6 * BK_T], sft[6 * BK_T];
+  const int64_t t0 = (int64_t)blockIdx.x * BK_T, t = t0 + threadIdx.x;
+  const int nb = nE - t0 < BK_T ? (int)(nE - t0) : BK_T;
   const int64_t nEd = *nEdp;
-  int v[4], h[6];
+  const uint32_t base = pre[t0], nh = pre[t0 + nb] - base;  // this workgroup's first-seen edges
+  if (t < nE) {
+    int v[4], h[6];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
-  const int2* h2 = reinterpret_cast<const int2*>(hp + 6 * t);  // 24 t bytes: 8-byte aligned
+    for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+    const int2* h2 = reinterpret_cast<const int2*>(hp + 6 * t);  // 24 t bytes: 8-byte aligned
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int2 x = h2[i];
-    h[2 * i] = x.x;
-    h[2 * i + 1] = x.y;
-  }
-  const uint32_t pt = pre[t];
-  uint32_t r = 0;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int32_t p = (int32_t)(6 * t + j);
-    int32_t id;
-    if (h[j] == p) {
-      id = (int32_t)(pt + r++);
-      const int a = v[ev0(j)], b = v[ev1(j)];
-      edges[id] = a < b ? a : b;
-      edges[nEd + id] = a < b ? b : a;
-      eft[id] = (int32_t)t;
-    } else {
-      id = bk_head_id<6>(h[j], hp, pre);
+    for (int i = 0; i < 3; ++i) {
+      const int2 x = h2[i];
+      h[2 * i] = x.x;
+      h[2 * i + 1] = x.y;
     }
-    tet2edge[j * nE + t] = id;
+    const uint32_t pt = pre[t];
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int32_t p = (int32_t)(6 * t + j);
+      int32_t id;
+      if (h[j] == p) {
+        id = (int32_t)(pt + r++);
+        const int a = v[ev0(j)], b = v[ev1(j)];
+        const uint32_t l = (uint32_t)id - base;  // < 6 BK_T: heads of this workgroup's tets
+        if (l < 6u * BK_T) {
+          slo[l] = a < b ? a : b;
+          shi[l] = a < b ? b : a;
+          sft[l] = (int32_t)t;
+        }
+      } else {
+        id = bk_head_id<6>(h[j], hp, pre);
+      }
+      tet2edge[j * nE + t] = id;
+    }
+    tet_edge_prefix[t] = (int32_t)pt;
   }
-  tet_edge_prefix[t] = (int32_t)pt;
+  __syncthreads();
+  for (uint32_t l = threadIdx.x; l < nh && l < 6u * BK_T; l += BK_T) {
+    edges[base + l] = slo[l];
+    edges[nEd + base + l] = shi[l];
+    eft[base + l] = sft[l];
+  }
 }
 
-// face outputs in tet order; pre = exclusive scan of k_bk_heads<4>, *nFp its total
+// face outputs in tet order; pre = exclusive scan of k_bk_heads<4> (nE + 1 entries), *nFp its
+// total.  The faces owned by a workgroup's tets have the consecutive ids
+// [pre[t0], pre[t0 + BK_T]): their rows of faces and face2tet are staged in LDS and stored as
+// contiguous ranges.
 __global__ __launch_bounds__(BK_T) void k_bk_face_assign(int64_t nE, const int32_t* __restrict__ tet,
                                                          const int32_t* __restrict__ hp,
                                                          const int32_t* __restrict__ pp,
@@ -809,33 +828,47 @@ __global__ __launch_bounds__(BK_T) void k_bk_face_assign(int64_t nE, const int32
                                                          int32_t* __restrict__ faces, int32_t* __restrict__ tet2face,
                                                          int8_t* __restrict__ sigma, int32_t* __restrict__ face2tet,
                                                          int32_t* __restrict__ nbr) {
-  const int64_t t = (int64_t)blockIdx.x * BK_T + threadIdx.x;
-  if (t >= nE) return;
+  __shared__ int32_t sfa[3][4 * BK_T], sft[2][4 * BK_T];
+  const int64_t t0 = (int64_t)blockIdx.x * BK_T, t = t0 + threadIdx.x;
+  const int nb = nE - t0 < BK_T ? (int)(nE - t0) : BK_T;
   const int64_t nF = *nFp;
-  int v[4];
+  const uint32_t base = pre[t0], nh = pre[t0 + nb] - base;  // this workgroup's owned faces
+  if (t < nE) {
+    int v[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
-  const int4 h4 = reinterpret_cast<const int4*>(hp)[t], p4 = reinterpret_cast<const int4*>(pp)[t];
-  const int h[4] = {h4.x, h4.y, h4.z, h4.w}, pr[4] = {p4.x, p4.y, p4.z, p4.w};
-  const uint32_t pt = pre[t];
-  uint32_t r = 0;
+    for (int i = 0; i < 4; ++i) v[i] = tet[i * nE + t];
+    const int4 h4 = reinterpret_cast<const int4*>(hp)[t], p4 = reinterpret_cast<const int4*>(pp)[t];
+    const int h[4] = {h4.x, h4.y, h4.z, h4.w}, pr[4] = {p4.x, p4.y, p4.z, p4.w};
+    const uint32_t pt = pre[t];
+    uint32_t r = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int32_t q = (int32_t)(4 * t + k);
-    if (h[k] == q) {
-      const int32_t id = (int32_t)(pt + r++);
+    for (int k = 0; k < 4; ++k) {
+      const int32_t q = (int32_t)(4 * t + k);
+      if (h[k] == q) {
+        const int32_t id = (int32_t)(pt + r++);
+        const uint32_t l = (uint32_t)id - base;  // < 4 BK_T: faces owned by this workgroup's tets
+        if (l < 4u * BK_T) {
 #pragma unroll
-      for (int m = 0; m < 3; ++m) faces[m * nF + id] = v[fv(k, m)];
-      face2tet[id] = q;
-      face2tet[nF + id] = pr[k];
-      tet2face[k * nE + t] = id;
-      sigma[k * nE + t] = 1;
-      if (nbr) nbr[k * nE + t] = pr[k] >= 0 ? (pr[k] >> 2) : -1;
-    } else {
-      tet2face[k * nE + t] = bk_head_id<4>(h[k], hp, pre);
-      sigma[k * nE + t] = -1;
-      if (nbr) nbr[k * nE + t] = h[k] >> 2;
+          for (int m = 0; m < 3; ++m) sfa[m][l] = v[fv(k, m)];
+          sft[0][l] = q;
+          sft[1][l] = pr[k];
+        }
+        tet2face[k * nE + t] = id;
+        sigma[k * nE + t] = 1;
+        if (nbr) nbr[k * nE + t] = pr[k] >= 0 ? (pr[k] >> 2) : -1;
+      } else {
+        tet2face[k * nE + t] = bk_head_id<4>(h[k], hp, pre);
+        sigma[k * nE + t] = -1;
+        if (nbr) nbr[k * nE + t] = h[k] >> 2;
+      }
     }
+  }
+  __syncthreads();
+  for (uint32_t l = threadIdx.x; l < nh && l < 4u * BK_T; l += BK_T) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) faces[m * nF + base + l] = sfa[m][l];
+    face2tet[base + l] = sft[0][l];
+    face2tet[nF + base + l] = sft[1][l];
   }
 }
 
