@@ -581,8 +581,8 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
   __shared__ R lS[10][CT];
   __shared__ R lr[4][CT];
   __shared__ int32_t lF[4][CT];
-  __shared__ int32_t lcol[PATTERN ? 6 * CT : 1];
-  __shared__ double lval[6 * CT];
+  __shared__ __align__(16) int32_t lcol[PATTERN ? 6 * CT : 2];
+  __shared__ __align__(16) double lval[6 * CT];
   __shared__ int32_t lrange[2];
   const int64_t T0 = (int64_t)blockIdx.x * CT;
   const int nb = nE - T0 < CT ? (int)(nE - T0) : CT;
@@ -731,9 +731,18 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
       }
     }
     __syncthreads();
-    for (int i = o; i < 6 * nloc; i += CT) {
-      st_nt(val + 6 * base + i, lval[i]);
-      if (PATTERN) st_nt(col + 6 * base + i, lcol[i]);
+    // as 16-byte value pairs and 8-byte column pairs (val + 48 base bytes is 16-byte aligned,
+    // col + 24 base bytes 8-byte aligned, given the alignment the entry point checks)
+    {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      typedef int32_t i2 __attribute__((ext_vector_type(2)));
+      const d2* lv2 = reinterpret_cast<const d2*>(lval);
+      d2* gv2 = reinterpret_cast<d2*>(val + 6 * base);
+      for (int i = o; i < 3 * nloc; i += CT) {
+        __builtin_nontemporal_store(lv2[i], gv2 + i);
+        if (PATTERN)
+          __builtin_nontemporal_store(reinterpret_cast<const i2*>(lcol)[i], reinterpret_cast<i2*>(col + 6 * base) + i);
+      }
     }
     __syncthreads();
   };
