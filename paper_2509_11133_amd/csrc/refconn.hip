@@ -175,6 +175,15 @@ struct RCArgs {
   int8_t* sig2;
   int32_t* f2t2;
   int32_t* nbr2;
+  // the level's check, done by pass 2's first workgroup (the flag and the totals are final
+  // before pass 2 starts): chk_flag = input ids out of range, chk_etot / chk_all = the edge
+  // total and edges + faces; a code is ORed into *status, and chk_out (when not null) gets
+  // {edges, faces, flag} for the synchronous check
+  const uint32_t* chk_etot;
+  const uint32_t* chk_all;
+  const uint32_t* chk_flag;
+  int32_t* status;
+  int64_t* chk_out;
 };
 
 __global__ __launch_bounds__(RCT) void k_rc_prep(int64_t nE, int64_t nEd, const int32_t* __restrict__ tet,
@@ -536,7 +545,23 @@ struct RCRange {  // one row range's first-seen edges and faces: [e0, e0 + ne), 
   int ne, nf;
 };
 
+// input ids out of range (flag) and refined totals against the recurrences (one thread)
+__device__ __forceinline__ void rc_check_level(const RCArgs& A) {
+  const int64_t ne = *A.chk_etot, nf = (int64_t)*A.chk_all - ne;
+  const uint32_t flag = *A.chk_flag;
+  int32_t code = 0;
+  if (flag) code |= 1;
+  if (ne != A.nEd2 || nf != A.nF2) code |= 2;
+  if (code && A.status) atomicOr(A.status, code);
+  if (A.chk_out) {
+    A.chk_out[0] = ne;
+    A.chk_out[1] = nf;
+    A.chk_out[2] = flag;
+  }
+}
+
 __global__ __launch_bounds__(RCB) __attribute__((amdgpu_waves_per_eu(6))) void k_rc_pass2(RCArgs A) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) rc_check_level(A);
   __shared__ int32_t sW[RCL];
   __shared__ RCRange sR[2];
   __shared__ int sh[NQ2 * RCW];
@@ -734,24 +759,6 @@ __global__ __launch_bounds__(RCT) void k_rc_init(int64_t nEd, int32_t* __restric
   for (int64_t i = (int64_t)blockIdx.x * RCT + threadIdx.x; i < nz; i += stride) z[i] = 0;
 }
 
-// input ids out of range (flag) and refined totals against the recurrences: ORs a code into
-// *status (device), and writes out[3] = {edges, faces, flag} when out != null.  etot = the
-// edge total, all = edges + faces.
-__global__ void k_rc_check(const uint32_t* __restrict__ etot, const uint32_t* __restrict__ all,
-                           const uint32_t* __restrict__ flag, int64_t nEd2, int64_t nF2, int32_t* __restrict__ status,
-                           int64_t* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int64_t ne = *etot, nf = (int64_t)*all - ne;
-  int32_t code = 0;
-  if (*flag) code |= 1;
-  if (ne != nEd2 || nf != nF2) code |= 2;
-  if (code && status) atomicOr(status, code);
-  if (out) {
-    out[0] = ne;
-    out[1] = nf;
-    out[2] = *flag;
-  }
-}
 
 struct RCWS {
   int32_t *minI, *efp;
@@ -865,6 +872,11 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   A.sig2 = sigma_out;
   A.f2t2 = face2tet_out;
   A.nbr2 = nbr_out;
+  A.chk_etot = w.tpre + 2 * w.ntiles;
+  A.chk_all = w.tpre + 4 * w.ntiles;
+  A.chk_flag = w.z + 2;
+  A.status = status;
+  A.chk_out = status ? nullptr : w.chk;
   // pass 1 reads the coarse AoS data once (cache-shared by the 12 rows of a tet) and writes
   // one record word per refined row and count
   PH_LAUNCH_B("refconn_pass1", 80.0 * nE + 12.0 * nEd + 8.0 * nE2, k_rc_pass1, (unsigned)w.ntiles, RCB, 0, s, A);
@@ -875,9 +887,6 @@ extern "C" int phfem_refine_connected(int64_t nC, const double* coord, int64_t n
   PH_LAUNCH_B("refconn_pass2", 80.0 * nE + 12.0 * nEd + 8.0 * nE2 + (24.0 + 4 + 16 + 1 * 4 + 16) * nE2 + 12.0 * nEd2 +
                                    20.0 * nF2,
               k_rc_pass2, (unsigned)w.ntiles, RCB, 0, s, A);
-  PH_LAUNCH("rc_check", k_rc_check, 1, 64, 0, s, (const uint32_t*)w.tpre + 2 * w.ntiles,
-            (const uint32_t*)w.tpre + 4 * w.ntiles, w.z + 2, nEd2, nF2, status,
-            status ? nullptr : w.chk);
   if (!status) {  // synchronous check
     int64_t chk[3] = {0, 0, 0};
     PH_HIP(hipMemcpyAsync(chk, w.chk, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
