@@ -577,7 +577,7 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
                                                   const uint16_t* __restrict__ cinfo, int32_t* __restrict__ rowptr,
                                                   int32_t* __restrict__ col, double* __restrict__ val,
                                                   double* __restrict__ diag, double* __restrict__ rhs) {
-  constexpr int NPF = sizeof(R) == 4 ? 2 : 1;
+  constexpr int NPF = 2;  // (4 waves per SIMD in FP32, 3 in FP64 either way)
   __shared__ R lS[10][CT];
   __shared__ R lr[4][CT];
   __shared__ int32_t lF[4][CT];
