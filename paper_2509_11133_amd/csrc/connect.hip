@@ -749,13 +749,32 @@ __global__ __launch_bounds__(BK_T) void k_bk_heads(int64_t nE, const int32_t* __
 }
 
 // id of the first appearance at position h = N th + oh: prefix of th + heads of th before oh
+// (tet th's N head records read as vectors: 3 x 8 bytes for edges, 16 bytes for faces)
 template <int N>
 __device__ __forceinline__ int32_t bk_head_id(int32_t h, const int32_t* __restrict__ hp,
                                               const uint32_t* __restrict__ pre) {
+  static_assert(N == 4 || N == 6, "edges or faces");
   const int64_t th = h / N;
   const int oh = (int)(h - N * th);
   uint32_t id = pre[th];
-  for (int i = 0; i < oh; ++i) id += hp[N * th + i] == (int32_t)(N * th + i) ? 1u : 0u;
+  int w[N];
+  if constexpr (N == 4) {
+    const int4 x = reinterpret_cast<const int4*>(hp)[th];
+    w[0] = x.x;
+    w[1] = x.y;
+    w[2] = x.z;
+    w[3] = x.w;
+  } else {
+    const int2* p = reinterpret_cast<const int2*>(hp + 6 * th);  // 24 th bytes: 8-byte aligned
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int2 x = p[i];
+      w[2 * i] = x.x;
+      w[2 * i + 1] = x.y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N - 1; ++i) id += (i < oh && w[i] == (int32_t)(N * th + i)) ? 1u : 0u;
   return (int32_t)id;
 }
 
