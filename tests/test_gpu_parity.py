@@ -433,6 +433,34 @@ def test_refine_connected_input_check():
     assert int(st.item()) == 0
 
 
+def test_refine_connected_count_check():
+    """Input ids all in range but not a consistent numbering: an interior face whose second tet
+    claims no neighbour there, so that both tets take the face's children and the refined totals
+    exceed the recurrences 2nEd+3nF+6nE, 4nF+16nE.  EINVAL when synchronous, status bit 2 (and
+    only it) when checked on the device; the untouched input still passes."""
+    from paper_2509_11133_amd import _binding as B
+    X, T, _, _ = levels(M.kuhn_cube, 1)
+    Xd, Td = dev(X), dev(T)
+    conn = P.connect(Td, X.shape[1], faces=True)
+    f2t = host(conn["face2tet"])
+    f = int(np.nonzero(f2t[1] >= 0)[0][3])  # an interior face
+    q1 = int(f2t[1, f])
+    nb = conn["nbr"].clone()
+    nb[q1 & 3, q1 >> 2] = -1  # its second tet (the higher index) loses its neighbour there
+    bad = dict(conn)
+    bad["nbr"] = nb
+    print("face", f, "second slot", q1, flush=True)
+    with pytest.raises(B.PhfemError) as e:
+        P.refine_connected(Xd, Td, bad)
+    assert e.value.code == B.EINVAL and "first-appearance" in str(e.value)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    P.refine_connected(Xd, Td, bad, st)
+    assert int(st.item()) == 2
+    st.zero_()
+    P.refine_connected(Xd, Td, conn, st)
+    assert int(st.item()) == 0
+
+
 @pytest.mark.parametrize("make,L", [(M.kuhn_cube, 1), (M.kuhn_cube, 4), (M.fichera, 3), (single_tet, 3)])
 def test_refine_connected_levels_equals_chained(make, L):
     """One multi-level call = L chained single-level calls, bit for bit."""
