@@ -452,6 +452,7 @@ __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __
   __shared__ int32_t lcnt;
   __shared__ uint32_t lw[CT / 64];
   const int64_t T0 = (int64_t)blockIdx.x * CX;
+  __builtin_amdgcn_s_setprio(2);  // raised while loads are issued (as in the tile pass)
   if (threadIdx.x == 0) lcnt = 0;
   __syncthreads();
   int nbv[CXK][4], sgv[CXK][4];
@@ -498,7 +499,9 @@ __global__ __launch_bounds__(CT) void k_cond_cross(int64_t nC, const double4* __
     const int64_t tb = base + (w >> 14);
     int sig[4], F[4];
     double x[4][3];
+    __builtin_amdgcn_s_setprio(2);
     elem_inputs(nC, XA, nE, t, tet, t2f, sigma, sig, F, x);
+    __builtin_amdgcn_s_setprio(0);
     for (int j = 0; j < nk; ++j) {  // field j of the group: kappa + j nE, records at recs + j rs
       opaque_coords(x);
       R su[10], r[4];
@@ -587,6 +590,9 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
   const int64_t T0 = (int64_t)blockIdx.x * CT;
   const int nb = nE - T0 < CT ? (int)(nE - T0) : CT;
   const int o = threadIdx.x;
+  // a raised wave priority while the tile's loads are issued, back to normal for the element
+  // arithmetic, so that other waves' loads start ahead of it
+  __builtin_amdgcn_s_setprio(2);
   if (o == 0) {
     lrange[0] = INT_MAX;
     lrange[1] = -1;
@@ -643,6 +649,7 @@ __global__ __launch_bounds__(CT) void k_cond_tile(int64_t nC, const double4* __r
 #pragma unroll
   for (int c = 0; c < NPF; ++c)
     if (cross_slot(pq1[c])) prec[c] = recs[rec_index(pq1[c] >> 2, pq1[c] & 3, cinfo[pq1[c] >> 2])];
+  __builtin_amdgcn_s_setprio(0);
   if (o < nb) {
     R su[10], r[4];
     elem_block<R>(x, sig, F, kap, P, nF, su, r);
